@@ -1,0 +1,52 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake (a dropped factor, a wrong sign or index, a
+transposed operand) in a copy of the oracle's C source, builds it on the CPU
+and runs the pin suite against it in a subprocess: the suite has to fail.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "bd3mg_oracle.c")
+
+MUTATIONS = {
+    "box-gradient-factor": ("acc += 2.0 * p->eta * (x[v]", "acc += 1.0 * p->eta * (x[v]"),
+    "box-curvature-factor": ("return quad + 2.0 * p->eta * box", "return quad + 1.0 * p->eta * box"),
+    "tv-adjoint-sign": ("if (i >= 1) tv += omega_at(p, x, k, j, i - 1)",
+                        "if (i >= 1) tv -= omega_at(p, x, k, j, i - 1)"),
+    "tv-adjoint-weight-index": ("if (j >= 1) tv += omega_at(p, x, k, j - 1, i) * dY(p, x, k, j - 1, i);",
+                                "if (j >= 1) tv += omega_at(p, x, k, j, i) * dY(p, x, k, j - 1, i);"),
+    "tv-curvature-drops-y": ("s += w * (dX(p, u, k, j, i) * dX(p, v, k, j, i) + dY(p, u, k, j, i) * dY(p, v, k, j, i));",
+                             "s += w * (dX(p, u, k, j, i) * dX(p, v, k, j, i));"),
+    "omega-delta-not-squared": ("return 1.0 / sqrt(gxv * gxv + gyv * gyv + p->delta * p->delta);",
+                                "return 1.0 / sqrt(gxv * gxv + gyv * gyv + p->delta);"),
+    "blur-transposed": ("int sg = transpose ? 1 : -1;", "int sg = transpose ? -1 : 1;"),
+    "adjoint-z-weight-of-output-slice": ("acc += p->gz[(size_t)m * p->kz + (c + rz)]",
+                                         "acc += p->gz[(size_t)k * p->kz + (c + rz)]"),
+    "step-sign": ("double u2 = -(P[1] * c1 + P[2] * c2);", "double u2 = (P[1] * c1 + P[2] * c2);"),
+    "pinv-offdiagonal-sign": ("P[1] = -b12 / det;", "P[1] = b12 / det;"),
+    "coloring-gap-off-by-one": ("if (gap < min_gap) { ok = 0; break; }",
+                                "if (gap < min_gap - 1) { ok = 0; break; }"),
+    "z-penalty-factor": ("acc += 2.0 * p->kappa * zz;", "acc += p->kappa * zz;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    mut = tmp_path / "mut.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libmut.so"
+    subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                    "-o", str(lib), str(mut), "-lm"], check=True)
+    env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert res.returncode != 0, "pins did not catch mutation %s\n%s" % (name, res.stdout[-2000:])
