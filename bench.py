@@ -1,0 +1,161 @@
+"""Benchmark of the BD3MG hot path on one MI355X.
+
+A step is one BD3MG sweep (every block of the partition updated once: gradient,
+direction, 2x2 solve and update passes for each colour of blocks) over the
+256x256x64 FP32 workload (FP64 inner products, 2x2 solve and f): 200-ellipsoid
+phantom, depth-variant Gaussian PSF 7x7x7 (sigma_xy 0.5 -> 3.0, sigma_z 1 -> 2),
+noise 0.02, lambda = 0.01, delta = 0.02, eta = 0.01, 16 uneven blocks of 2..6
+slices.  Inputs are synthetic and seeded; the observation y = H xbar + noise
+is formed with the library's own H on the GPU.
+
+Prints one JSON line: voxel-iterations/s over exactly --steps sweeps (after
+--warmup untimed sweeps), the roofline figure of the dominant kernel (HIP
+events on the library's stream, algorithmic bytes from the library), the
+time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y, and the FP64 CPU oracle
+timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iterations/s + time-to-f-tolerance (plain vs warm-started), % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def make_problem(binding, w):
+    nz, ny, nx = w.shape
+    g = binding.Problem(nx, ny, nz, binding.FP64 if w.fp64 else binding.FP32)
+    g.set_psf_gaussian(w.kxy, w.kz, w.sigma_xy, w.sigma_z)
+    g.set_params(w.lam, w.delta, w.eta, w.kappa)
+    y = g.H(w.xbar) + w.noise.astype(g.dtype)  # degradation model y = H xbar + b
+    g.set_data(y.astype(g.dtype))
+    g.set_blocks(w.nslices)
+    return g
+
+
+def cpu_baseline(w, budget_s):
+    """FP64 oracle on the same workload: as many whole sweeps as fit the budget."""
+    import oracle
+    gxy = oracle.gauss_table(w.sigma_xy, w.kxy)
+    gz = oracle.gauss_table(w.sigma_z, w.kz)
+    y = oracle.Problem(np.zeros(w.shape), gxy, gxy, gz).H(w.xbar) + w.noise
+    o = oracle.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
+    nc, order, _ = oracle.color_schedule(w.nslices, 2 * (w.kz // 2))
+    x = y.copy()
+    d = np.zeros(w.shape)
+    t0 = time.perf_counter()
+    o.run(x, d, w.nslices, order, 1, history=False)
+    t1 = time.perf_counter()
+    per = t1 - t0
+    more = max(0, int(budget_s / per) - 1)
+    if more:
+        o.run(x, d, w.nslices, order, more, history=False)
+    t2 = time.perf_counter()
+    sweeps = 1 + more
+    nvox = int(np.prod(w.shape))
+    return {"value": nvox * sweeps / (t2 - t0), "unit": "voxel-iterations/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d sweeps of the %s workload from x0 = y (FP64, coloured order)"
+                      % (sweeps, w.name),
+            "seconds": t2 - t0}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="plain-fp32-256x256x64")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-sweeps-to-tol", type=int, default=20000)
+    ap.add_argument("--no-tol", action="store_true", help="skip the time-to-tolerance run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only (one GPU's share of the volume); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2002_02328_amd import binding, inputs
+    w = inputs.WORKLOADS[args.workload]()
+    nvox = int(np.prod(w.shape))
+    g = make_problem(binding, w)
+    nc, order, color = g.get_schedule()
+
+    # timed sweeps
+    g.set_x0(None)
+    g.run(args.warmup, check_every=0)
+    t0 = time.perf_counter()
+    g.run(args.steps, check_every=0)  # returns after the device has finished
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    value = nvox * args.steps / secs
+
+    # per-kernel device time over the same number of sweeps, events on the library's stream
+    g.set_option(binding.OPT_PROFILE, 1)
+    g.run(args.steps, check_every=0)
+    prof = g.get_profile(reset=True)
+    g.set_option(binding.OPT_PROFILE, 0)
+    hot = {k: v for k, v in prof.items() if k != "eval" and v[0] > 0}
+    dom = max(hot, key=lambda k: hot[k][1])
+    n, ms, by = hot[dom]
+    achieved = by / (ms * 1e-3) / 1e9
+    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                   "GB/s": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
+               for k, v in prof.items() if v[0] > 0}
+    total_ms = sum(v[1] for v in hot.values())
+    all_bytes = sum(v[2] for v in hot.values())
+
+    probe_gbs, _ = binding.probe_copy(4 << 30, 5)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * secs / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w.fp64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "shape_zyx": list(w.shape), "psf": "%dx%dx%d" % (w.kxy, w.kxy, w.kz),
+                   "blocks": int(len(w.nslices)), "colors": int(nc),
+                   "reductions": "f64", "step": "one sweep (every block updated once)"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n},
+        "kernels": kernels,
+        "sweep_algorithmic_GBps": all_bytes / (total_ms * 1e-3) / 1e9,
+        "copy_probe_GBps": probe_gbs,
+    }
+
+    if not args.no_tol:
+        g.set_x0(None)
+        t0 = time.perf_counter()
+        res = g.run(args.max_sweeps_to_tol, grad_rtol=args.tol, check_every=1)
+        t1 = time.perf_counter()
+        out["time_to_tol"] = {"plain_x0_y": {"seconds": t1 - t0, "sweeps": res["sweeps"],
+                                             "converged": bool(res["converged"]),
+                                             "grad_rel": res["grad_norm"] / res["grad_norm_ref"],
+                                             "f": res["f"], "tol": args.tol},
+                              "warm_started": None}
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,219 @@
+/*
+ * bd3mg.h -- C interface of libbd3mg, the MI355X (gfx950) implementation of
+ * the block distributed 3MG method (BD3MG) for restoring a 3D volume blurred
+ * by a depth-variant PSF (Chalvidal & Chouzenoux, arXiv 2002.02328).
+ *
+ * Problem (Sec. 2, eq. "P"; Sec. 3.1, eqs. "model" and "eq_crit"):
+ *   minimise over x in R^N, N = nx*ny*nz,
+ *     f(x) = 1/2 ||H x - y||^2 + eta * d^2(x, [xmin, xmax]^N)
+ *          + lambda * sum_n sqrt((V^X x)_n^2 + (V^Y x)_n^2 + delta^2)
+ *          + kappa * ||V^Z x||^2
+ *   where H is a depth-variant 3D blur and V^X, V^Y, V^Z are forward
+ *   differences (last difference 0).  The variables are split into blocks of
+ *   whole z-slices (Sec. 3.1), and each block update is one memory-gradient
+ *   majorize-minimize step (Sec. 2.3, boxes "Master" and "Worker").
+ *
+ * Conventions
+ *   - Volumes are [nz][ny][nx], x fastest, dense, no padding.
+ *   - Element type of every volume crossing this interface is the problem's
+ *     storage type: double for BD3MG_FP64, float for BD3MG_FP32.  Scalars
+ *     (f, norms, PSF tables, parameters) are always double.
+ *   - PSF: separable per output slice k,
+ *       (H x)_{k,j,i} = sum_{c,b,a} gz_k[c] gy_k[b] gx_k[a] x_{k-c, j-b, i-a},
+ *     zero padding; table rows are indexed [k][a + r], a in [-r, r].
+ *   - "on_device" pointers are device memory of the calling process on the
+ *     current HIP device; the library reads/writes them in order on its own
+ *     stream and synchronises before returning.  Host pointers may be
+ *     pageable.
+ *   - Ownership: every input is copied before the call returns; the library
+ *     keeps no caller pointer.  A problem handle owns all of its device
+ *     memory and releases it in bd3mg_destroy.
+ *   - Errors: every call returns a status; nothing aborts or throws across
+ *     this interface.  bd3mg_last_error() returns a thread-local description
+ *     of the last failure in the calling thread.
+ *   - Calls on one handle must not overlap (no internal locking).
+ */
+#ifndef BD3MG_H
+#define BD3MG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bd3mg_problem_s *bd3mg_problem;
+
+typedef enum {
+    BD3MG_OK = 0,
+    BD3MG_ERR_ARG = 1,           /* invalid argument (sizes, parameters, tables) */
+    BD3MG_ERR_STATE = 2,         /* call made before the state it needs was set */
+    BD3MG_ERR_NOMEM = 3,         /* device or host allocation failed */
+    BD3MG_ERR_HIP = 4,           /* a HIP runtime call failed */
+    BD3MG_ERR_NOT_CONVERGED = 5  /* run stopped at max_sweeps above the tolerance; x is valid */
+} bd3mg_status;
+
+typedef enum {
+    BD3MG_FP64 = 0,  /* storage, stencils, reductions and solve in double */
+    BD3MG_FP32 = 1   /* storage and stencils in float; inner products, the 2x2
+                        majorant system, its solve and f in double */
+} bd3mg_precision;
+
+typedef enum {
+    /* Blocks at least max(2*r_z, kappa > 0) slices apart share a colour and are
+     * updated together; colours run in order.  Same-colour blocks read and
+     * write disjoint data, so this equals the sequential (delay-free) rule of
+     * Sec. 3.1 applied in colour-major order (Sec. 2.4, delta_k = 0). */
+    BD3MG_SCHED_COLORED = 0,
+    /* One block at a time in z order (the natural sequential rule). */
+    BD3MG_SCHED_SEQUENTIAL = 1
+} bd3mg_schedule;
+
+typedef enum { BD3MG_OP_H = 0, BD3MG_OP_HT = 1, BD3MG_OP_GRAD = 2 } bd3mg_op;
+
+typedef struct {
+    int sweeps;           /* sweeps done by this call (a sweep updates every block once) */
+    int converged;        /* 1 if ||grad f|| <= grad_rtol * grad_norm_ref was reached */
+    double f;             /* f at the returned x (from the maintained residual) */
+    double grad_norm;     /* ||grad f(x)|| at the last check */
+    double grad_norm_ref; /* ||grad f(y)||, the normaliser of the stop rule */
+    double seconds;       /* device time of the call, from HIP events */
+} bd3mg_result;
+
+/* Library version, (major << 16) | minor. */
+int bd3mg_version(void);
+
+/* Thread-local text of the last failure ("" if none). */
+const char *bd3mg_last_error(void);
+
+/* PSF factor tables of a depth-variant Gaussian (Sec. 3.1: per-depth blur
+ * widths).  table[z][a + r] = exp(-a^2 / (2 sigma[z]^2)) normalised to sum 1
+ * over a in [-r, r], r = (k - 1) / 2.  Host arrays: sigma[nz], table[nz*k].
+ * ERR_ARG: nz < 1, k < 1 or even, sigma <= 0 or not finite. */
+bd3mg_status bd3mg_psf_gaussian(int nz, int k, const double *sigma, double *table);
+
+/* Create a problem of nx*ny*nz voxels in the given precision (bd3mg_precision)
+ * on the current HIP device.  ERR_ARG: a dimension < 1 or precision unknown. */
+bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *out);
+
+/* Release the handle and all its device memory.  NULL is accepted. */
+bd3mg_status bd3mg_destroy(bd3mg_problem p);
+
+/* Separable depth-variant PSF (Sec. 3.1).  Host tables gx[nz*kx], gy[nz*ky],
+ * gz[nz*kz].  ERR_ARG: even or < 1 sizes, kx or ky > 9, kz > 9, or a
+ * non-finite entry.  Marks the residual stale. */
+bd3mg_status bd3mg_set_psf_separable(bd3mg_problem p, int kx, int ky, int kz,
+                                     const double *gx, const double *gy, const double *gz);
+
+/* Depth-variant Gaussian PSF built with bd3mg_psf_gaussian: kxy x kxy in-slice
+ * with widths sigma_xy[nz], kz along z with widths sigma_z[nz]. */
+bd3mg_status bd3mg_set_psf_gaussian(bd3mg_problem p, int kxy, int kz,
+                                    const double *sigma_xy, const double *sigma_z);
+
+/* Parameters of f (Sec. 3.1, eq. "eq_crit").  ERR_ARG: delta <= 0, lambda,
+ * eta or kappa < 0, xmin > xmax, or a non-finite value.  Defaults before the
+ * first call: lambda = eta = kappa = 0, delta = 1, [xmin, xmax] = [0, 1]. */
+bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, double eta,
+                              double kappa, double xmin, double xmax);
+
+/* Observation y (eq. "model"), nz*ny*nx elements of the storage type. */
+bd3mg_status bd3mg_set_data(bd3mg_problem p, const void *y, int on_device);
+
+/* Block partition along z: nblocks blocks of nslices[b] consecutive slices,
+ * in z order (Sec. 3.1; the sets are pairwise disjoint, Sec. 2.3 eq. "disj").
+ * schedule is a bd3mg_schedule.  ERR_ARG: nblocks < 1, a count < 1, or the
+ * counts not summing to nz.  Resets every block's previous step to 0. */
+bd3mg_status bd3mg_set_blocks(bd3mg_problem p, int nblocks, const int *nslices, int schedule);
+
+/* The sweep order in use: *ncolors, order[nblocks] (block indices in update
+ * order) and color[nblocks].  Arrays may be NULL.  ERR_STATE before set_blocks
+ * (needs the PSF too, as the colouring depends on r_z). */
+bd3mg_status bd3mg_get_schedule(bd3mg_problem p, int *ncolors, int *order, int *color);
+
+/* Initial point x^0 (box "Master", initialisation).  x0 == NULL means x^0 = y.
+ * Resets every block's previous step to 0. */
+bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device);
+
+/* Run BD3MG sweeps from the current state (x, each block's previous step and
+ * the maintained residual r = H x - y), so calls can be chained: run(a) then
+ * run(b) gives bitwise the same state as run(a + b).  Stops after max_sweeps
+ * sweeps, or, when grad_rtol > 0, at the first check with ||grad f(x)|| <=
+ * grad_rtol * ||grad f(y)||; a check happens every check_every sweeps and
+ * after the last sweep.  With grad_rtol <= 0 and check_every == 0 nothing is
+ * evaluated (res->f and res->grad_norm are NaN) and the call only enqueues
+ * the sweeps and waits for them.  res may be NULL.  ERR_ARG: max_sweeps < 0
+ * or check_every < 0.  ERR_STATE: PSF, data or blocks not set.
+ * ERR_NOT_CONVERGED: grad_rtol > 0 and not reached (state still valid). */
+bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,
+                       bd3mg_result *res);
+
+/* Copy the current iterate out (storage type). */
+bd3mg_status bd3mg_get_x(bd3mg_problem p, void *x, int on_device);
+
+/* Copy the previous-step volume (each block's last step on its own slices). */
+bd3mg_status bd3mg_get_dprev(bd3mg_problem p, void *d, int on_device);
+
+/* Checkpoint: copy out the whole solver state -- iterate x, previous steps
+ * dprev, maintained residual r (volumes of the storage type; r may be NULL)
+ * and the number of sweeps done since x^0 (may be NULL). */
+bd3mg_status bd3mg_get_state(bd3mg_problem p, void *x, void *dprev, void *r, long long *sweeps,
+                             int on_device);
+
+/* Resume: restore a state saved with bd3mg_get_state.  With r == NULL the
+ * residual is recomputed from x (equal up to rounding, not bitwise). */
+bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, const void *r,
+                             long long sweeps, int on_device);
+
+/* f(x) and ||grad f(x)|| at the current iterate, recomputing the residual
+ * H x - y from x first.  Either pointer may be NULL. */
+bd3mg_status bd3mg_eval(bd3mg_problem p, double *f, double *grad_norm);
+
+/* Apply one operator of the criterion to a volume: BD3MG_OP_H (H in),
+ * BD3MG_OP_HT (H^T in), BD3MG_OP_GRAD (grad f at in; needs the data).  Uses
+ * the kernels of the solver.  in and out must not overlap. */
+bd3mg_status bd3mg_apply(bd3mg_problem p, int op, const void *in, void *out, int on_device);
+
+/* One block update (worker step and master update, Sec. 2.3) of block b
+ * alone, from the current state; info (may be NULL) receives
+ * {B11, B12, B22, c1, c2, u1, u2, ||g_S||^2} of the 2x2 subspace system. */
+bd3mg_status bd3mg_block_step(bd3mg_problem p, int block, double *info);
+
+/* Tunables (bd3mg_option).  BD3MG_OPT_REFRESH_EVERY: recompute the residual
+ * r = H x - y from x after every that many sweeps (counted from x^0; 0 =
+ * never; default 0 for FP64, 64 for FP32), bounding the drift of the
+ * incrementally updated r.  BD3MG_OPT_PROFILE: 1 records HIP events around
+ * every kernel launch of bd3mg_run on the problem's stream (0 = off). */
+typedef enum { BD3MG_OPT_REFRESH_EVERY = 0, BD3MG_OPT_PROFILE = 1 } bd3mg_option;
+bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
+
+/* Kernel kinds reported by bd3mg_get_profile. */
+typedef enum {
+    BD3MG_K_GRAD = 0,    /* gradient pass of a colour of blocks */
+    BD3MG_K_DIRS = 1,    /* direction pass (H d1, H d2, inner products) */
+    BD3MG_K_SOLVE = 2,   /* per-block 2x2 solve */
+    BD3MG_K_UPDATE = 3,  /* update pass (x, dprev, r) */
+    BD3MG_K_EVAL = 4,    /* whole-volume residual refresh and f / ||grad f|| checks */
+    BD3MG_K_COUNT = 5
+} bd3mg_kernel_kind;
+
+/* Profile of the bd3mg_run calls made since profiling was switched on (or
+ * since the last reset == 1): per kernel kind, the number of launches, their
+ * summed device time in milliseconds (HIP events on the problem's stream) and
+ * the summed algorithmic bytes -- the bytes each launch must move to or from
+ * device memory by the method's definition, counting every element it reads
+ * or writes once.  Arrays of BD3MG_K_COUNT entries; any may be NULL. */
+bd3mg_status bd3mg_get_profile(bd3mg_problem p, long long *launches, double *ms, double *bytes,
+                               int reset);
+
+/* Attainable device-memory bandwidth: copies a buffer of the given size
+ * (rounded down to 16 B) with a plain streaming copy kernel, iters times on
+ * the current device, and reports the best launch as read + write bytes per
+ * second (*gbps, GB/s) and its duration (*ms).  Allocates and frees its two
+ * buffers.  ERR_ARG: bytes < 1 MiB or iters < 1. */
+bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BD3MG_H */
