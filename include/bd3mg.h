@@ -74,7 +74,7 @@ typedef enum { BD3MG_OP_H = 0, BD3MG_OP_HT = 1, BD3MG_OP_GRAD = 2 } bd3mg_op;
 typedef struct {
     int sweeps;           /* sweeps done by this call (a sweep updates every block once) */
     int converged;        /* 1 if ||grad f|| <= grad_rtol * grad_norm_ref was reached */
-    double f;             /* f at the returned x (from the maintained residual) */
+    double f;             /* f at the returned x (NaN when nothing was evaluated) */
     double grad_norm;     /* ||grad f(x)|| at the last check */
     double grad_norm_ref; /* ||grad f(y)||, the normaliser of the stop rule */
     double seconds;       /* device time of the call, from HIP events */
@@ -135,8 +135,10 @@ bd3mg_status bd3mg_get_schedule(bd3mg_problem p, int *ncolors, int *order, int *
 bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device);
 
 /* Run BD3MG sweeps from the current state (x, each block's previous step and
- * the maintained residual r = H x - y), so calls can be chained: run(a) then
- * run(b) gives bitwise the same state as run(a + b).  Stops after max_sweeps
+ * the maintained blurred residual q, q_m = XY^T_m (H x - y)_m: the residual of
+ * slice m blurred by the adjoint of slice m's in-slice factors, from which
+ * H^T (H x - y) is a z-stencil), so calls can be chained: run(a) then run(b)
+ * gives bitwise the same state as run(a + b).  Stops after max_sweeps
  * sweeps, or, when grad_rtol > 0, at the first check with ||grad f(x)|| <=
  * grad_rtol * ||grad f(y)||; a check happens every check_every sweeps and
  * after the last sweep.  With grad_rtol <= 0 and check_every == 0 nothing is
@@ -154,18 +156,19 @@ bd3mg_status bd3mg_get_x(bd3mg_problem p, void *x, int on_device);
 bd3mg_status bd3mg_get_dprev(bd3mg_problem p, void *d, int on_device);
 
 /* Checkpoint: copy out the whole solver state -- iterate x, previous steps
- * dprev, maintained residual r (volumes of the storage type; r may be NULL)
- * and the number of sweeps done since x^0 (may be NULL). */
-bd3mg_status bd3mg_get_state(bd3mg_problem p, void *x, void *dprev, void *r, long long *sweeps,
+ * dprev, maintained blurred residual q (see bd3mg_run; volumes of the storage
+ * type, any may be NULL) and the number of sweeps done since x^0 (may be
+ * NULL). */
+bd3mg_status bd3mg_get_state(bd3mg_problem p, void *x, void *dprev, void *q, long long *sweeps,
                              int on_device);
 
-/* Resume: restore a state saved with bd3mg_get_state.  With r == NULL the
- * residual is recomputed from x (equal up to rounding, not bitwise). */
-bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, const void *r,
+/* Resume: restore a state saved with bd3mg_get_state.  With q == NULL the
+ * blurred residual is recomputed from x (equal up to rounding, not bitwise). */
+bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, const void *q,
                              long long sweeps, int on_device);
 
-/* f(x) and ||grad f(x)|| at the current iterate, recomputing the residual
- * H x - y from x first.  Either pointer may be NULL. */
+/* f(x) and ||grad f(x)|| at the current iterate, recomputing the blurred
+ * residual q from x first.  Either pointer may be NULL. */
 bd3mg_status bd3mg_eval(bd3mg_problem p, double *f, double *grad_norm);
 
 /* Apply one operator of the criterion to a volume: BD3MG_OP_H (H in),
@@ -178,10 +181,10 @@ bd3mg_status bd3mg_apply(bd3mg_problem p, int op, const void *in, void *out, int
  * {B11, B12, B22, c1, c2, u1, u2, ||g_S||^2} of the 2x2 subspace system. */
 bd3mg_status bd3mg_block_step(bd3mg_problem p, int block, double *info);
 
-/* Tunables (bd3mg_option).  BD3MG_OPT_REFRESH_EVERY: recompute the residual
- * r = H x - y from x after every that many sweeps (counted from x^0; 0 =
+/* Tunables (bd3mg_option).  BD3MG_OPT_REFRESH_EVERY: recompute the blurred
+ * residual q from x after every that many sweeps (counted from x^0; 0 =
  * never; default 0 for FP64, 64 for FP32), bounding the drift of the
- * incrementally updated r.  BD3MG_OPT_PROFILE: 1 records HIP events around
+ * incrementally updated q.  BD3MG_OPT_PROFILE: 1 records HIP events around
  * every kernel launch of bd3mg_run on the problem's stream (0 = off). */
 typedef enum { BD3MG_OPT_REFRESH_EVERY = 0, BD3MG_OPT_PROFILE = 1 } bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
@@ -192,7 +195,7 @@ typedef enum {
     BD3MG_K_DIRS = 1,    /* direction pass (H d1, H d2, inner products) */
     BD3MG_K_SOLVE = 2,   /* per-block 2x2 solve */
     BD3MG_K_UPDATE = 3,  /* update pass (x, dprev, r) */
-    BD3MG_K_EVAL = 4,    /* whole-volume residual refresh and f / ||grad f|| checks */
+    BD3MG_K_EVAL = 4,    /* whole-volume refresh of q and ||grad f|| checks */
     BD3MG_K_COUNT = 5
 } bd3mg_kernel_kind;
 

@@ -50,9 +50,6 @@ bd3mg_status fail(bd3mg_status st, const char *fmt, ...)
         if (s_ != BD3MG_OK) return s_;                 \
     } while (0)
 
-// Whole-volume passes split the slices into chunks of this many slices.
-constexpr int CHUNK = 8;
-
 }  // namespace
 
 struct bd3mg_problem_s {
@@ -61,6 +58,7 @@ struct bd3mg_problem_s {
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Geom geom{};
+    int ntiles = 0;
     Params prm{0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
 
     // PSF
@@ -68,33 +66,38 @@ struct bd3mg_problem_s {
     int kx = 0, ky = 0, kz = 0;
     void *d_gx = nullptr, *d_gy = nullptr, *d_gz = nullptr;
 
-    // volumes (storage type)
-    void *x = nullptr, *y = nullptr, *r = nullptr, *g = nullptr, *dpb[2] = {nullptr, nullptr};
+    // volumes (storage type); q is the in-slice adjoint-blurred residual
+    void *x = nullptr, *y = nullptr, *q = nullptr, *g = nullptr, *dpb[2] = {nullptr, nullptr};
     void *tmp[3] = {nullptr, nullptr, nullptr};
     int cur = 0;  // dpb[cur] holds every block's last step
-    bool data_set = false, x_set = false, r_stale = true;
+    bool data_set = false, x_set = false, q_stale = true;
 
-    // blocks and schedule
+    // blocks, schedule and the work-item lists of every launch group
     bool blocks_set = false, sched_dirty = true;
     int schedule = BD3MG_SCHED_COLORED;
     std::vector<int> nsl, z0, order, color;
     int ncolors = 0;
-    std::vector<int> col_off, col_cnt;  // segments of each colour in d_segs
-    Segment *d_segs = nullptr;
-    int nseg_alloc = 0;
-    Segment *d_chunks = nullptr;
-    int nchunks = 0;
+    struct Group {
+        int g_off, g_cnt, d_off, d_cnt, u_off, u_cnt, br_off, br_cnt;
+        double bytes[4];  // algorithmic bytes of the gradient, direction, solve and update passes
+    };
+    std::vector<Group> groups;  // ncolors colour groups, then one group per block
+    Item *d_items = nullptr;
+    size_t items_alloc = 0;
+    BlockRange *d_br = nullptr;
+    size_t br_alloc = 0;
+    Item *d_vol = nullptr;  // every slice of the volume, for whole-volume passes
 
     // reductions
-    double *d_partials = nullptr;
-    size_t partials_cap = 0;  // doubles
-    double *d_u = nullptr, *d_info = nullptr, *d_eval = nullptr;
+    double *d_pg = nullptr, *d_pd = nullptr, *d_pe = nullptr, *d_pr = nullptr;
+    size_t pg_cap = 0, pd_cap = 0;
+    double *d_u = nullptr, *d_info = nullptr, *d_sum = nullptr;
     int nblocks_alloc = 0;
 
     double gnorm_ref = 0.0;
     bool gnorm_ref_valid = false;
 
-    long long sweeps_done = 0;  // sweeps since x^0 (drives the residual refresh)
+    long long sweeps_done = 0;  // sweeps since x^0 (drives the refresh of q)
     long long refresh_every = 0;
 
     // profiling: event pairs of the launches not yet folded into the totals
@@ -109,7 +112,6 @@ struct bd3mg_problem_s {
     long long prof_launches[BD3MG_K_COUNT] = {0, 0, 0, 0, 0};
     double prof_ms[BD3MG_K_COUNT] = {0, 0, 0, 0, 0};
     double prof_bytes[BD3MG_K_COUNT] = {0, 0, 0, 0, 0};
-    std::vector<double> color_bytes;  // algorithmic bytes of each colour's passes, [ncolors][4]
 };
 
 namespace {
@@ -120,7 +122,7 @@ DevState<T> dev_state(bd3mg_problem p)
     DevState<T> s;
     s.x = (T *)p->x;
     s.y = (T *)p->y;
-    s.r = (T *)p->r;
+    s.q = (T *)p->q;
     s.g = (T *)p->g;
     s.dp[0] = (T *)p->dpb[p->cur];
     s.dp[1] = (T *)p->dpb[p->cur ^ 1];
@@ -185,47 +187,14 @@ bd3mg_status prof_collect(bd3mg_problem p)
     return BD3MG_OK;
 }
 
-// Algorithmic bytes of the passes of one colour (each element a pass must
-// read or write counted once): gradient pass reads r on S +- r_z and x, dp on
-// S, writes g on S; direction pass reads g, dp and x on S; solve reads the
-// partial sums; update pass reads g, dp, x on S and r on S +- r_z, writes x,
-// dp on S and r on S +- r_z.
-void color_bytes(bd3mg_problem p)
+bd3mg_status realloc_dev(void **ptr, size_t *cap, size_t bytes, const char *what)
 {
-    const int nb = (int)p->nsl.size();
-    const double A = (double)p->nx * p->ny * p->esz;
-    const int rz = p->kz / 2;
-    p->color_bytes.assign((size_t)p->ncolors * 4, 0.0);
-    std::vector<char> inhalo(p->nz);
-    for (int c = 0; c < p->ncolors; ++c) {
-        std::fill(inhalo.begin(), inhalo.end(), 0);
-        double sl = 0.0, nblk = 0.0;
-        for (int b = 0; b < nb; ++b) {
-            if (p->color[b] != c) continue;
-            sl += p->nsl[b];
-            nblk += 1.0;
-            for (int k = std::max(0, p->z0[b] - rz); k < std::min(p->nz, p->z0[b] + p->nsl[b] + rz); ++k)
-                inhalo[k] = 1;
-        }
-        double h = 0.0;
-        for (int k = 0; k < p->nz; ++k) h += inhalo[k];
-        double *cb = &p->color_bytes[(size_t)c * 4];
-        cb[0] = A * (h + 3.0 * sl);
-        cb[1] = A * 3.0 * sl;
-        cb[2] = nblk * p->geom.ntx * p->geom.nty * NQ * sizeof(double);
-        cb[3] = A * (5.0 * sl + 2.0 * h);
-    }
-}
-
-bd3mg_status ensure_partials(bd3mg_problem p, size_t doubles)
-{
-    if (doubles <= p->partials_cap) return BD3MG_OK;
-    if (p->d_partials) HIP_TRY(hipFree(p->d_partials));
-    p->d_partials = nullptr;
-    p->partials_cap = 0;
-    if (hipMalloc(&p->d_partials, doubles * sizeof(double)) != hipSuccess)
-        return fail(BD3MG_ERR_NOMEM, "partial-sum buffer of %zu doubles", doubles);
-    p->partials_cap = doubles;
+    if (bytes <= *cap && *ptr) return BD3MG_OK;
+    if (*ptr) HIP_TRY(hipFree(*ptr));
+    *ptr = nullptr;
+    *cap = 0;
+    if (hipMalloc(ptr, bytes) != hipSuccess) return fail(BD3MG_ERR_NOMEM, "%s (%zu bytes)", what, bytes);
+    *cap = bytes;
     return BD3MG_OK;
 }
 
@@ -296,6 +265,56 @@ void color_blocks(bd3mg_problem p)
             if (p->color[b] == c) p->order.push_back(b);
 }
 
+// Work items of a launch group (a set of blocks updated together):
+//   gradient pass: the blocks' own slices S;
+//   direction pass: S +- r_z (and slice z0 - 1 when kappa > 0, for VZ);
+//   update pass: S +- r_z,
+// all clipped to the volume, block by block in z order.
+void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<Item> &gi,
+                 std::vector<Item> &di, std::vector<Item> &ui, std::vector<BlockRange> &br,
+                 bd3mg_problem_s::Group &grp)
+{
+    const int rz = p->kz / 2;
+    const int rd = std::max(rz, p->prm.kappa > 0.0 ? 1 : 0);
+    grp.g_off = (int)gi.size();
+    grp.d_off = (int)di.size();
+    grp.u_off = (int)ui.size();
+    grp.br_off = (int)br.size();
+    std::vector<char> halo(p->nz, 0);
+    double sl = 0.0;
+    for (int b : blocks) {
+        const int z0 = p->z0[b], n = p->nsl[b];
+        BlockRange r{b, (int)gi.size() - grp.g_off, 0, (int)di.size() - grp.d_off, 0};
+        for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n});
+        for (int k = std::max(0, z0 - rd); k < std::min(p->nz, z0 + n + rz); ++k)
+            di.push_back(Item{k, b, z0, n});
+        for (int k = std::max(0, z0 - rz); k < std::min(p->nz, z0 + n + rz); ++k) {
+            ui.push_back(Item{k, b, z0, n});
+            halo[k] = 1;
+        }
+        r.gn = (int)gi.size() - grp.g_off - r.g0;
+        r.dn = (int)di.size() - grp.d_off - r.d0;
+        br.push_back(r);
+        sl += n;
+    }
+    grp.g_cnt = (int)gi.size() - grp.g_off;
+    grp.d_cnt = (int)di.size() - grp.d_off;
+    grp.u_cnt = (int)ui.size() - grp.u_off;
+    grp.br_cnt = (int)br.size() - grp.br_off;
+    double h = 0.0;
+    for (char c : halo) h += c;
+    // Algorithmic bytes (every element a pass must read or write counted once):
+    // gradient pass reads q on S +- r_z and x, dp on S and writes g on S;
+    // direction pass reads g, dp and x on S; solve reads the partial sums;
+    // update pass reads g, dp, x on S and q on S +- r_z, writes x, dp on S and
+    // q on S +- r_z.
+    const double A = (double)p->nx * p->ny * p->esz;
+    grp.bytes[0] = A * (h + 3.0 * sl);
+    grp.bytes[1] = A * 3.0 * sl;
+    grp.bytes[2] = (double)(grp.g_cnt * NQG + grp.d_cnt * NQD) * p->ntiles * sizeof(double);
+    grp.bytes[3] = A * (5.0 * sl + 2.0 * h);
+}
+
 bd3mg_status build_schedule(bd3mg_problem p)
 {
     if (!p->sched_dirty) return BD3MG_OK;
@@ -303,29 +322,31 @@ bd3mg_status build_schedule(bd3mg_problem p)
     if (!p->psf_set) return fail(BD3MG_ERR_STATE, "the PSF is not set (the colouring needs r_z)");
     color_blocks(p);
     const int nb = (int)p->nsl.size();
-    std::vector<Segment> segs;
-    p->col_off.assign(p->ncolors, 0);
-    p->col_cnt.assign(p->ncolors, 0);
-    int q = 0;
+    std::vector<Item> gi, di, ui;
+    std::vector<BlockRange> br;
+    p->groups.assign(p->ncolors + nb, bd3mg_problem_s::Group{});
     for (int c = 0; c < p->ncolors; ++c) {
-        p->col_off[c] = (int)segs.size();
-        while (q < nb && p->color[p->order[q]] == c) {
-            const int b = p->order[q++];
-            segs.push_back(Segment{p->z0[b], p->nsl[b], b, 0});
-        }
-        p->col_cnt[c] = (int)segs.size() - p->col_off[c];
+        std::vector<int> blocks;
+        for (int b : p->order)
+            if (p->color[b] == c) blocks.push_back(b);
+        group_items(p, blocks, gi, di, ui, br, p->groups[c]);
     }
-    // single-block segments for bd3mg_block_step follow, one per block
-    for (int b = 0; b < nb; ++b) segs.push_back(Segment{p->z0[b], p->nsl[b], b, 0});
-    if ((int)segs.size() > p->nseg_alloc) {
-        if (p->d_segs) HIP_TRY(hipFree(p->d_segs));
-        p->d_segs = nullptr;
-        if (hipMalloc(&p->d_segs, segs.size() * sizeof(Segment)) != hipSuccess)
-            return fail(BD3MG_ERR_NOMEM, "segment table");
-        p->nseg_alloc = (int)segs.size();
+    for (int b = 0; b < nb; ++b) group_items(p, {b}, gi, di, ui, br, p->groups[p->ncolors + b]);
+    // one device array: gradient items, then direction items, then update items
+    const int ng = (int)gi.size(), nd = (int)di.size();
+    for (auto &grp : p->groups) {
+        grp.d_off += ng;
+        grp.u_off += ng + nd;
     }
-    HIP_TRY(hipMemcpyAsync(p->d_segs, segs.data(), segs.size() * sizeof(Segment),
-                           hipMemcpyHostToDevice, p->stream));
+    std::vector<Item> all(gi);
+    all.insert(all.end(), di.begin(), di.end());
+    all.insert(all.end(), ui.begin(), ui.end());
+    ST_TRY(realloc_dev((void **)&p->d_items, &p->items_alloc, all.size() * sizeof(Item), "work items"));
+    ST_TRY(realloc_dev((void **)&p->d_br, &p->br_alloc, br.size() * sizeof(BlockRange), "block ranges"));
+    HIP_TRY(hipMemcpyAsync(p->d_items, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice,
+                           p->stream));
+    HIP_TRY(hipMemcpyAsync(p->d_br, br.data(), br.size() * sizeof(BlockRange), hipMemcpyHostToDevice,
+                           p->stream));
     if (nb > p->nblocks_alloc) {
         if (p->d_u) HIP_TRY(hipFree(p->d_u));
         if (p->d_info) HIP_TRY(hipFree(p->d_info));
@@ -335,54 +356,66 @@ bd3mg_status build_schedule(bd3mg_problem p)
             return fail(BD3MG_ERR_NOMEM, "per-block coefficients");
         p->nblocks_alloc = nb;
     }
-    int maxc = 1;
-    for (int c = 0; c < p->ncolors; ++c) maxc = std::max(maxc, p->col_cnt[c]);
-    const size_t slots = (size_t)p->geom.ntx * p->geom.nty;
-    ST_TRY(ensure_partials(p, std::max(slots * maxc * NQ, slots * p->nchunks * NE)));
+    int maxg = 1, maxd = 1;
+    for (auto &grp : p->groups) {
+        maxg = std::max(maxg, grp.g_cnt);
+        maxd = std::max(maxd, grp.d_cnt);
+    }
+    ST_TRY(realloc_dev((void **)&p->d_pg, &p->pg_cap, (size_t)maxg * p->ntiles * NQG * sizeof(double),
+                       "gradient partial sums"));
+    ST_TRY(realloc_dev((void **)&p->d_pd, &p->pd_cap, (size_t)maxd * p->ntiles * NQD * sizeof(double),
+                       "direction partial sums"));
     HIP_TRY(hipStreamSynchronize(p->stream));
-    color_bytes(p);
     p->sched_dirty = false;
     return BD3MG_OK;
 }
 
+// q = XY^T (H src - y), slice by slice, into qout.
 template <typename T>
-bd3mg_status residual_t(bd3mg_problem p, const T *xin, T *rout)
+bd3mg_status refresh_t(bd3mg_problem p, const T *src, T *qout)
 {
     DevState<T> s = dev_state<T>(p);
-    HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, rout, p->d_chunks, p->nchunks, p->stream));
+    HIP_TRY(launch_update<T>(p->geom, s, src, qout, p->d_vol, p->nz, nullptr, UM_REFRESH, p->stream));
     return BD3MG_OK;
 }
 
-bd3mg_status residual(bd3mg_problem p, const void *xin, void *rout)
+bd3mg_status refresh(bd3mg_problem p, const void *src, void *qout)
 {
-    return p->prec == BD3MG_FP64 ? residual_t<double>(p, (const double *)xin, (double *)rout)
-                                 : residual_t<float>(p, (const float *)xin, (float *)rout);
+    return p->prec == BD3MG_FP64 ? refresh_t<double>(p, (const double *)src, (double *)qout)
+                                 : refresh_t<float>(p, (const float *)src, (float *)qout);
 }
 
-// f and ||grad f|| at xin with residual rin (whole-volume gradient pass in
-// evaluation mode; partial sums reduced in a fixed order on the device).
+// ||grad f(xin)|| from the blurred residual qin, and, when f is wanted, f(xin)
+// (which needs the residual itself: one H pass into a scratch volume).  Sums
+// are reduced in a fixed order on the device.
 template <typename T>
-bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *rin, double *f, double *gn)
+bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, double *gn)
 {
     DevState<T> s = dev_state<T>(p);
-    s.x = (T *)xin;
-    HIP_TRY(launch_grad<T>(p->geom, p->prm, s, rin, nullptr, p->d_chunks, p->nchunks, GM_EVAL,
-                           p->d_partials, p->stream));
-    HIP_TRY(launch_sum_eval(p->d_partials, p->geom.ntx * p->geom.nty * p->nchunks, p->d_eval,
+    const int nslot = p->ntiles * p->nz;
+    HIP_TRY(launch_grad<T>(p->geom, p->prm, s, qin, xin, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe,
+                           p->stream));
+    HIP_TRY(launch_sum(p->d_pe, nslot, NQE, p->d_sum, p->stream));
+    if (f) {
+        ST_TRY(ensure_tmp(p, 1));
+        HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, (T *)p->tmp[0], p->d_vol, p->nz, p->d_pr,
                             p->stream));
-    double q[NE];
-    HIP_TRY(hipMemcpyAsync(q, p->d_eval, sizeof(q), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(launch_sum(p->d_pr, nslot, 1, p->d_sum + NQE, p->stream));
+    }
+    double q[NQE + 1] = {0, 0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(q, p->d_sum, (f ? NQE + 1 : NQE) * sizeof(double), hipMemcpyDeviceToHost,
+                           p->stream));
     HIP_TRY(hipStreamSynchronize(p->stream));
-    if (f) *f = 0.5 * q[1] + p->prm.eta * q[3] + p->prm.lambda * q[2] + p->prm.kappa * q[4];
+    if (f) *f = 0.5 * q[NQE] + p->prm.lambda * q[1] + p->prm.eta * q[2] + p->prm.kappa * q[3];
     if (gn) *gn = std::sqrt(q[0]);
     return BD3MG_OK;
 }
 
-bd3mg_status eval_at(bd3mg_problem p, const void *xin, const void *rin, double *f, double *gn)
+bd3mg_status eval_at(bd3mg_problem p, const void *xin, const void *qin, double *f, double *gn)
 {
     return p->prec == BD3MG_FP64
-               ? eval_t<double>(p, (const double *)xin, (const double *)rin, f, gn)
-               : eval_t<float>(p, (const float *)xin, (const float *)rin, f, gn);
+               ? eval_t<double>(p, (const double *)xin, (const double *)qin, f, gn)
+               : eval_t<float>(p, (const float *)xin, (const float *)qin, f, gn);
 }
 
 bd3mg_status ensure_ready(bd3mg_problem p)
@@ -394,49 +427,70 @@ bd3mg_status ensure_ready(bd3mg_problem p)
         HIP_TRY(hipMemcpyAsync(p->x, p->y, p->N * p->esz, hipMemcpyDeviceToDevice, p->stream));
         ST_TRY(zero_steps(p));
         p->x_set = true;
-        p->r_stale = true;
+        p->q_stale = true;
         p->sweeps_done = 0;
     }
     if (!p->gnorm_ref_valid) {
-        ST_TRY(ensure_tmp(p, 1));
-        ST_TRY(residual(p, p->y, p->tmp[0]));
-        ST_TRY(eval_at(p, p->y, p->tmp[0], nullptr, &p->gnorm_ref));
+        ST_TRY(ensure_tmp(p, 2));
+        ST_TRY(refresh(p, p->y, p->tmp[1]));
+        ST_TRY(eval_at(p, p->y, p->tmp[1], nullptr, &p->gnorm_ref));
         p->gnorm_ref_valid = true;
     }
-    if (p->r_stale) {
-        ST_TRY(residual(p, p->x, p->r));
-        p->r_stale = false;
+    if (p->q_stale) {
+        ST_TRY(refresh(p, p->x, p->q));
+        p->q_stale = false;
     }
     return BD3MG_OK;
 }
 
-// Enqueue the four passes of one colour phase over nseg segments.  cb (may be
-// null) holds the algorithmic bytes of the four passes for the profile.
+// Enqueue the passes of one launch group: gradient, direction, solve, update.
 template <typename T>
-bd3mg_status phase_t(bd3mg_problem p, const Segment *segs, int nseg, const double *cb)
+bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof)
 {
     DevState<T> s = dev_state<T>(p);
-    const int slots = p->geom.ntx * p->geom.nty;
-    ST_TRY(prof_begin(p, BD3MG_K_GRAD, cb ? cb[0] : 0.0));
-    HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.r, nullptr, segs, nseg, GM_BLOCK, p->d_partials,
-                           p->stream));
-    ST_TRY(prof_end(p));
-    ST_TRY(prof_begin(p, BD3MG_K_DIRS, cb ? cb[1] : 0.0));
-    HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, segs, nseg, p->d_partials, p->stream));
-    ST_TRY(prof_end(p));
-    ST_TRY(prof_begin(p, BD3MG_K_SOLVE, cb ? cb[2] : 0.0));
-    HIP_TRY(launch_solve(p->prm, segs, nseg, slots, p->d_partials, p->d_u, p->d_info, p->stream));
-    ST_TRY(prof_end(p));
-    ST_TRY(prof_begin(p, BD3MG_K_UPDATE, cb ? cb[3] : 0.0));
-    HIP_TRY(launch_update<T>(p->geom, s, segs, nseg, p->d_u, p->stream));
-    ST_TRY(prof_end(p));
+    const Item *it = p->d_items;
+    if (prof) ST_TRY(prof_begin(p, BD3MG_K_GRAD, gr.bytes[0]));
+    HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK,
+                           p->d_pg, p->stream));
+    if (prof) ST_TRY(prof_end(p));
+    if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
+    HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, it + gr.d_off, gr.d_cnt, p->d_pd, p->stream));
+    if (prof) ST_TRY(prof_end(p));
+    if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
+    HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles, p->d_pg, p->d_pd, p->d_u,
+                         p->d_info, p->stream));
+    if (prof) ST_TRY(prof_end(p));
+    if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
+    HIP_TRY(launch_update<T>(p->geom, s, nullptr, s.q, it + gr.u_off, gr.u_cnt, p->d_u, UM_UPDATE,
+                             p->stream));
+    if (prof) ST_TRY(prof_end(p));
     return BD3MG_OK;
 }
 
-bd3mg_status phase(bd3mg_problem p, const Segment *segs, int nseg, const double *cb)
+bd3mg_status phase(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof)
 {
-    return p->prec == BD3MG_FP64 ? phase_t<double>(p, segs, nseg, cb)
-                                 : phase_t<float>(p, segs, nseg, cb);
+    return p->prec == BD3MG_FP64 ? phase_t<double>(p, gr, prof) : phase_t<float>(p, gr, prof);
+}
+
+// One operator of the criterion on ti into to (tr: scratch), with the
+// solver's kernels: H directly; H^T as the adjoint in-slice blur of every
+// slice followed by the z-stencil; grad f from q = XY^T (H ti - y).
+template <typename T>
+bd3mg_status apply_t(bd3mg_problem p, int op, T *ti, T *to, T *tr)
+{
+    DevState<T> s = dev_state<T>(p);
+    if (op == BD3MG_OP_H) {
+        HIP_TRY(launch_H<T>(p->geom, s, ti, nullptr, to, p->d_vol, p->nz, nullptr, p->stream));
+    } else if (op == BD3MG_OP_HT) {
+        HIP_TRY(launch_blurT<T>(p->geom, s, ti, tr, p->d_vol, p->nz, p->stream));
+        HIP_TRY(launch_grad<T>(p->geom, p->prm, s, tr, ti, to, p->d_vol, p->nz, GM_ZCOMB, nullptr,
+                               p->stream));
+    } else {
+        HIP_TRY(launch_update<T>(p->geom, s, ti, tr, p->d_vol, p->nz, nullptr, UM_REFRESH, p->stream));
+        HIP_TRY(launch_grad<T>(p->geom, p->prm, s, tr, ti, to, p->d_vol, p->nz, GM_GRAD, nullptr,
+                               p->stream));
+    }
+    return BD3MG_OK;
 }
 
 bd3mg_status validate_handle(bd3mg_problem p)
@@ -501,20 +555,21 @@ bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *
         return bail(BD3MG_ERR_HIP, "stream creation failed");
     if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
         return bail(BD3MG_ERR_HIP, "event creation failed");
-    void **vols[] = {&p->x, &p->y, &p->r, &p->g, &p->dpb[0], &p->dpb[1]};
+    p->ntiles = p->geom.ntx * p->geom.nty;
+    void **vols[] = {&p->x, &p->y, &p->q, &p->g, &p->dpb[0], &p->dpb[1]};
     for (void **v : vols)
         if (hipMalloc(v, p->N * p->esz) != hipSuccess) return bail(BD3MG_ERR_NOMEM, "volume allocation failed");
-    // whole-volume chunks
-    p->nchunks = (nz + CHUNK - 1) / CHUNK;
-    std::vector<Segment> ch;
-    for (int z = 0; z < nz; z += CHUNK) ch.push_back(Segment{z, std::min(CHUNK, nz - z), -1, 0});
-    if (hipMalloc(&p->d_chunks, ch.size() * sizeof(Segment)) != hipSuccess ||
-        hipMalloc(&p->d_eval, NE * sizeof(double)) != hipSuccess)
+    // every slice of the volume as a work item, and the evaluation sums
+    std::vector<Item> vol;
+    for (int k = 0; k < nz; ++k) vol.push_back(Item{k, -1, 0, nz});
+    const size_t nslot = (size_t)p->ntiles * nz;
+    if (hipMalloc(&p->d_vol, vol.size() * sizeof(Item)) != hipSuccess ||
+        hipMalloc(&p->d_pe, nslot * NQE * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->d_pr, nslot * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->d_sum, (NQE + 1) * sizeof(double)) != hipSuccess)
         return bail(BD3MG_ERR_NOMEM, "tables");
-    if (hipMemcpy(p->d_chunks, ch.data(), ch.size() * sizeof(Segment), hipMemcpyHostToDevice) != hipSuccess)
-        return bail(BD3MG_ERR_HIP, "chunk upload failed");
-    if (ensure_partials(p, (size_t)p->geom.ntx * p->geom.nty * p->nchunks * NE) != BD3MG_OK)
-        return bail(BD3MG_ERR_NOMEM, "partials");
+    if (hipMemcpy(p->d_vol, vol.data(), vol.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(BD3MG_ERR_HIP, "item upload failed");
     if (zero_steps(p) != BD3MG_OK) return bail(BD3MG_ERR_HIP, "clearing steps failed");
     *out = p;
     return BD3MG_OK;
@@ -524,9 +579,9 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
 {
     if (!p) return BD3MG_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    void *bufs[] = {p->x, p->y, p->r, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2],
-                    p->d_gx, p->d_gy, p->d_gz, p->d_segs, p->d_chunks, p->d_partials, p->d_u,
-                    p->d_info, p->d_eval};
+    void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2],
+                    p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_pg, p->d_pd,
+                    p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &q : p->pending) {
@@ -553,8 +608,15 @@ bd3mg_status bd3mg_set_psf_separable(bd3mg_problem p, int kx, int ky, int kz, co
     ST_TRY(check_finite(gx, (size_t)p->nz * kx, "gx"));
     ST_TRY(check_finite(gy, (size_t)p->nz * ky, "gy"));
     ST_TRY(check_finite(gz, (size_t)p->nz * kz, "gz"));
-    const double *src[3] = {gx, gy, gz};
-    const int ks[3] = {kx, ky, kz};
+    // in-slice tables are stored centred in 2R + 1 taps, R = max(rx, ry, 1)
+    const int R = std::max(1, std::max(kx / 2, ky / 2)), KR = 2 * R + 1;
+    std::vector<double> px((size_t)p->nz * KR, 0.0), py((size_t)p->nz * KR, 0.0);
+    for (int z = 0; z < p->nz; ++z) {
+        for (int a = 0; a < kx; ++a) px[(size_t)z * KR + R - kx / 2 + a] = gx[(size_t)z * kx + a];
+        for (int a = 0; a < ky; ++a) py[(size_t)z * KR + R - ky / 2 + a] = gy[(size_t)z * ky + a];
+    }
+    const double *src[3] = {px.data(), py.data(), gz};
+    const int ks[3] = {KR, KR, kz};
     void **dst[3] = {&p->d_gx, &p->d_gy, &p->d_gz};
     for (int t = 0; t < 3; ++t) {
         const size_t n = (size_t)p->nz * ks[t];
@@ -568,6 +630,7 @@ bd3mg_status bd3mg_set_psf_separable(bd3mg_problem p, int kx, int ky, int kz, co
             HIP_TRY(hipMemcpy(*dst[t], f.data(), n * sizeof(float), hipMemcpyHostToDevice));
         }
     }
+    p->geom.R = R;
     p->kx = kx;
     p->ky = ky;
     p->kz = kz;
@@ -575,7 +638,7 @@ bd3mg_status bd3mg_set_psf_separable(bd3mg_problem p, int kx, int ky, int kz, co
     p->geom.ry = ky / 2;
     p->geom.rz = kz / 2;
     p->psf_set = true;
-    p->r_stale = true;
+    p->q_stale = true;
     p->gnorm_ref_valid = false;
     p->sched_dirty = true;
     return BD3MG_OK;
@@ -614,7 +677,7 @@ bd3mg_status bd3mg_set_data(bd3mg_problem p, const void *y, int on_device)
     if (!y) return fail(BD3MG_ERR_ARG, "null data");
     ST_TRY(upload(p, p->y, y, on_device));
     p->data_set = true;
-    p->r_stale = true;
+    p->q_stale = true;
     p->gnorm_ref_valid = false;
     return BD3MG_OK;
 }
@@ -669,7 +732,7 @@ bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device)
     ST_TRY(zero_steps(p));
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->x_set = true;
-    p->r_stale = true;
+    p->q_stale = true;
     p->sweeps_done = 0;
     return BD3MG_OK;
 }
@@ -689,20 +752,19 @@ bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int ch
     bool conv = false;
     double gn = NAN, f = NAN;
     for (int s = 0; s < max_sweeps; ++s) {
-        for (int c = 0; c < p->ncolors; ++c)
-            ST_TRY(phase(p, p->d_segs + p->col_off[c], p->col_cnt[c], &p->color_bytes[(size_t)c * 4]));
+        for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile));
         p->cur ^= 1;
         ++done;
         ++p->sweeps_done;
         if (p->refresh_every > 0 && (p->sweeps_done % p->refresh_every) == 0) {
             ST_TRY(prof_begin(p, BD3MG_K_EVAL, 3.0 * vol));
-            ST_TRY(residual(p, p->x, p->r));
+            ST_TRY(refresh(p, p->x, p->q));
             ST_TRY(prof_end(p));
         }
         const bool last = (s == max_sweeps - 1);
         if (checking && ((done % check_every) == 0 || last)) {
             ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol));
-            ST_TRY(eval_at(p, p->x, p->r, &f, &gn));
+            ST_TRY(eval_at(p, p->x, p->q, nullptr, &gn));
             ST_TRY(prof_end(p));
             if (grad_rtol > 0.0 && gn <= grad_rtol * p->gnorm_ref) {
                 conv = true;
@@ -712,6 +774,7 @@ bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int ch
         if (p->pending.size() > 4096) ST_TRY(prof_collect(p));
     }
     HIP_TRY(hipEventRecord(p->ev1, p->stream));
+    if (checking) ST_TRY(eval_at(p, p->x, p->q, &f, &gn));
     HIP_TRY(hipEventSynchronize(p->ev1));
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
@@ -745,20 +808,20 @@ bd3mg_status bd3mg_get_dprev(bd3mg_problem p, void *d, int on_device)
     return download(p, d, p->dpb[p->cur], on_device);
 }
 
-bd3mg_status bd3mg_get_state(bd3mg_problem p, void *x, void *dprev, void *r, long long *sweeps,
+bd3mg_status bd3mg_get_state(bd3mg_problem p, void *x, void *dprev, void *q, long long *sweeps,
                              int on_device)
 {
     ST_TRY(validate_handle(p));
     if (!p->x_set) return fail(BD3MG_ERR_STATE, "no iterate yet");
-    if (r && p->r_stale) ST_TRY(ensure_ready(p));
+    if (q && p->q_stale) ST_TRY(ensure_ready(p));
     if (x) ST_TRY(download(p, x, p->x, on_device));
     if (dprev) ST_TRY(download(p, dprev, p->dpb[p->cur], on_device));
-    if (r) ST_TRY(download(p, r, p->r, on_device));
+    if (q) ST_TRY(download(p, q, p->q, on_device));
     if (sweeps) *sweeps = p->sweeps_done;
     return BD3MG_OK;
 }
 
-bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, const void *r,
+bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, const void *q,
                              long long sweeps, int on_device)
 {
     ST_TRY(validate_handle(p));
@@ -767,11 +830,11 @@ bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, 
     ST_TRY(upload(p, p->x, x, on_device));
     ST_TRY(upload(p, p->dpb[p->cur], dprev, on_device));
     p->x_set = true;
-    if (r) {
-        ST_TRY(upload(p, p->r, r, on_device));
-        p->r_stale = false;
+    if (q) {
+        ST_TRY(upload(p, p->q, q, on_device));
+        p->q_stale = false;
     } else {
-        p->r_stale = true;
+        p->q_stale = true;
     }
     p->sweeps_done = sweeps;
     return BD3MG_OK;
@@ -816,8 +879,8 @@ bd3mg_status bd3mg_eval(bd3mg_problem p, double *f, double *grad_norm)
 {
     ST_TRY(validate_handle(p));
     ST_TRY(ensure_ready(p));
-    ST_TRY(residual(p, p->x, p->r));
-    return eval_at(p, p->x, p->r, f, grad_norm);
+    ST_TRY(refresh(p, p->x, p->q));
+    return eval_at(p, p->x, p->q, f, grad_norm);
 }
 
 bd3mg_status bd3mg_apply(bd3mg_problem p, int op, const void *in, void *out, int on_device)
@@ -831,35 +894,9 @@ bd3mg_status bd3mg_apply(bd3mg_problem p, int op, const void *in, void *out, int
     ST_TRY(ensure_tmp(p, 3));
     ST_TRY(upload(p, p->tmp[0], in, on_device));
     if (p->prec == BD3MG_FP64) {
-        DevState<double> s = dev_state<double>(p);
-        double *ti = (double *)p->tmp[0], *to = (double *)p->tmp[1], *tr = (double *)p->tmp[2];
-        if (op == BD3MG_OP_H) {
-            HIP_TRY(launch_H<double>(p->geom, s, ti, nullptr, to, p->d_chunks, p->nchunks, p->stream));
-        } else if (op == BD3MG_OP_HT) {
-            HIP_TRY(launch_grad<double>(p->geom, p->prm, s, ti, to, p->d_chunks, p->nchunks, GM_HT,
-                                        nullptr, p->stream));
-        } else {
-            HIP_TRY(launch_H<double>(p->geom, s, ti, (const double *)p->y, tr, p->d_chunks, p->nchunks,
-                                     p->stream));
-            s.x = ti;
-            HIP_TRY(launch_grad<double>(p->geom, p->prm, s, tr, to, p->d_chunks, p->nchunks, GM_GRAD,
-                                        nullptr, p->stream));
-        }
+        ST_TRY(apply_t<double>(p, op, (double *)p->tmp[0], (double *)p->tmp[1], (double *)p->tmp[2]));
     } else {
-        DevState<float> s = dev_state<float>(p);
-        float *ti = (float *)p->tmp[0], *to = (float *)p->tmp[1], *tr = (float *)p->tmp[2];
-        if (op == BD3MG_OP_H) {
-            HIP_TRY(launch_H<float>(p->geom, s, ti, nullptr, to, p->d_chunks, p->nchunks, p->stream));
-        } else if (op == BD3MG_OP_HT) {
-            HIP_TRY(launch_grad<float>(p->geom, p->prm, s, ti, to, p->d_chunks, p->nchunks, GM_HT,
-                                       nullptr, p->stream));
-        } else {
-            HIP_TRY(launch_H<float>(p->geom, s, ti, (const float *)p->y, tr, p->d_chunks, p->nchunks,
-                                    p->stream));
-            s.x = ti;
-            HIP_TRY(launch_grad<float>(p->geom, p->prm, s, tr, to, p->d_chunks, p->nchunks, GM_GRAD,
-                                       nullptr, p->stream));
-        }
+        ST_TRY(apply_t<float>(p, op, (float *)p->tmp[0], (float *)p->tmp[1], (float *)p->tmp[2]));
     }
     return download(p, out, p->tmp[1], on_device);
 }
@@ -870,8 +907,7 @@ bd3mg_status bd3mg_block_step(bd3mg_problem p, int block, double *info)
     ST_TRY(ensure_ready(p));
     const int nb = (int)p->nsl.size();
     if (block < 0 || block >= nb) return fail(BD3MG_ERR_ARG, "block %d out of range", block);
-    const int segi = p->col_off.empty() ? 0 : (int)(p->order.size()) + block;
-    ST_TRY(phase(p, p->d_segs + segi, 1, nullptr));
+    ST_TRY(phase(p, p->groups[p->ncolors + block], false));
     // keep every block's step in one buffer: copy this block's new step back
     const size_t off = (size_t)p->z0[block] * p->nx * p->ny * p->esz;
     const size_t len = (size_t)p->nsl[block] * p->nx * p->ny * p->esz;

@@ -8,30 +8,38 @@
 
 namespace bd3mg {
 
-// Output tile of one workgroup: TX columns (one wavefront wide) by TY rows.
+// Output tile of one workgroup: TX columns (one wavefront wide) by TY rows;
+// each of the NT threads owns TY / (NT / TX) = 4 outputs of a column.
 constexpr int TX = 64;
 constexpr int TY = 16;
 constexpr int NT = 256;     // threads per workgroup (4 wavefronts)
 constexpr int RMAX = 4;     // largest in-slice kernel radius (kernels up to 9 wide)
 constexpr int KZMAX = 9;    // largest kernel extent along z
 
-// Number of double partial sums each workgroup slot writes for a block.
-//  0 <g,g>        1 <g,dp>        2 <dp,dp>            (gradient pass)
-//  3 <Hd1,Hd1>    4 <Hd1,Hd2>     5 <Hd2,Hd2>          (direction pass)
-//  6 sum w Dd1.Dd1  7 sum w Dd1.Dd2  8 sum w Dd2.Dd2
-//  9 <VZd1,VZd1>  10 <VZd1,VZd2>  11 <VZd2,VZd2>
-constexpr int NQ = 12;
-// Partial sums of the evaluation pass:
-//  0 ||g||^2  1 ||r||^2  2 sum sqrt(|Dx|^2 + delta^2)  3 sum (x - clip x)^2  4 ||VZ x||^2
-constexpr int NE = 5;
+// Partial sums written per (work item, tile) slot.
+//  gradient pass: 0 <g,g>  1 <g,dp>  2 <dp,dp>
+constexpr int NQG = 3;
+//  direction pass: 0 <Hd1,Hd1> 1 <Hd1,Hd2> 2 <Hd2,Hd2>
+//                  3 sum w Dd1.Dd1  4 sum w Dd1.Dd2  5 sum w Dd2.Dd2
+//                  6 <VZd1,VZd1>  7 <VZd1,VZd2>  8 <VZd2,VZd2>
+constexpr int NQD = 9;
+//  evaluation: 0 ||g||^2  1 sum sqrt(|Dx|^2 + delta^2)  2 sum (x - clip x)^2  3 ||VZ x||^2
+constexpr int NQE = 4;
 
-// A run of consecutive z-slices handled by one column of workgroups: a block
-// of the partition, or a chunk of the volume for whole-volume passes.
-struct Segment {
+// One output slice k of a pass, for the block [z0, z0 + n) (block -1 and the
+// whole volume for volume passes).
+struct Item {
+    int k;
+    int block;
     int z0;
     int n;
-    int block;   // block index (or -1 for volume chunks)
-    int parity;  // which previous-step buffer holds the block's last step
+};
+
+// Work items of one block inside the item lists of a launch group.
+struct BlockRange {
+    int block;
+    int g0, gn;  // gradient-pass items [g0, g0 + gn)
+    int d0, dn;  // direction-pass items [d0, d0 + dn)
 };
 
 struct Params {
@@ -41,48 +49,64 @@ struct Params {
 struct Geom {
     int nx, ny, nz;
     int rx, ry, rz;
+    int R;         // in-slice radius of the device tables: max(rx, ry, 1)
     int ntx, nty;  // tiles per slice
 };
 
-// Device state of a problem, in storage type T.
+// Device state of a problem, in storage type T.  q holds, slice by slice,
+// q_m = XY^T_m (H x - y)_m: the residual blurred in-slice by the adjoint of
+// slice m's own factors, so that (H^T (H x - y))_k = sum_c gz_{k+c}[c] q_{k+c}.
 template <typename T>
 struct DevState {
-    T *x, *y, *r, *g, *dp[2];
-    const T *gx, *gy, *gz;  // PSF tables [nz][k]
+    T *x, *y, *q, *g, *dp[2];  // dp[0]: previous steps read, dp[1]: written
+    const T *gx, *gy;          // in-slice PSF tables [nz][2R + 1], centred, zero-padded
+    const T *gz;               // z PSF table [nz][kz]
 };
 
 enum GradMode : int {
-    GM_BLOCK = 0,  // write g on the block, partial sums 0..2
-    GM_EVAL = 1,   // no write; evaluation partial sums of f and ||grad f||
-    GM_HT = 2,     // write H^T r into out
-    GM_GRAD = 3    // write grad f into out
+    GM_BLOCK = 0,  // g on the items' slices -> s.g, partials NQG
+    GM_EVAL = 1,   // no write; partials NQE of ||grad f|| and the non-data terms of f
+    GM_ZCOMB = 2,  // out = sum_c gz_{k+c}[c] q_{k+c}  (H^T of the blurred input)
+    GM_GRAD = 3    // out = grad f
+};
+
+enum UpdateMode : int {
+    UM_UPDATE = 0,  // d' = -u1 g + u2 dp on the block: q += XY^T H d', x += d', dp[1] = d'
+    UM_REFRESH = 1  // q = XY^T (H src - y) on the items' slices
 };
 
 template <typename T>
-hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *rin,
-                       T *out, const Segment *segs, int nseg, int mode, double *partials,
-                       hipStream_t st);
+hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *q,
+                       const T *x, T *out, const Item *items, int nitems, int mode,
+                       double *partials, hipStream_t st);
 
 template <typename T>
-hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s,
-                       const Segment *segs, int nseg, double *partials, hipStream_t st);
+hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
+                       int nitems, double *partials, hipStream_t st);
 
 template <typename T>
-hipError_t launch_update(const Geom &g, const DevState<T> &s, const Segment *segs, int nseg,
-                         const double *u, hipStream_t st);
+hipError_t launch_update(const Geom &g, const DevState<T> &s, const T *src, T *qout,
+                         const Item *items, int nitems, const double *u, int mode, hipStream_t st);
 
-// out = H(in) - sub (sub may be null) on the slices of the segments.
+// out = H(in) - sub (sub may be null) on the items' slices; with partials,
+// each slot also receives its sum of out^2.
 template <typename T>
 hipError_t launch_H(const Geom &g, const DevState<T> &s, const T *in, const T *sub, T *out,
-                    const Segment *segs, int nseg, hipStream_t st);
+                    const Item *items, int nitems, double *partials, hipStream_t st);
 
-// Per block: fixed-order sum of its workgroup partials, the 2x2 majorant
-// system, its pseudo-inverse and the step coefficients u (2 doubles per block).
-hipError_t launch_solve(const Params &prm, const Segment *segs, int nseg, int slots_per_seg,
-                        const double *partials, double *u, double *info, hipStream_t st);
+// out_m = XY^T_m in_m on the items' slices.
+template <typename T>
+hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out,
+                        const Item *items, int nitems, hipStream_t st);
 
-// Fixed-order sum of nslot evaluation slots of NE doubles into out[NE].
-hipError_t launch_sum_eval(const double *partials, int nslot, double *out, hipStream_t st);
+// Per block range: fixed-order reduction of the block's slots, the 2x2
+// majorant system, its pseudo-inverse and the step coefficients u.
+hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles,
+                        const double *pg, const double *pd, double *u, double *info,
+                        hipStream_t st);
+
+// Fixed-order sum of nslot slots of nq doubles into out[nq].
+hipError_t launch_sum(const double *partials, int nslot, int nq, double *out, hipStream_t st);
 
 // Streaming copy of n 16-byte words (bandwidth probe).
 hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st);

@@ -1,28 +1,38 @@
 // gfx950 kernels of libbd3mg: the per-block work of one BD3MG update
 // (Sec. 2.3, box "Worker", for the criterion of Sec. 3.1).
 //
-// Layout: volumes are [nz][ny][nx], x fastest.  A workgroup owns a TX x TY
-// tile of every slice it touches and marches along z through its segment:
-// each global row it reads is 64 consecutive elements (one wavefront, fully
-// coalesced), in-slice halos are staged through LDS, and the separable
-// depth-variant blur is applied as an x pass then a y pass in LDS.  The
-// z-direction of H^T is carried in a register ring of KZ partial sums.
+// Layout and decomposition.  Volumes are [nz][ny][nx], x fastest.  Every pass
+// is split into independent work items, one output slice each, and a
+// workgroup computes one TX x TY tile of one item: a launch has (tiles per
+// slice) x (items) workgroups, enough to fill the 256 CUs even for a single
+// colour of blocks.  Global rows are read 64 consecutive elements at a time
+// (one wavefront, coalesced); in-slice halos go through LDS, where the
+// separable depth-variant blur runs as an x pass then a y pass.
 //
-// Inner products are accumulated in double: per thread in index order, then a
-// wavefront shuffle tree, then the four wavefronts in order, then the
-// workgroup slots of a block in slot order (k_solve) -- a fixed order, so
-// every run gives bitwise identical results.
+// The z extent KZ and the in-slice radius R of the PSF are template
+// parameters: every tile loop has a compile-time trip count, so each thread
+// issues all global loads of a stencil before it waits for any of them, and
+// the filter taps sit in registers.  In-slice tables are stored with 2R + 1
+// taps per slice (zero-padded when kx != ky).
+//
+// The residual enters only through q_m = XY^T_m (H x - y)_m (each slice
+// blurred by the adjoint of its own in-slice factors), so the data part of
+// the gradient is a pure z-stencil, (H^T r)_k = sum_c gz_{k+c}[c] q_{k+c},
+// and the update pass keeps q current: q_m += XY^T_m (H d')_m.
+//
+// Inner products are accumulated in double: per thread in index order, a
+// wavefront shuffle tree, the four wavefronts in order, then the slots of a
+// block in slot order (k_solve) -- a fixed order, so runs are bitwise
+// reproducible.
 #include "bd3mg_internal.h"
 
 namespace bd3mg {
 
 namespace {
 
-constexpr int LW = TX + 2 * RMAX;  // LDS row stride of halo tiles
-constexpr int LH = TY + 2 * RMAX;  // LDS rows of halo tiles
-constexpr int XW = TX + 2;         // iterate tile with a 1-voxel halo
+constexpr int RPT = TY / (NT / TX);  // outputs (rows) per thread: 4
+constexpr int XW = TX + 2;           // iterate tile with a 1-voxel halo
 constexpr int XH = TY + 2;
-constexpr int ROWS_PER_THREAD = TY / (NT / TX);  // 4
 
 __device__ __forceinline__ size_t vidx(const Geom &g, int k, int j, int i)
 {
@@ -32,51 +42,80 @@ __device__ __forceinline__ size_t vidx(const Geom &g, int k, int j, int i)
 template <typename T>
 __device__ __forceinline__ T clampv(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// Fill a (TY+2R) x (TX+2R) halo tile with f(j, i) at global (j, i) =
-// (y0 - R + jj, x0 - R + ii); zero outside the slice.
-template <typename T, typename F>
-__device__ __forceinline__ void fill_halo(T *A, int x0, int y0, int R, const Geom &g, F f)
+// 1 / sqrt(v): the hardware reciprocal square root in single precision
+// (about 1 ulp), the correctly rounded quotient in double precision.
+__device__ __forceinline__ float inv_sqrt(float v) { return rsqrtf(v); }
+__device__ __forceinline__ double inv_sqrt(double v) { return 1.0 / sqrt(v); }
+
+__device__ __forceinline__ int out_row(int e) { return (int)(threadIdx.x / TX) + (NT / TX) * e; }
+
+constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// Element e = threadIdx.x + q NT of a W x H region whose corner is at global
+// (y0 - HY, x0 - HX): in-range flags and the in-slice offset j nx + i (valid
+// when inb).  Element e sits at LDS index e of a W-wide tile.
+template <int W, int H, int HX, int HY>
+struct Region {
+    static constexpr int N = W * H;
+    static constexpr int E = cdiv(N, NT);
+    int off[E];
+    bool act[E], inb[E];
+    __device__ __forceinline__ Region(const Geom &g, int x0, int y0)
+    {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int e = threadIdx.x + q * NT;
+            const int jj = e / W, ii = e - jj * W;
+            const int j = y0 - HY + jj, i = x0 - HX + ii;
+            act[q] = e < N;
+            inb[q] = act[q] && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+            off[q] = inb[q] ? j * g.nx + i : 0;
+        }
+    }
+};
+
+// x pass from I (rows of width WI) to O (rows of width WO), WO output columns
+// over ROWS rows:  forward O[r][c] = sum_a wx[a] I[r][c + OFF - a],
+//                  adjoint O[r][c] = sum_a wx[a] I[r][c + OFF + a].
+template <typename T, int R, int WI, int WO, int ROWS, int OFF, bool ADJ>
+__device__ __forceinline__ void xpass(const T *I, T *O, const T (&wx)[2 * R + 1])
 {
-    const int w = TX + 2 * R, tot = w * (TY + 2 * R);
-    for (int e = threadIdx.x; e < tot; e += NT) {
-        const int jj = e / w, ii = e - jj * w;
-        const int j = y0 - R + jj, i = x0 - R + ii;
-        A[jj * LW + ii] = (i >= 0 && i < g.nx && j >= 0 && j < g.ny) ? f(j, i) : T(0);
+    constexpr int N = WO * ROWS, E = cdiv(N, NT);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (e < N) {
+            const int r = e / WO, c = e - r * WO;
+            const T *row = I + r * WI + c + OFF;
+            T acc = 0;
+#pragma unroll
+            for (int a = -R; a <= R; ++a) acc += wx[a + R] * row[ADJ ? a : -a];
+            O[e] = acc;
+        }
     }
 }
 
-// x pass of the in-slice blur over rows [R - ry, R + TY + ry) of A into B.
-// Forward (H):   B[jb][i] = sum_a wx[a + rx] A[.][i + R - a]
-// Adjoint (H^T): B[jb][i] = sum_a wx[a + rx] A[.][i + R + a]
-template <typename T, bool ADJ>
-__device__ __forceinline__ void xpass(const T *A, T *B, const T *__restrict__ wx, int rx, int ry,
-                                      int R)
+// y pass into registers: v[e] at tile row out_row(e), column threadIdx.x % TX,
+// reading rows (out_row + OFF -/+ b) of B (rows of width WB).
+template <typename T, int R, int WB, int OFF, bool ADJ>
+__device__ __forceinline__ void ypass_out(const T *B, T (&v)[RPT], const T (&wy)[2 * R + 1])
 {
     const int i = threadIdx.x & (TX - 1);
-    const int rows = TY + 2 * ry;
-    for (int jb = threadIdx.x / TX; jb < rows; jb += NT / TX) {
-        const T *row = A + (jb + R - ry) * LW + i + R;
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const T *col = B + (out_row(e) + OFF) * WB + i;
         T acc = 0;
-        for (int a = -rx; a <= rx; ++a) acc += wx[a + rx] * row[ADJ ? a : -a];
-        B[jb * TX + i] = acc;
+#pragma unroll
+        for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[(ADJ ? b : -b) * WB];
+        v[e] = acc;
     }
 }
 
-// y pass: v[e] at output row ty + 4 e.
-// Forward: sum_b wy[b + ry] B[j + ry - b];  adjoint: B[j + ry + b].
-template <typename T, bool ADJ>
-__device__ __forceinline__ void ypass(const T *B, T (&v)[ROWS_PER_THREAD], const T *__restrict__ wy,
-                                      int ry)
+template <typename T, int R>
+__device__ __forceinline__ void load_taps(T (&w)[2 * R + 1], const T *__restrict__ t)
 {
-    const int i = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
 #pragma unroll
-    for (int e = 0; e < ROWS_PER_THREAD; ++e) {
-        const int j = ty + (NT / TX) * e;
-        const T *col = B + (j + ry) * TX + i;
-        T acc = 0;
-        for (int b = -ry; b <= ry; ++b) acc += wy[b + ry] * col[(ADJ ? b : -b) * TX];
-        v[e] = acc;
-    }
+    for (int a = 0; a < 2 * R + 1; ++a) w[a] = t[a];
 }
 
 // Workgroup reduction of NV doubles (shuffle tree per wavefront, then the
@@ -100,431 +139,548 @@ __device__ __forceinline__ void wg_reduce_store(double (&q)[NV], double *red, do
     }
 }
 
-// Iterate tile of slice k with a one-voxel halo into X ((TY+2) x (TX+2)).
-template <typename T>
-__device__ __forceinline__ void fill_x_tile(T *X, const T *__restrict__ x, const Geom &g, int k,
-                                            int x0, int y0)
+__device__ __forceinline__ size_t slot_of()
 {
-    const T *xs = x + (size_t)k * g.nx * g.ny;
-    for (int e = threadIdx.x; e < XW * XH; e += NT) {
-        const int jj = e / XW, ii = e - jj * XW;
-        const int j = y0 - 1 + jj, i = x0 - 1 + ii;
-        X[e] = (i >= 0 && i < g.nx && j >= 0 && j < g.ny) ? xs[(size_t)j * g.nx + i] : T(0);
-    }
+    return ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Gradient pass.  For each output slice k of the segment:
-//   (H^T r)_k = sum_c gz_{k+c}[c] XY^T_{k+c}(r_{k+c})
-// computed by blurring every input slice m once (its own factors, adjoint
-// form) and scattering it into the KZ pending outputs held in registers.
-// Then, per mode:
-//   GM_BLOCK: g = H^T r + lambda (VX^T w VX x + VY^T w VY x) + 2 eta (x - clip x)
-//             + 2 kappa VZ^T VZ x, written to s.g, with <g,g>, <g,dp>, <dp,dp>;
-//   GM_GRAD:  the same g written to out;
-//   GM_EVAL:  no write; sums of ||g||^2, ||r||^2, TV, box and VZ terms of f;
-//   GM_HT:    H^T r written to out.
+// Gradient pass, one output slice k per item:
+//   (H^T r)_k = sum_c gz_{k+c}[c] q_{k+c}
+//   g = H^T r + lambda (VX^T(w VX x) + VY^T(w VY x)) + 2 eta (x - clip x)
+//       + 2 kappa VZ^T VZ x,     w = 1 / sqrt((VX x)^2 + (VY x)^2 + delta^2)
+// GM_BLOCK writes g to s.g with <g,g>, <g,dp>, <dp,dp>; GM_GRAD writes g to
+// out; GM_EVAL sums ||g||^2 and the TV, box and z terms of f; GM_ZCOMB writes
+// only the z-stencil of q to out.
 // ---------------------------------------------------------------------------
 template <typename T, int KZ>
 __global__ void __launch_bounds__(NT)
-k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ rin, T *__restrict__ out,
-       const Segment *__restrict__ segs, int mode, double *__restrict__ partials)
+k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
+       T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials)
 {
     constexpr int RZ = KZ / 2;
-    __shared__ T A[LH * LW];
-    __shared__ T B[LH * TX];
+    constexpr int PW = TX + 1, PH = TY + 1;
     __shared__ T X[XW * XH];
-    __shared__ double red[(NT / 64) * NE];
+    __shared__ T PX[PW * PH];
+    __shared__ T PY[PW * PH];
+    __shared__ double red[(NT / 64) * NQE];
 
-    const Segment sg = segs[blockIdx.z];
+    const Item it = items[blockIdx.z];
+    const int k = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-    const int R = max(g.rx, g.ry);
-    const int kx = 2 * g.rx + 1, ky = 2 * g.ry + 1;
+    const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
-    const T lam = (T)prm.lambda, del2 = (T)(prm.delta * prm.delta), eta2 = (T)(2.0 * prm.eta),
-            kap2 = (T)(2.0 * prm.kappa), lo = (T)prm.xmin, hi = (T)prm.xmax;
-    const T *dpv = s.dp[sg.parity & 1];
 
-    T acc[KZ][ROWS_PER_THREAD];
+    // iterate tile of slice k with a one-voxel halo, loads issued first
+    Region<XW, XH, 1, 1> rx(g, x0, y0);
+    T xr[rx.E];
+    if (mode != GM_ZCOMB) {
+        const T *xs = x + (size_t)k * S;
 #pragma unroll
-    for (int q = 0; q < KZ; ++q)
-#pragma unroll
-        for (int e = 0; e < ROWS_PER_THREAD; ++e) acc[q][e] = 0;
-    double qs[NE] = {0.0, 0.0, 0.0, 0.0, 0.0};
-
-    for (int m = sg.z0 - RZ; m < sg.z0 + sg.n + RZ; ++m) {
-        if (m >= 0 && m < g.nz) {
-            const T *rs = rin + (size_t)m * S;
-            __syncthreads();
-            fill_halo(A, x0, y0, R, g, [&](int j, int i) { return rs[(size_t)j * g.nx + i]; });
-            __syncthreads();
-            xpass<T, true>(A, B, s.gx + (size_t)m * kx, g.rx, g.ry, R);
-            __syncthreads();
-            T v[ROWS_PER_THREAD];
-            ypass<T, true>(B, v, s.gy + (size_t)m * ky, g.ry);
-            const T *wz = s.gz + (size_t)m * KZ;
-#pragma unroll
-            for (int q = 0; q < KZ; ++q) {
-                const T w = wz[2 * RZ - q];  // input m feeds output k = m - RZ + q with c = RZ - q
-#pragma unroll
-                for (int e = 0; e < ROWS_PER_THREAD; ++e) acc[q][e] += w * v[e];
-            }
-        }
-        const int k = m - RZ;
-        if (k >= sg.z0) {
-            if (mode == GM_HT) {
-#pragma unroll
-                for (int e = 0; e < ROWS_PER_THREAD; ++e) {
-                    const int j = y0 + ty + (NT / TX) * e, i = x0 + tx;
-                    if (i < g.nx && j < g.ny) out[vidx(g, k, j, i)] = acc[0][e];
-                }
-            } else {
-                __syncthreads();
-                fill_x_tile(X, s.x, g, k, x0, y0);
-                __syncthreads();
-#pragma unroll
-                for (int e = 0; e < ROWS_PER_THREAD; ++e) {
-                    const int lj = ty + (NT / TX) * e, li = tx;
-                    const int j = y0 + lj, i = x0 + li;
-                    if (i >= g.nx || j >= g.ny) continue;
-                    const T *xc = X + (lj + 1) * XW + (li + 1);
-                    const T xv = xc[0];
-                    const bool lastx = (i == g.nx - 1), lasty = (j == g.ny - 1);
-                    // forward differences at (j,i), (j,i-1), (j-1,i)
-                    const T dxc = lastx ? T(0) : xc[1] - xv;
-                    const T dyc = lasty ? T(0) : xc[XW] - xv;
-                    const T wc = T(1) / sqrt(dxc * dxc + dyc * dyc + del2);
-                    T tv = -wc * (dxc + dyc);
-                    if (i >= 1) {
-                        const T dxl = xv - xc[-1];
-                        const T dyl = lasty ? T(0) : xc[XW - 1] - xc[-1];
-                        tv += dxl / sqrt(dxl * dxl + dyl * dyl + del2);
-                    }
-                    if (j >= 1) {
-                        const T dxu = lastx ? T(0) : xc[-XW + 1] - xc[-XW];
-                        const T dyu = xv - xc[-XW];
-                        tv += dyu / sqrt(dxu * dxu + dyu * dyu + del2);
-                    }
-                    const T box = xv - clampv(xv, lo, hi);
-                    T gv = acc[0][e] + lam * tv + eta2 * box;
-                    T dz = 0;
-                    if (prm.kappa != 0.0) {
-                        const size_t o = vidx(g, k, j, i);
-                        T zz = 0;
-                        if (k >= 1) zz += xv - s.x[o - S];
-                        if (k < g.nz - 1) {
-                            dz = s.x[o + S] - xv;
-                            zz -= dz;
-                        }
-                        gv += kap2 * zz;
-                    }
-                    const size_t o = vidx(g, k, j, i);
-                    if (mode == GM_BLOCK) {
-                        s.g[o] = gv;
-                        const double gd = (double)gv, dd = (double)dpv[o];
-                        qs[0] += gd * gd;
-                        qs[1] += gd * dd;
-                        qs[2] += dd * dd;
-                    } else if (mode == GM_GRAD) {
-                        out[o] = gv;
-                    } else {  // GM_EVAL: terms of f in double
-                        const double gd = (double)gv, rd = (double)rin[o];
-                        const double dxd = (double)dxc, dyd = (double)dyc, dzd = (double)dz;
-                        const double xd = (double)xv;
-                        const double bx = xd - (xd < prm.xmin ? prm.xmin : (xd > prm.xmax ? prm.xmax : xd));
-                        qs[0] += gd * gd;
-                        qs[1] += rd * rd;
-                        qs[2] += sqrt(dxd * dxd + dyd * dyd + prm.delta * prm.delta);
-                        qs[3] += bx * bx;
-                        qs[4] += dzd * dzd;
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < KZ - 1; ++q)
-#pragma unroll
-            for (int e = 0; e < ROWS_PER_THREAD; ++e) acc[q][e] = acc[q + 1][e];
-#pragma unroll
-        for (int e = 0; e < ROWS_PER_THREAD; ++e) acc[KZ - 1][e] = 0;
+        for (int qq = 0; qq < rx.E; ++qq) xr[qq] = rx.inb[qq] ? xs[rx.off[qq]] : T(0);
     }
-
-    if (mode == GM_BLOCK || mode == GM_EVAL) {
-        const size_t slot = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        if (mode == GM_BLOCK) {
-            double q3[3] = {qs[0], qs[1], qs[2]};
-            wg_reduce_store<3>(q3, red, partials + slot * NQ);
-        } else {
-            wg_reduce_store<NE>(qs, red, partials + slot * NE);
+    T ht[RPT];
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) ht[e] = 0;
+#pragma unroll
+    for (int c = -RZ; c <= RZ; ++c) {
+        const int m = k + c;
+        if (m < 0 || m >= g.nz) continue;
+        const T w = s.gz[(size_t)m * KZ + (c + RZ)];
+        const T *qm = q + (size_t)m * S;
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int j = y0 + out_row(e), i = x0 + tx;
+            if (i < g.nx && j < g.ny) ht[e] += w * qm[(size_t)j * g.nx + i];
         }
     }
-}
-
-// ---------------------------------------------------------------------------
-// Direction pass of a block S = [z0, z0+n): with d1 = -g and d2 = dp (both
-// zero outside S), H d1 and H d2 on output slices S +- r_z:
-//   (H d)_k = XY_k( sum_c gz_k[c] d_{k-c} )
-// and the sums <Hd_a, Hd_b>, sum_S w (VX d_a VX d_b + VY d_a VY d_b) and
-// <VZ d_a, VZ d_b> (a, b in {1, 2}) that fill the 2x2 majorant matrix.
-// ---------------------------------------------------------------------------
-template <typename T, int KZ>
-__global__ void __launch_bounds__(NT)
-k_dirs(Geom g, Params prm, DevState<T> s, const Segment *__restrict__ segs,
-       double *__restrict__ partials)
-{
-    constexpr int RZ = KZ / 2;
-    __shared__ T A1[LH * LW];
-    __shared__ T A2[LH * LW];
-    __shared__ T B1[LH * TX];
-    __shared__ T B2[LH * TX];
-    __shared__ double red[(NT / 64) * 9];
-
-    const Segment sg = segs[blockIdx.z];
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-    const int R = max(g.rx, g.ry);
-    const int kx = 2 * g.rx + 1, ky = 2 * g.ry + 1;
-    const size_t S = (size_t)g.nx * g.ny;
-    const T *__restrict__ gg = s.g;
-    const T *__restrict__ dpv = s.dp[sg.parity & 1];
-    const int z0 = sg.z0, z1 = sg.z0 + sg.n;
-    const double del2 = prm.delta * prm.delta;
-
-    double qs[9];
+    if (mode == GM_ZCOMB) {
 #pragma unroll
-    for (int v = 0; v < 9; ++v) qs[v] = 0.0;
-
-    const int kb = max(0, z0 - max(RZ, 1)), ke = min(g.nz, z1 + RZ);
-    for (int k = kb; k < ke; ++k) {
-        const T *wz = s.gz + (size_t)k * KZ;
-        __syncthreads();
-        {
-            const int w = TX + 2 * R, tot = w * (TY + 2 * R);
-            for (int e = threadIdx.x; e < tot; e += NT) {
-                const int jj = e / w, ii = e - jj * w;
-                const int j = y0 - R + jj, i = x0 - R + ii;
-                T v1 = 0, v2 = 0;
+        for (int e = 0; e < RPT; ++e) {
+            const int j = y0 + out_row(e), i = x0 + tx;
+            if (i < g.nx && j < g.ny) out[vidx(g, k, j, i)] = ht[e];
+        }
+        return;
+    }
+#pragma unroll
+    for (int qq = 0; qq < rx.E; ++qq)
+        if (rx.act[qq]) X[threadIdx.x + qq * NT] = xr[qq];
+    __syncthreads();
+    // w VX x and w VY x once per position (y0-1+jj, x0-1+ii), jj < TY+1,
+    // ii < TX+1; zero outside the slice
+    const T del2 = (T)(prm.delta * prm.delta);
+    {
+        constexpr int N = PW * PH, E = cdiv(N, NT);
+#pragma unroll
+        for (int qq = 0; qq < E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            if (e < N) {
+                const int jj = e / PW, ii = e - jj * PW;
+                const int j = y0 - 1 + jj, i = x0 - 1 + ii;
+                T px = 0, py = 0;
                 if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
-                    const size_t o = (size_t)j * g.nx + i;
-#pragma unroll
-                    for (int c = -RZ; c <= RZ; ++c) {
-                        const int sl = k - c;
-                        if (sl >= z0 && sl < z1) {
-                            const T wv = wz[c + RZ];
-                            v1 -= wv * gg[(size_t)sl * S + o];
-                            v2 += wv * dpv[(size_t)sl * S + o];
-                        }
-                    }
+                    const T *xc = X + jj * XW + ii;
+                    const T dxv = (i < g.nx - 1) ? xc[1] - xc[0] : T(0);
+                    const T dyv = (j < g.ny - 1) ? xc[XW] - xc[0] : T(0);
+                    const T w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
+                    px = w * dxv;
+                    py = w * dyv;
                 }
-                A1[jj * LW + ii] = v1;
-                A2[jj * LW + ii] = v2;
-            }
-        }
-        __syncthreads();
-        xpass<T, false>(A1, B1, s.gx + (size_t)k * kx, g.rx, g.ry, R);
-        xpass<T, false>(A2, B2, s.gx + (size_t)k * kx, g.rx, g.ry, R);
-        __syncthreads();
-        T h1[ROWS_PER_THREAD], h2[ROWS_PER_THREAD];
-        ypass<T, false>(B1, h1, s.gy + (size_t)k * ky, g.ry);
-        ypass<T, false>(B2, h2, s.gy + (size_t)k * ky, g.ry);
-        const bool ink = (k >= z0 && k < z1);
-        const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
-#pragma unroll
-        for (int e = 0; e < ROWS_PER_THREAD; ++e) {
-            const int j = y0 + ty + (NT / TX) * e, i = x0 + tx;
-            if (i >= g.nx || j >= g.ny) continue;
-            const double a = (double)h1[e], b = (double)h2[e];
-            qs[0] += a * a;
-            qs[1] += a * b;
-            qs[2] += b * b;
-            const size_t o = vidx(g, k, j, i);
-            if (ink) {
-                const bool lastx = (i == g.nx - 1), lasty = (j == g.ny - 1);
-                const double xv = (double)s.x[o];
-                const double dxx = lastx ? 0.0 : (double)s.x[o + 1] - xv;
-                const double dyx = lasty ? 0.0 : (double)s.x[o + g.nx] - xv;
-                const double w = 1.0 / sqrt(dxx * dxx + dyx * dyx + del2);
-                const double g0 = (double)gg[o], p0 = (double)dpv[o];
-                const double dx1 = lastx ? 0.0 : g0 - (double)gg[o + 1];
-                const double dy1 = lasty ? 0.0 : g0 - (double)gg[o + g.nx];
-                const double dx2 = lastx ? 0.0 : (double)dpv[o + 1] - p0;
-                const double dy2 = lasty ? 0.0 : (double)dpv[o + g.nx] - p0;
-                qs[3] += w * (dx1 * dx1 + dy1 * dy1);
-                qs[4] += w * (dx1 * dx2 + dy1 * dy2);
-                qs[5] += w * (dx2 * dx2 + dy2 * dy2);
-            }
-            if (zterm) {
-                // VZ d at slice k: d_{k+1} - d_k with d zero outside S
-                double z1v = 0.0, z2v = 0.0;
-                if (k + 1 >= z0 && k + 1 < z1) {
-                    z1v -= (double)gg[o + S];
-                    z2v += (double)dpv[o + S];
-                }
-                if (ink) {
-                    z1v += (double)gg[o];
-                    z2v -= (double)dpv[o];
-                }
-                qs[6] += z1v * z1v;
-                qs[7] += z1v * z2v;
-                qs[8] += z2v * z2v;
+                PX[e] = px;
+                PY[e] = py;
             }
         }
     }
-    const size_t slot = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    wg_reduce_store<9>(qs, red, partials + slot * NQ + 3);
+    __syncthreads();
+
+    const T lam = (T)prm.lambda, eta2 = (T)(2.0 * prm.eta), kap2 = (T)(2.0 * prm.kappa),
+            lo = (T)prm.xmin, hi = (T)prm.xmax;
+    const T *dpv = s.dp[0];
+    double qs[NQE] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int lj = out_row(e), li = tx;
+        const int j = y0 + lj, i = x0 + li;
+        if (i >= g.nx || j >= g.ny) continue;
+        const T *xc = X + (lj + 1) * XW + (li + 1);
+        const T xv = xc[0];
+        // VX^T(w VX x) + VY^T(w VY x) at (j, i); P is zero outside the slice
+        const int pc = (lj + 1) * PW + (li + 1);
+        const T tv = PX[pc - 1] - PX[pc] + PY[pc - PW] - PY[pc];
+        const T box = xv - clampv(xv, lo, hi);
+        T gv = ht[e] + lam * tv + eta2 * box;
+        const size_t o = vidx(g, k, j, i);
+        T dz = 0;
+        if (prm.kappa != 0.0) {
+            T zz = 0;
+            if (k >= 1) zz += xv - x[o - S];
+            if (k < g.nz - 1) {
+                dz = x[o + S] - xv;
+                zz -= dz;
+            }
+            gv += kap2 * zz;
+        }
+        if (mode == GM_BLOCK) {
+            s.g[o] = gv;
+            const double gd = (double)gv, dd = (double)dpv[o];
+            qs[0] += gd * gd;
+            qs[1] += gd * dd;
+            qs[2] += dd * dd;
+        } else if (mode == GM_GRAD) {
+            out[o] = gv;
+        } else {  // GM_EVAL: terms of f in double
+            const double xd = (double)xv;
+            const double dxd = (i < g.nx - 1) ? (double)xc[1] - xd : 0.0;
+            const double dyd = (j < g.ny - 1) ? (double)xc[XW] - xd : 0.0;
+            const double dzd = (double)dz;
+            const double bx = xd - (xd < prm.xmin ? prm.xmin : (xd > prm.xmax ? prm.xmax : xd));
+            const double gd = (double)gv;
+            qs[0] += gd * gd;
+            qs[1] += sqrt(dxd * dxd + dyd * dyd + prm.delta * prm.delta);
+            qs[2] += bx * bx;
+            qs[3] += dzd * dzd;
+        }
+    }
+    if (mode == GM_BLOCK) {
+        double q3[NQG] = {qs[0], qs[1], qs[2]};
+        wg_reduce_store<NQG>(q3, red, partials + slot_of() * NQG);
+    } else if (mode == GM_EVAL) {
+        wg_reduce_store<NQE>(qs, red, partials + slot_of() * NQE);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Update pass of a block S: d' = u1 d1 + u2 d2 = -u1 g + u2 dp on S;
-// r += H d' on S +- r_z; x_S += d'; dp_out,S = d'.  The previous step is
-// read from dp[parity] and written to dp[parity ^ 1], so workgroups reading
-// a neighbour's halo never see a half-updated step.
+// Direction pass, one output slice k per item, for the block S = [z0, z0+n):
+// with d1 = -g and d2 = dp (zero outside S),
+//   (H d)_k = XY_k( sum_c gz_k[c] d_{k-c} ),
+// the sums <Hd_a, Hd_b>, and on S the curvature sums
+// sum w (VX d_a VX d_b + VY d_a VY d_b) and <VZ d_a, VZ d_b> (a, b in {1, 2}).
 // ---------------------------------------------------------------------------
-template <typename T, int KZ>
+template <typename T, int KZ, int R>
 __global__ void __launch_bounds__(NT)
-k_update(Geom g, DevState<T> s, const Segment *__restrict__ segs, const double *__restrict__ u)
+k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double *__restrict__ partials)
 {
-    constexpr int RZ = KZ / 2;
-    __shared__ T A[LH * LW];
-    __shared__ T B[LH * TX];
+    constexpr int RZ = KZ / 2, K = 2 * R + 1;
+    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    __shared__ T A1[W * H];
+    __shared__ T A2[W * H];
+    __shared__ T B1[TX * H];
+    __shared__ T B2[TX * H];
+    __shared__ double red[(NT / 64) * NQD];
 
-    const Segment sg = segs[blockIdx.z];
+    const Item it = items[blockIdx.z];
+    const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-    const int R = max(g.rx, g.ry);
-    const int kx = 2 * g.rx + 1, ky = 2 * g.ry + 1;
+    const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
-    const T u1 = (T)u[2 * sg.block], u2 = (T)u[2 * sg.block + 1];
     const T *__restrict__ gg = s.g;
-    const T *__restrict__ dpi = s.dp[sg.parity & 1];
-    T *__restrict__ dpo = s.dp[(sg.parity & 1) ^ 1];
-    const int z0 = sg.z0, z1 = sg.z0 + sg.n;
+    const T *__restrict__ dpv = s.dp[0];
+    const T *wz = s.gz + (size_t)k * KZ;
+    T wx[K], wy[K];
+    load_taps<T, R>(wx, s.gx + (size_t)k * K);
+    load_taps<T, R>(wy, s.gy + (size_t)k * K);
 
-    const int kb = max(0, z0 - RZ), ke = min(g.nz, z1 + RZ);
-    for (int k = kb; k < ke; ++k) {
-        const T *wz = s.gz + (size_t)k * KZ;
-        __syncthreads();
-        fill_halo(A, x0, y0, R, g, [&](int j, int i) {
-            const size_t o = (size_t)j * g.nx + i;
-            T v = 0;
+    // z-combine of d1 and d2 on the tile plus an R halo
+    Region<W, H, R, R> rg(g, x0, y0);
+    T v1[rg.E], v2[rg.E];
 #pragma unroll
-            for (int c = -RZ; c <= RZ; ++c) {
-                const int sl = k - c;
-                if (sl >= z0 && sl < z1) {
-                    const size_t q = (size_t)sl * S + o;
-                    const T d = u2 * dpi[q] - u1 * gg[q];
-                    v += wz[c + RZ] * d;
-                }
+    for (int qq = 0; qq < rg.E; ++qq) v1[qq] = v2[qq] = 0;
+#pragma unroll
+    for (int c = -RZ; c <= RZ; ++c) {
+        const int sl = k - c;
+        if (sl < z0 || sl >= z1) continue;
+        const T wv = wz[c + RZ];
+        const T *gs = gg + (size_t)sl * S, *ds = dpv + (size_t)sl * S;
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq)
+            if (rg.inb[qq]) {
+                v1[qq] -= wv * gs[rg.off[qq]];
+                v2[qq] += wv * ds[rg.off[qq]];
             }
-            return v;
-        });
-        __syncthreads();
-        xpass<T, false>(A, B, s.gx + (size_t)k * kx, g.rx, g.ry, R);
-        __syncthreads();
-        T h[ROWS_PER_THREAD];
-        ypass<T, false>(B, h, s.gy + (size_t)k * ky, g.ry);
+    }
 #pragma unroll
-        for (int e = 0; e < ROWS_PER_THREAD; ++e) {
-            const int j = y0 + ty + (NT / TX) * e, i = x0 + tx;
-            if (i < g.nx && j < g.ny) s.r[vidx(g, k, j, i)] += h[e];
+    for (int qq = 0; qq < rg.E; ++qq)
+        if (rg.act[qq]) {
+            A1[threadIdx.x + qq * NT] = v1[qq];
+            A2[threadIdx.x + qq * NT] = v2[qq];
+        }
+    __syncthreads();
+    xpass<T, R, W, TX, H, R, false>(A1, B1, wx);
+    xpass<T, R, W, TX, H, R, false>(A2, B2, wx);
+    __syncthreads();
+    T h1[RPT], h2[RPT];
+    ypass_out<T, R, TX, R, false>(B1, h1, wy);
+    ypass_out<T, R, TX, R, false>(B2, h2, wy);
+
+    double qs[NQD];
+#pragma unroll
+    for (int v = 0; v < NQD; ++v) qs[v] = 0.0;
+    const bool ink = (k >= z0 && k < z1);
+    const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
+    const T del2 = (T)(prm.delta * prm.delta);
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int j = y0 + out_row(e), i = x0 + tx;
+        if (i >= g.nx || j >= g.ny) continue;
+        const double a = (double)h1[e], b = (double)h2[e];
+        qs[0] += a * a;
+        qs[1] += a * b;
+        qs[2] += b * b;
+        const size_t o = vidx(g, k, j, i);
+        if (ink) {
+            const bool lastx = (i == g.nx - 1), lasty = (j == g.ny - 1);
+            const T xv = s.x[o];
+            const T dxx = lastx ? T(0) : s.x[o + 1] - xv;
+            const T dyx = lasty ? T(0) : s.x[o + g.nx] - xv;
+            const double w = (double)inv_sqrt(dxx * dxx + dyx * dyx + del2);
+            const double g0 = (double)gg[o], p0 = (double)dpv[o];
+            const double dx1 = lastx ? 0.0 : g0 - (double)gg[o + 1];
+            const double dy1 = lasty ? 0.0 : g0 - (double)gg[o + g.nx];
+            const double dx2 = lastx ? 0.0 : (double)dpv[o + 1] - p0;
+            const double dy2 = lasty ? 0.0 : (double)dpv[o + g.nx] - p0;
+            qs[3] += w * (dx1 * dx1 + dy1 * dy1);
+            qs[4] += w * (dx1 * dx2 + dy1 * dy2);
+            qs[5] += w * (dx2 * dx2 + dy2 * dy2);
+        }
+        if (zterm) {
+            // VZ d at slice k: d_{k+1} - d_k with d zero outside S
+            double z1v = 0.0, z2v = 0.0;
+            if (k + 1 >= z0 && k + 1 < z1) {
+                z1v -= (double)gg[o + S];
+                z2v += (double)dpv[o + S];
+            }
+            if (ink) {
+                z1v += (double)gg[o];
+                z2v -= (double)dpv[o];
+            }
+            qs[6] += z1v * z1v;
+            qs[7] += z1v * z2v;
+            qs[8] += z2v * z2v;
         }
     }
-    for (int k = z0; k < z1; ++k) {
-#pragma unroll
-        for (int e = 0; e < ROWS_PER_THREAD; ++e) {
-            const int j = y0 + ty + (NT / TX) * e, i = x0 + tx;
-            if (i >= g.nx || j >= g.ny) continue;
-            const size_t q = vidx(g, k, j, i);
-            const T d = u2 * dpi[q] - u1 * gg[q];
-            s.x[q] += d;
-            dpo[q] = d;
-        }
-    }
+    wg_reduce_store<NQD>(qs, red, partials + slot_of() * NQD);
 }
 
 // ---------------------------------------------------------------------------
-// out = H(in) - sub on the slices of each segment (sub may be null).
+// Update pass, one slice m per item.
+// UM_UPDATE (block S = [z0, z0+n), step coefficients u of the block):
+//   d' = -u1 g + u2 dp on S;  q_m += XY^T_m (H d')_m  (m in S +- r_z);
+//   and for m in S: x_m += d'_m, dp[1]_m = d'_m.
+// UM_REFRESH: q_m = XY^T_m (H src - y)_m.
+// (H v)_m is formed on the tile plus an R halo (z-combine on a 2R halo, x and
+// y passes), zeroed outside the slice (the adjoint blur sees zero padding),
+// then blurred back by the adjoint x and y passes of slice m.  Previous steps
+// are read from dp[0] and written to dp[1], so a workgroup reading its
+// neighbours' halo never sees a half-updated step.
 // ---------------------------------------------------------------------------
-template <typename T, int KZ>
+template <typename T, int KZ, int R>
 __global__ void __launch_bounds__(NT)
-k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub,
-    T *__restrict__ out, const Segment *__restrict__ segs)
+k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
+         const Item *__restrict__ items, const double *__restrict__ u, int mode)
 {
-    constexpr int RZ = KZ / 2;
-    __shared__ T A[LH * LW];
-    __shared__ T B[LH * TX];
-    const Segment sg = segs[blockIdx.z];
+    constexpr int RZ = KZ / 2, K = 2 * R + 1;
+    constexpr int W1 = TX + 4 * R, H1 = TY + 4 * R;  // z-combined source, 2R halo
+    constexpr int W2 = TX + 2 * R, H2 = TY + 2 * R;  // H v, R halo
+    __shared__ T A[W1 * H1];                         // z-combined source, later H v
+    __shared__ T B[W2 * H1];                         // forward x pass, later adjoint x pass
+
+    const Item it = items[blockIdx.z];
+    const int m = it.k, z0 = it.z0, z1 = it.z0 + it.n;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int tx = threadIdx.x & (TX - 1), ty = threadIdx.x / TX;
-    const int R = max(g.rx, g.ry);
-    const int kx = 2 * g.rx + 1, ky = 2 * g.ry + 1;
+    const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
-    for (int k = sg.z0; k < sg.z0 + sg.n; ++k) {
-        const T *wz = s.gz + (size_t)k * KZ;
-        __syncthreads();
-        fill_halo(A, x0, y0, R, g, [&](int j, int i) {
-            const size_t o = (size_t)j * g.nx + i;
-            T v = 0;
+    const T *wz = s.gz + (size_t)m * KZ;
+    T wx[K], wy[K];
+    load_taps<T, R>(wx, s.gx + (size_t)m * K);
+    load_taps<T, R>(wy, s.gy + (size_t)m * K);
+    const bool upd = (mode == UM_UPDATE);
+    T u1 = 0, u2 = 0;
+    if (upd) {
+        u1 = (T)u[2 * it.block];
+        u2 = (T)u[2 * it.block + 1];
+    }
+    const T *__restrict__ gg = s.g;
+    const T *__restrict__ dpi = s.dp[0];
+
+    // 1. z-combine of the source on the tile plus a 2R halo
+    {
+        Region<W1, H1, 2 * R, 2 * R> rg(g, x0, y0);
+        T v[rg.E];
 #pragma unroll
-            for (int c = -RZ; c <= RZ; ++c) {
-                const int sl = k - c;
-                if (sl >= 0 && sl < g.nz) v += wz[c + RZ] * in[(size_t)sl * S + o];
-            }
-            return v;
-        });
-        __syncthreads();
-        xpass<T, false>(A, B, s.gx + (size_t)k * kx, g.rx, g.ry, R);
-        __syncthreads();
-        T h[ROWS_PER_THREAD];
-        ypass<T, false>(B, h, s.gy + (size_t)k * ky, g.ry);
+        for (int qq = 0; qq < rg.E; ++qq) v[qq] = 0;
 #pragma unroll
-        for (int e = 0; e < ROWS_PER_THREAD; ++e) {
-            const int j = y0 + ty + (NT / TX) * e, i = x0 + tx;
-            if (i < g.nx && j < g.ny) {
-                const size_t o = vidx(g, k, j, i);
-                out[o] = sub ? h[e] - sub[o] : h[e];
+        for (int c = -RZ; c <= RZ; ++c) {
+            const int sl = m - c;
+            const T wv = wz[c + RZ];
+            if (upd) {
+                if (sl < z0 || sl >= z1) continue;
+                const T *gs = gg + (size_t)sl * S, *ds = dpi + (size_t)sl * S;
+#pragma unroll
+                for (int qq = 0; qq < rg.E; ++qq)
+                    if (rg.inb[qq]) v[qq] += wv * (u2 * ds[rg.off[qq]] - u1 * gs[rg.off[qq]]);
+            } else {
+                if (sl < 0 || sl >= g.nz) continue;
+                const T *ss = src + (size_t)sl * S;
+#pragma unroll
+                for (int qq = 0; qq < rg.E; ++qq)
+                    if (rg.inb[qq]) v[qq] += wv * ss[rg.off[qq]];
             }
+        }
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq)
+            if (rg.act[qq]) A[threadIdx.x + qq * NT] = v[qq];
+    }
+    // the data term of a refresh is needed on the R halo; load it early
+    Region<W2, H2, R, R> r2(g, x0, y0);
+    T yv[r2.E];
+    if (!upd) {
+        const T *ys = s.y + (size_t)m * S;
+#pragma unroll
+        for (int qq = 0; qq < r2.E; ++qq) yv[qq] = r2.inb[qq] ? ys[r2.off[qq]] : T(0);
+    }
+    __syncthreads();
+    // 2. forward x pass: all H1 rows, the W2 columns of the R-halo tile
+    xpass<T, R, W1, W2, H1, R, false>(A, B, wx);
+    __syncthreads();
+    // 3. forward y pass on the R-halo tile into A (H v), zero outside the slice
+#pragma unroll
+    for (int qq = 0; qq < r2.E; ++qq) {
+        if (!r2.act[qq]) continue;
+        const int e = threadIdx.x + qq * NT;
+        const int r = e / W2, c = e - r * W2;
+        T acc = 0;
+        if (r2.inb[qq]) {
+            const T *col = B + (r + R) * W2 + c;
+#pragma unroll
+            for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[-b * W2];
+            if (!upd) acc -= yv[qq];
+        }
+        A[e] = acc;
+    }
+    __syncthreads();
+    // 4. adjoint x pass over the R-halo rows into B
+    xpass<T, R, W2, TX, H2, R, true>(A, B, wx);
+    __syncthreads();
+    // 5. adjoint y pass into registers
+    T v[RPT];
+    ypass_out<T, R, TX, R, true>(B, v, wy);
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int j = y0 + out_row(e), i = x0 + tx;
+        if (i >= g.nx || j >= g.ny) continue;
+        const size_t o = vidx(g, m, j, i);
+        if (upd) {
+            qout[o] += v[e];
+            if (m >= z0 && m < z1) {
+                const T d = u2 * dpi[o] - u1 * gg[o];
+                s.x[o] += d;
+                s.dp[1][o] = d;
+            }
+        } else {
+            qout[o] = v[e];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Per block: fixed-order reduction of its slots, then the 2x2 system of the
-// memory-gradient subspace (Sec. 2.3, eq. "minimizer"):
+// out_k = (H in)_k - sub_k per item; optional per-slot sums of out^2.
+// ---------------------------------------------------------------------------
+template <typename T, int KZ, int R>
+__global__ void __launch_bounds__(NT)
+k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, T *__restrict__ out,
+    const Item *__restrict__ items, double *__restrict__ partials)
+{
+    constexpr int RZ = KZ / 2, K = 2 * R + 1;
+    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    __shared__ T A[W * H];
+    __shared__ T B[TX * H];
+    __shared__ double red[NT / 64];
+    const Item it = items[blockIdx.z];
+    const int k = it.k;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int tx = threadIdx.x & (TX - 1);
+    const size_t S = (size_t)g.nx * g.ny;
+    const T *wz = s.gz + (size_t)k * KZ;
+    T wx[K], wy[K];
+    load_taps<T, R>(wx, s.gx + (size_t)k * K);
+    load_taps<T, R>(wy, s.gy + (size_t)k * K);
+    {
+        Region<W, H, R, R> rg(g, x0, y0);
+        T v[rg.E];
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) v[qq] = 0;
+#pragma unroll
+        for (int c = -RZ; c <= RZ; ++c) {
+            const int sl = k - c;
+            if (sl < 0 || sl >= g.nz) continue;
+            const T wv = wz[c + RZ];
+            const T *ss = in + (size_t)sl * S;
+#pragma unroll
+            for (int qq = 0; qq < rg.E; ++qq)
+                if (rg.inb[qq]) v[qq] += wv * ss[rg.off[qq]];
+        }
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq)
+            if (rg.act[qq]) A[threadIdx.x + qq * NT] = v[qq];
+    }
+    __syncthreads();
+    xpass<T, R, W, TX, H, R, false>(A, B, wx);
+    __syncthreads();
+    T h[RPT];
+    ypass_out<T, R, TX, R, false>(B, h, wy);
+    double ss[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int j = y0 + out_row(e), i = x0 + tx;
+        if (i < g.nx && j < g.ny) {
+            const size_t o = vidx(g, k, j, i);
+            const T v = sub ? h[e] - sub[o] : h[e];
+            out[o] = v;
+            ss[0] += (double)v * (double)v;
+        }
+    }
+    if (partials) wg_reduce_store<1>(ss, red, partials + slot_of());
+}
+
+// ---------------------------------------------------------------------------
+// out_m = XY^T_m in_m per item (adjoint in-slice blur with slice m's factors).
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__global__ void __launch_bounds__(NT)
+k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
+        const Item *__restrict__ items)
+{
+    constexpr int K = 2 * R + 1;
+    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    __shared__ T A[W * H];
+    __shared__ T B[TX * H];
+    const Item it = items[blockIdx.z];
+    const int m = it.k;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int tx = threadIdx.x & (TX - 1);
+    T wx[K], wy[K];
+    load_taps<T, R>(wx, s.gx + (size_t)m * K);
+    load_taps<T, R>(wy, s.gy + (size_t)m * K);
+    {
+        Region<W, H, R, R> rg(g, x0, y0);
+        const T *im = in + (size_t)m * g.nx * g.ny;
+        T v[rg.E];
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) v[qq] = rg.inb[qq] ? im[rg.off[qq]] : T(0);
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq)
+            if (rg.act[qq]) A[threadIdx.x + qq * NT] = v[qq];
+    }
+    __syncthreads();
+    xpass<T, R, W, TX, H, R, true>(A, B, wx);
+    __syncthreads();
+    T v[RPT];
+    ypass_out<T, R, TX, R, true>(B, v, wy);
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int j = y0 + out_row(e), i = x0 + tx;
+        if (i < g.nx && j < g.ny) out[vidx(g, m, j, i)] = v[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per block: fixed-order reduction of its gradient and direction slots, then
+// the 2x2 system of the memory-gradient subspace (Sec. 2.3, eq. "minimizer"):
 //   B = D^T A_S D with D = [d1 | d2], d1 = -g, d2 = dp,
 //   c = D^T g = (-<g,g>, <dp,g>),  u = -B^+ c.
 // B^+ is the exact inverse when det > 1e-12 B11 B22, else the rank-one
 // pseudo-inverse B / tr(B)^2 (zero when tr(B) = 0).
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT)
-k_solve(Params prm, const Segment *__restrict__ segs, int slots, const double *__restrict__ partials,
-        double *__restrict__ u, double *__restrict__ info)
+k_solve(Params prm, const BlockRange *__restrict__ brs, int ntiles, const double *__restrict__ pg,
+        const double *__restrict__ pd, double *__restrict__ u, double *__restrict__ info)
 {
-    __shared__ double red[NT];
-    __shared__ double tot[NQ];
-    const Segment sg = segs[blockIdx.x];
-    const double *p = partials + (size_t)blockIdx.x * slots * NQ;
-    for (int v = 0; v < NQ; ++v) {
-        double s = 0.0;
-        for (int t = threadIdx.x; t < slots; t += NT) s += p[(size_t)t * NQ + v];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = NT / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) tot[v] = red[0];
-        __syncthreads();
+    constexpr int NV = NQG + NQD;
+    __shared__ double red[NT / 64][NV];
+    __shared__ double tot[NV];
+    const BlockRange br = brs[blockIdx.x];
+    // each thread sums its slots in order, then one tree over the threads
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    {
+        const double *p = pg + (size_t)br.g0 * ntiles * NQG;
+        const int n = br.gn * ntiles;
+        for (int t = threadIdx.x; t < n; t += NT)
+#pragma unroll
+            for (int v = 0; v < NQG; ++v) acc[v] += p[(size_t)t * NQG + v];
     }
+    {
+        const double *p = pd + (size_t)br.d0 * ntiles * NQD;
+        const int n = br.dn * ntiles;
+        for (int t = threadIdx.x; t < n; t += NT)
+#pragma unroll
+            for (int v = 0; v < NQD; ++v) acc[NQG + v] += p[(size_t)t * NQD + v];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double sv = acc[v];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sv += __shfl_down(sv, off, 64);
+        if (lane == 0) red[wave][v] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double sv = 0.0;
+        for (int w = 0; w < NT / 64; ++w) sv += red[w][threadIdx.x];
+        tot[threadIdx.x] = sv;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
         const double gg = tot[0], gd = tot[1], dd = tot[2];
+        const double *h = tot + NQG;
         const double e2 = 2.0 * prm.eta, k2 = 2.0 * prm.kappa, lam = prm.lambda;
-        const double b11 = tot[3] + e2 * gg + lam * tot[6] + k2 * tot[9];
-        const double b12 = tot[4] - e2 * gd + lam * tot[7] + k2 * tot[10];
-        const double b22 = tot[5] + e2 * dd + lam * tot[8] + k2 * tot[11];
+        const double b11 = h[0] + e2 * gg + lam * h[3] + k2 * h[6];
+        const double b12 = h[1] - e2 * gd + lam * h[4] + k2 * h[7];
+        const double b22 = h[2] + e2 * dd + lam * h[5] + k2 * h[8];
         const double c1 = -gg, c2 = gd;
         const double det = b11 * b22 - b12 * b12, tr = b11 + b22;
         double p11, p12, p22;
@@ -542,23 +698,23 @@ k_solve(Params prm, const Segment *__restrict__ segs, int slots, const double *_
         }
         const double u1 = -(p11 * c1 + p12 * c2);
         const double u2 = -(p12 * c1 + p22 * c2);
-        u[2 * sg.block] = u1;
-        u[2 * sg.block + 1] = u2;
+        u[2 * br.block] = u1;
+        u[2 * br.block + 1] = u2;
         if (info) {
-            double *o = info + 8 * sg.block;
+            double *o = info + 8 * br.block;
             o[0] = b11; o[1] = b12; o[2] = b22; o[3] = c1; o[4] = c2; o[5] = u1; o[6] = u2; o[7] = gg;
         }
     }
 }
 
 __global__ void __launch_bounds__(NT)
-k_sum_eval(const double *__restrict__ partials, int nslot, double *__restrict__ out)
+k_sum(const double *__restrict__ partials, int nslot, int nq, double *__restrict__ out)
 {
     __shared__ double red[NT];
-    for (int v = 0; v < NE; ++v) {
-        double s = 0.0;
-        for (int t = threadIdx.x; t < nslot; t += NT) s += partials[(size_t)t * NE + v];
-        red[threadIdx.x] = s;
+    for (int v = 0; v < nq; ++v) {
+        double sv = 0.0;
+        for (int t = threadIdx.x; t < nslot; t += NT) sv += partials[(size_t)t * nq + v];
+        red[threadIdx.x] = sv;
         __syncthreads();
         for (int w = NT / 2; w > 0; w >>= 1) {
             if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
@@ -569,87 +725,104 @@ k_sum_eval(const double *__restrict__ partials, int nslot, double *__restrict__ 
     }
 }
 
-// ---------------------------------------------------------------------------
-// Launchers: dispatch on the z extent of the PSF (a template parameter so the
-// ring and the z-combine unroll).
-// ---------------------------------------------------------------------------
-#define BD3MG_KZ_SWITCH(kz, CALL)          \
-    switch (kz) {                          \
-    case 1: { constexpr int KZ = 1; CALL; } break; \
-    case 3: { constexpr int KZ = 3; CALL; } break; \
-    case 5: { constexpr int KZ = 5; CALL; } break; \
-    case 7: { constexpr int KZ = 7; CALL; } break; \
-    case 9: { constexpr int KZ = 9; CALL; } break; \
-    default: return hipErrorInvalidValue;  \
-    }
-
-static dim3 grid_of(const Geom &g, int nseg) { return dim3(g.ntx, g.nty, nseg); }
-
-template <typename T>
-hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *rin, T *out,
-                       const Segment *segs, int nseg, int mode, double *partials, hipStream_t st)
-{
-    if (nseg <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                    hipLaunchKernelGGL((k_grad<T, KZ>), grid_of(g, nseg), dim3(NT), 0, st, g, prm,
-                                       s, rin, out, segs, mode, partials));
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Segment *segs,
-                       int nseg, double *partials, hipStream_t st)
-{
-    if (nseg <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                    hipLaunchKernelGGL((k_dirs<T, KZ>), grid_of(g, nseg), dim3(NT), 0, st, g, prm,
-                                       s, segs, partials));
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_update(const Geom &g, const DevState<T> &s, const Segment *segs, int nseg,
-                         const double *u, hipStream_t st)
-{
-    if (nseg <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                    hipLaunchKernelGGL((k_update<T, KZ>), grid_of(g, nseg), dim3(NT), 0, st, g, s,
-                                       segs, u));
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_H(const Geom &g, const DevState<T> &s, const T *in, const T *sub, T *out,
-                    const Segment *segs, int nseg, hipStream_t st)
-{
-    if (nseg <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                    hipLaunchKernelGGL((k_H<T, KZ>), grid_of(g, nseg), dim3(NT), 0, st, g, s, in,
-                                       sub, out, segs));
-    return hipGetLastError();
-}
-
-hipError_t launch_solve(const Params &prm, const Segment *segs, int nseg, int slots_per_seg,
-                        const double *partials, double *u, double *info, hipStream_t st)
-{
-    if (nseg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_solve, dim3(nseg), dim3(NT), 0, st, prm, segs, slots_per_seg, partials, u,
-                       info);
-    return hipGetLastError();
-}
-
-hipError_t launch_sum_eval(const double *partials, int nslot, double *out, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_sum_eval, dim3(1), dim3(NT), 0, st, partials, nslot, out);
-    return hipGetLastError();
-}
-
 // Streaming copy, 16 bytes per lane per iteration, grid-stride.
 __global__ void __launch_bounds__(NT) k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                              size_t n)
 {
     const size_t stride = (size_t)gridDim.x * NT;
     for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers: dispatch on the z extent KZ and the in-slice radius R.
+// ---------------------------------------------------------------------------
+#define BD3MG_R_SWITCH(r, CALL)                   \
+    switch (r) {                                  \
+    case 1: { constexpr int R = 1; CALL; } break; \
+    case 2: { constexpr int R = 2; CALL; } break; \
+    case 3: { constexpr int R = 3; CALL; } break; \
+    case 4: { constexpr int R = 4; CALL; } break; \
+    default: return hipErrorInvalidValue;         \
+    }
+
+#define BD3MG_KZ_SWITCH(kz, CALL)                  \
+    switch (kz) {                                  \
+    case 1: { constexpr int KZ = 1; CALL; } break; \
+    case 3: { constexpr int KZ = 3; CALL; } break; \
+    case 5: { constexpr int KZ = 5; CALL; } break; \
+    case 7: { constexpr int KZ = 7; CALL; } break; \
+    case 9: { constexpr int KZ = 9; CALL; } break; \
+    default: return hipErrorInvalidValue;          \
+    }
+
+static dim3 grid_of(const Geom &g, int nitems) { return dim3(g.ntx, g.nty, nitems); }
+
+template <typename T>
+hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *q, const T *x,
+                       T *out, const Item *items, int nitems, int mode, double *partials, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_KZ_SWITCH(2 * g.rz + 1,
+                    hipLaunchKernelGGL((k_grad<T, KZ>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
+                                       s, q, x, out, items, mode, partials));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
+                       int nitems, double *partials, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R,
+                    hipLaunchKernelGGL((k_dirs<T, KZ, R>), grid_of(g, nitems), dim3(NT), 0, st, g,
+                                       prm, s, items, partials)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_update(const Geom &g, const DevState<T> &s, const T *src, T *qout, const Item *items,
+                         int nitems, const double *u, int mode, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R,
+                    hipLaunchKernelGGL((k_update<T, KZ, R>), grid_of(g, nitems), dim3(NT), 0, st, g,
+                                       s, src, qout, items, u, mode)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_H(const Geom &g, const DevState<T> &s, const T *in, const T *sub, T *out,
+                    const Item *items, int nitems, double *partials, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R,
+                    hipLaunchKernelGGL((k_H<T, KZ, R>), grid_of(g, nitems), dim3(NT), 0, st, g, s,
+                                       in, sub, out, items, partials)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out, const Item *items,
+                        int nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_R_SWITCH(g.R, hipLaunchKernelGGL((k_blurT<T, R>), grid_of(g, nitems), dim3(NT), 0, st, g,
+                                           s, in, out, items));
+    return hipGetLastError();
+}
+
+hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles, const double *pg,
+                        const double *pd, double *u, double *info, hipStream_t st)
+{
+    if (nbr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_solve, dim3(nbr), dim3(NT), 0, st, prm, br, ntiles, pg, pd, u, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum(const double *partials, int nslot, int nq, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(NT), 0, st, partials, nslot, nq, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
@@ -659,16 +832,18 @@ hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
     return hipGetLastError();
 }
 
-#define BD3MG_INSTANTIATE(T)                                                                     \
-    template hipError_t launch_grad<T>(const Geom &, const Params &, const DevState<T> &,         \
-                                       const T *, T *, const Segment *, int, int, double *,      \
-                                       hipStream_t);                                             \
-    template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,         \
-                                       const Segment *, int, double *, hipStream_t);             \
-    template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Segment *, int, \
-                                         const double *, hipStream_t);                           \
-    template hipError_t launch_H<T>(const Geom &, const DevState<T> &, const T *, const T *, T *, \
-                                    const Segment *, int, hipStream_t);
+#define BD3MG_INSTANTIATE(T)                                                                      \
+    template hipError_t launch_grad<T>(const Geom &, const Params &, const DevState<T> &,          \
+                                       const T *, const T *, T *, const Item *, int, int,         \
+                                       double *, hipStream_t);                                    \
+    template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
+                                       const Item *, int, double *, hipStream_t);                 \
+    template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const T *, T *,        \
+                                         const Item *, int, const double *, int, hipStream_t);    \
+    template hipError_t launch_H<T>(const Geom &, const DevState<T> &, const T *, const T *, T *,  \
+                                    const Item *, int, double *, hipStream_t);                    \
+    template hipError_t launch_blurT<T>(const Geom &, const DevState<T> &, const T *, T *,         \
+                                        const Item *, int, hipStream_t);
 
 BD3MG_INSTANTIATE(float)
 BD3MG_INSTANTIATE(double)
