@@ -92,6 +92,13 @@ struct bd3mg_problem_s {
     double *d_pg = nullptr, *d_pd = nullptr, *d_pe = nullptr, *d_pr = nullptr;
     size_t pg_cap = 0, pd_cap = 0;
     double *d_u = nullptr, *d_info = nullptr, *d_sum = nullptr;
+    // device stop test: {int stop, int stop_sweep, double gnorm}
+    struct Ctl {
+        int stop;
+        int stop_sweep;
+        double gnorm;
+    };
+    Ctl *d_ctl = nullptr;
     int nblocks_alloc = 0;
 
     double gnorm_ref = 0.0;
@@ -129,6 +136,7 @@ DevState<T> dev_state(bd3mg_problem p)
     s.gx = (const T *)p->d_gx;
     s.gy = (const T *)p->d_gy;
     s.gz = (const T *)p->d_gz;
+    s.stop = nullptr;
     return s;
 }
 
@@ -305,12 +313,12 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     for (char c : halo) h += c;
     // Algorithmic bytes (every element a pass must read or write counted once):
     // gradient pass reads q on S +- r_z and x, dp on S and writes g on S;
-    // direction pass reads g, dp and x on S; solve reads the partial sums;
+    // direction pass reads g and dp on S; solve reads the partial sums;
     // update pass reads g, dp, x on S and q on S +- r_z, writes x, dp on S and
     // q on S +- r_z.
     const double A = (double)p->nx * p->ny * p->esz;
     grp.bytes[0] = A * (h + 3.0 * sl);
-    grp.bytes[1] = A * 3.0 * sl;
+    grp.bytes[1] = A * 2.0 * sl;
     grp.bytes[2] = (double)(grp.g_cnt * NQG + grp.d_cnt * NQD) * p->ntiles * sizeof(double);
     grp.bytes[3] = A * (5.0 * sl + 2.0 * h);
 }
@@ -370,19 +378,39 @@ bd3mg_status build_schedule(bd3mg_problem p)
     return BD3MG_OK;
 }
 
-// q = XY^T (H src - y), slice by slice, into qout.
+// q = XY^T (H src - y), slice by slice, into qout (skipped once *stop is set).
 template <typename T>
-bd3mg_status refresh_t(bd3mg_problem p, const T *src, T *qout)
+bd3mg_status refresh_t(bd3mg_problem p, const T *src, T *qout, const int *stop)
 {
     DevState<T> s = dev_state<T>(p);
+    s.stop = stop;
     HIP_TRY(launch_update<T>(p->geom, s, src, qout, p->d_vol, p->nz, nullptr, UM_REFRESH, p->stream));
     return BD3MG_OK;
 }
 
-bd3mg_status refresh(bd3mg_problem p, const void *src, void *qout)
+bd3mg_status refresh(bd3mg_problem p, const void *src, void *qout, const int *stop = nullptr)
 {
-    return p->prec == BD3MG_FP64 ? refresh_t<double>(p, (const double *)src, (double *)qout)
-                                 : refresh_t<float>(p, (const float *)src, (float *)qout);
+    return p->prec == BD3MG_FP64 ? refresh_t<double>(p, (const double *)src, (double *)qout, stop)
+                                 : refresh_t<float>(p, (const float *)src, (float *)qout, stop);
+}
+
+// Enqueue the stop test: evaluation pass of ||grad f|| from q, then k_check
+// (threshold thr; thr < 0 only records the norm).  No host synchronisation.
+template <typename T>
+bd3mg_status check_t(bd3mg_problem p, double thr, int sweep, int *stop)
+{
+    DevState<T> s = dev_state<T>(p);
+    s.stop = stop;
+    HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.q, s.x, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe,
+                           p->stream));
+    HIP_TRY(launch_check(p->d_pe, p->ntiles * p->nz, thr, sweep, &p->d_ctl->stop, &p->d_ctl->stop_sweep,
+                         &p->d_ctl->gnorm, p->stream));
+    return BD3MG_OK;
+}
+
+bd3mg_status check(bd3mg_problem p, double thr, int sweep, int *stop)
+{
+    return p->prec == BD3MG_FP64 ? check_t<double>(p, thr, sweep, stop) : check_t<float>(p, thr, sweep, stop);
 }
 
 // ||grad f(xin)|| from the blurred residual qin, and, when f is wanted, f(xin)
@@ -445,9 +473,10 @@ bd3mg_status ensure_ready(bd3mg_problem p)
 
 // Enqueue the passes of one launch group: gradient, direction, solve, update.
 template <typename T>
-bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof)
+bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof, const int *stop)
 {
     DevState<T> s = dev_state<T>(p);
+    s.stop = stop;
     const Item *it = p->d_items;
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_GRAD, gr.bytes[0]));
     HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK,
@@ -458,7 +487,7 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
     HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles, p->d_pg, p->d_pd, p->d_u,
-                         p->d_info, p->stream));
+                         p->d_info, stop, p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
     HIP_TRY(launch_update<T>(p->geom, s, nullptr, s.q, it + gr.u_off, gr.u_cnt, p->d_u, UM_UPDATE,
@@ -467,9 +496,11 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
     return BD3MG_OK;
 }
 
-bd3mg_status phase(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof)
+bd3mg_status phase(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof,
+                   const int *stop = nullptr)
 {
-    return p->prec == BD3MG_FP64 ? phase_t<double>(p, gr, prof) : phase_t<float>(p, gr, prof);
+    return p->prec == BD3MG_FP64 ? phase_t<double>(p, gr, prof, stop)
+                                 : phase_t<float>(p, gr, prof, stop);
 }
 
 // One operator of the criterion on ti into to (tr: scratch), with the
@@ -566,7 +597,8 @@ bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *
     if (hipMalloc(&p->d_vol, vol.size() * sizeof(Item)) != hipSuccess ||
         hipMalloc(&p->d_pe, nslot * NQE * sizeof(double)) != hipSuccess ||
         hipMalloc(&p->d_pr, nslot * sizeof(double)) != hipSuccess ||
-        hipMalloc(&p->d_sum, (NQE + 1) * sizeof(double)) != hipSuccess)
+        hipMalloc(&p->d_sum, (NQE + 1) * sizeof(double)) != hipSuccess ||
+        hipMalloc(&p->d_ctl, sizeof(bd3mg_problem_s::Ctl)) != hipSuccess)
         return bail(BD3MG_ERR_NOMEM, "tables");
     if (hipMemcpy(p->d_vol, vol.data(), vol.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess)
         return bail(BD3MG_ERR_HIP, "item upload failed");
@@ -581,7 +613,7 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2],
                     p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_pg, p->d_pd,
-                    p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum};
+                    p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &q : p->pending) {
@@ -747,33 +779,52 @@ bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int ch
     if (grad_rtol > 0.0 && check_every == 0) check_every = max_sweeps > 0 ? max_sweeps : 1;
     ST_TRY(ensure_ready(p));
     const double vol = (double)p->N * p->esz;
+    // The stop test runs on the device: a check that meets the tolerance
+    // raises a flag and every later pass returns at entry, so the host only
+    // waits once per chunk of sweeps.
+    constexpr int CHUNK = 16;
+    const bool stopping = grad_rtol > 0.0;
+    int *stop = stopping ? &p->d_ctl->stop : nullptr;
+    const double thr = stopping ? grad_rtol * p->gnorm_ref : -1.0;
+    HIP_TRY(hipMemsetAsync(p->d_ctl, 0, sizeof(bd3mg_problem_s::Ctl), p->stream));
     HIP_TRY(hipEventRecord(p->ev0, p->stream));
-    int done = 0;
+    const int cur0 = p->cur;
+    const long long sweeps0 = p->sweeps_done;
+    int done = max_sweeps;
     bool conv = false;
-    double gn = NAN, f = NAN;
-    for (int s = 0; s < max_sweeps; ++s) {
-        for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile));
-        p->cur ^= 1;
-        ++done;
-        ++p->sweeps_done;
-        if (p->refresh_every > 0 && (p->sweeps_done % p->refresh_every) == 0) {
-            ST_TRY(prof_begin(p, BD3MG_K_EVAL, 3.0 * vol));
-            ST_TRY(refresh(p, p->x, p->q));
-            ST_TRY(prof_end(p));
+    bd3mg_problem_s::Ctl ctl{0, 0, NAN};
+    for (int s = 0; s < max_sweeps;) {
+        const int end = std::min(max_sweeps, s + CHUNK);
+        for (; s < end; ++s) {
+            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile, stop));
+            p->cur ^= 1;
+            const long long sw = sweeps0 + s + 1;
+            if (p->refresh_every > 0 && (sw % p->refresh_every) == 0) {
+                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 3.0 * vol));
+                ST_TRY(refresh(p, p->x, p->q, stop));
+                ST_TRY(prof_end(p));
+            }
+            if (checking && (((s + 1) % check_every) == 0 || s + 1 == max_sweeps)) {
+                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol));
+                ST_TRY(check(p, thr, s + 1, stop));
+                ST_TRY(prof_end(p));
+            }
         }
-        const bool last = (s == max_sweeps - 1);
-        if (checking && ((done % check_every) == 0 || last)) {
-            ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol));
-            ST_TRY(eval_at(p, p->x, p->q, nullptr, &gn));
-            ST_TRY(prof_end(p));
-            if (grad_rtol > 0.0 && gn <= grad_rtol * p->gnorm_ref) {
+        if (checking) {
+            HIP_TRY(hipMemcpyAsync(&ctl, p->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, p->stream));
+            HIP_TRY(hipStreamSynchronize(p->stream));
+            if (ctl.stop) {
+                done = ctl.stop_sweep;
                 conv = true;
                 break;
             }
         }
         if (p->pending.size() > 4096) ST_TRY(prof_collect(p));
     }
+    p->cur = cur0 ^ (done & 1);
+    p->sweeps_done = sweeps0 + done;
     HIP_TRY(hipEventRecord(p->ev1, p->stream));
+    double gn = ctl.gnorm, f = NAN;
     if (checking) ST_TRY(eval_at(p, p->x, p->q, &f, &gn));
     HIP_TRY(hipEventSynchronize(p->ev1));
     float ms = 0.f;

@@ -16,13 +16,13 @@ constexpr int NT = 256;     // threads per workgroup (4 wavefronts)
 constexpr int RMAX = 4;     // largest in-slice kernel radius (kernels up to 9 wide)
 constexpr int KZMAX = 9;    // largest kernel extent along z
 
-// Partial sums written per (work item, tile) slot.
+// Partial sums written per (work item, tile) slot, with d1 = -g, d2 = dp.
 //  gradient pass: 0 <g,g>  1 <g,dp>  2 <dp,dp>
-constexpr int NQG = 3;
+//                 3 sum w Dd1.Dd1  4 sum w Dd1.Dd2  5 sum w Dd2.Dd2
+constexpr int NQG = 6;
 //  direction pass: 0 <Hd1,Hd1> 1 <Hd1,Hd2> 2 <Hd2,Hd2>
-//                  3 sum w Dd1.Dd1  4 sum w Dd1.Dd2  5 sum w Dd2.Dd2
-//                  6 <VZd1,VZd1>  7 <VZd1,VZd2>  8 <VZd2,VZd2>
-constexpr int NQD = 9;
+//                  3 <VZd1,VZd1>  4 <VZd1,VZd2>  5 <VZd2,VZd2>
+constexpr int NQD = 6;
 //  evaluation: 0 ||g||^2  1 sum sqrt(|Dx|^2 + delta^2)  2 sum (x - clip x)^2  3 ||VZ x||^2
 constexpr int NQE = 4;
 
@@ -59,6 +59,7 @@ struct Geom {
 template <typename T>
 struct DevState {
     T *x, *y, *q, *g, *dp[2];  // dp[0]: previous steps read, dp[1]: written
+    const int *stop;           // when non-null and set, every pass returns at entry
     const T *gx, *gy;          // in-slice PSF tables [nz][2R + 1], centred, zero-padded
     const T *gz;               // z PSF table [nz][kz]
 };
@@ -103,7 +104,11 @@ hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out
 // majorant system, its pseudo-inverse and the step coefficients u.
 hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles,
                         const double *pg, const double *pd, double *u, double *info,
-                        hipStream_t st);
+                        const int *stop, hipStream_t st);
+
+// Device stop test after an evaluation pass (see k_check).
+hipError_t launch_check(const double *partials, int nslot, double thr, int sweep, int *stop,
+                        int *stop_sweep, double *gnorm, hipStream_t st);
 
 // Fixed-order sum of nslot slots of nq doubles into out[nq].
 hipError_t launch_sum(const double *partials, int nslot, int nq, double *out, hipStream_t st);

@@ -31,8 +31,6 @@ namespace bd3mg {
 namespace {
 
 constexpr int RPT = TY / (NT / TX);  // outputs (rows) per thread: 4
-constexpr int XW = TX + 2;           // iterate tile with a 1-voxel halo
-constexpr int XH = TY + 2;
 
 __device__ __forceinline__ size_t vidx(const Geom &g, int k, int j, int i)
 {
@@ -52,14 +50,17 @@ __device__ __forceinline__ int out_row(int e) { return (int)(threadIdx.x / TX) +
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // Element e = threadIdx.x + q NT of a W x H region whose corner is at global
-// (y0 - HY, x0 - HX): in-range flags and the in-slice offset j nx + i (valid
-// when inb).  Element e sits at LDS index e of a W-wide tile.
+// (y0 - HY, x0 - HX): the in-slice offset j nx + i of the element, or 0 (a
+// valid address) when it lies outside the slice or past the region, with a
+// flag.  Loads through off[] need no branch: the value is kept or zeroed by a
+// select.  Element e sits at index e of a W-wide LDS tile padded to E NT.
 template <int W, int H, int HX, int HY>
 struct Region {
     static constexpr int N = W * H;
     static constexpr int E = cdiv(N, NT);
+    static constexpr int PAD = E * NT;  // LDS elements to allocate
     int off[E];
-    bool act[E], inb[E];
+    bool inb[E];
     __device__ __forceinline__ Region(const Geom &g, int x0, int y0)
     {
 #pragma unroll
@@ -67,16 +68,20 @@ struct Region {
             const int e = threadIdx.x + q * NT;
             const int jj = e / W, ii = e - jj * W;
             const int j = y0 - HY + jj, i = x0 - HX + ii;
-            act[q] = e < N;
-            inb[q] = act[q] && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+            inb[q] = e < N && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
             off[q] = inb[q] ? j * g.nx + i : 0;
         }
     }
 };
 
-// x pass from I (rows of width WI) to O (rows of width WO), WO output columns
-// over ROWS rows:  forward O[r][c] = sum_a wx[a] I[r][c + OFF - a],
-//                  adjoint O[r][c] = sum_a wx[a] I[r][c + OFF + a].
+template <int W, int H>
+constexpr int padded() { return cdiv(W * H, NT) * NT; }
+
+// x pass from I (rows of width WI, at least ROWS rows) to O (rows of width WO,
+// padded to a multiple of NT), WO output columns over ROWS rows:
+//   forward O[r][c] = sum_a wx[a] I[r][c + OFF - a],
+//   adjoint O[r][c] = sum_a wx[a] I[r][c + OFF + a].
+// Elements past the last row recompute the last row into the padding.
 template <typename T, int R, int WI, int WO, int ROWS, int OFF, bool ADJ>
 __device__ __forceinline__ void xpass(const T *I, T *O, const T (&wx)[2 * R + 1])
 {
@@ -84,14 +89,14 @@ __device__ __forceinline__ void xpass(const T *I, T *O, const T (&wx)[2 * R + 1]
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int e = threadIdx.x + q * NT;
-        if (e < N) {
-            const int r = e / WO, c = e - r * WO;
-            const T *row = I + r * WI + c + OFF;
-            T acc = 0;
+        int r = e / WO;
+        const int c = e - r * WO;
+        if (q == E - 1) r = r < ROWS ? r : ROWS - 1;
+        const T *row = I + r * WI + c + OFF;
+        T acc = 0;
 #pragma unroll
-            for (int a = -R; a <= R; ++a) acc += wx[a + R] * row[ADJ ? a : -a];
-            O[e] = acc;
-        }
+        for (int a = -R; a <= R; ++a) acc += wx[a + R] * row[ADJ ? a : -a];
+        O[e] = acc;
     }
 }
 
@@ -151,39 +156,60 @@ __device__ __forceinline__ size_t slot_of()
 //   (H^T r)_k = sum_c gz_{k+c}[c] q_{k+c}
 //   g = H^T r + lambda (VX^T(w VX x) + VY^T(w VY x)) + 2 eta (x - clip x)
 //       + 2 kappa VZ^T VZ x,     w = 1 / sqrt((VX x)^2 + (VY x)^2 + delta^2)
-// GM_BLOCK writes g to s.g with <g,g>, <g,dp>, <dp,dp>; GM_GRAD writes g to
-// out; GM_EVAL sums ||g||^2 and the TV, box and z terms of f; GM_ZCOMB writes
-// only the z-stencil of q to out.
+// g is formed on the tile plus one column and one row beyond it, so the
+// curvature sums of the block's total-variation majorant, which need the
+// forward differences of g and dp, come out of the same workgroup.
+// GM_BLOCK writes g to s.g with <g,g>, <g,dp>, <dp,dp> and, with d1 = -g and
+// d2 = dp, sum w (VX d_a VX d_b + VY d_a VY d_b); GM_GRAD writes g to out;
+// GM_EVAL sums ||g||^2 and the TV, box and z terms of f; GM_ZCOMB writes only
+// the z-stencil of q to out.
 // ---------------------------------------------------------------------------
 template <typename T, int KZ>
 __global__ void __launch_bounds__(NT)
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials)
 {
+    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2;
-    constexpr int PW = TX + 1, PH = TY + 1;
-    __shared__ T X[XW * XH];
-    __shared__ T PX[PW * PH];
-    __shared__ T PY[PW * PH];
-    __shared__ double red[(NT / 64) * NQE];
+    constexpr int XW = TX + 3, XH = TY + 3;  // x at (y0-1+jj, x0-1+ii)
+    constexpr int PW = TX + 2, PH = TY + 2;  // w VX x, w VY x, w at (y0-1+jj, x0-1+ii)
+    constexpr int GW = TX + 1, GH = TY + 1;  // g, dp at (y0+jj, x0+ii)
+    __shared__ T X[padded<XW, XH>()];
+    __shared__ T PX[padded<PW, PH>()];
+    __shared__ T PY[padded<PW, PH>()];
+    __shared__ T WW[padded<PW, PH>()];
+    __shared__ T G[padded<GW, GH>()];
+    __shared__ T D[padded<GW, GH>()];
+    __shared__ double red[(NT / 64) * NQG];
 
     const Item it = items[blockIdx.z];
     const int k = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
+    const bool block = (mode == GM_BLOCK);
 
-    // iterate tile of slice k with a one-voxel halo, loads issued first
+    // loads first: x with its halo, q on the KZ slices, dp
     Region<XW, XH, 1, 1> rx(g, x0, y0);
-    T xr[rx.E];
+    Region<GW, GH, 0, 0> rg(g, x0, y0);
+    T xr[rx.E], ht[rg.E], dv[rg.E];
     if (mode != GM_ZCOMB) {
         const T *xs = x + (size_t)k * S;
 #pragma unroll
-        for (int qq = 0; qq < rx.E; ++qq) xr[qq] = rx.inb[qq] ? xs[rx.off[qq]] : T(0);
+        for (int qq = 0; qq < rx.E; ++qq) {
+            const T v = xs[rx.off[qq]];
+            xr[qq] = rx.inb[qq] ? v : T(0);
+        }
     }
-    T ht[RPT];
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) ht[e] = 0;
+    for (int qq = 0; qq < rg.E; ++qq) ht[qq] = dv[qq] = 0;
+    if (block) {
+        const T *ds = s.dp[0] + (size_t)k * S;
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const T v = ds[rg.off[qq]];
+            dv[qq] = rg.inb[qq] ? v : T(0);
+        }
+    }
 #pragma unroll
     for (int c = -RZ; c <= RZ; ++c) {
         const int m = k + c;
@@ -191,25 +217,21 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         const T w = s.gz[(size_t)m * KZ + (c + RZ)];
         const T *qm = q + (size_t)m * S;
 #pragma unroll
-        for (int e = 0; e < RPT; ++e) {
-            const int j = y0 + out_row(e), i = x0 + tx;
-            if (i < g.nx && j < g.ny) ht[e] += w * qm[(size_t)j * g.nx + i];
-        }
+        for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * qm[rg.off[qq]];
     }
     if (mode == GM_ZCOMB) {
 #pragma unroll
-        for (int e = 0; e < RPT; ++e) {
-            const int j = y0 + out_row(e), i = x0 + tx;
-            if (i < g.nx && j < g.ny) out[vidx(g, k, j, i)] = ht[e];
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            const int lj = e / GW, li = e - lj * GW;
+            if (rg.inb[qq] && lj < TY && li < TX) out[(size_t)k * S + rg.off[qq]] = ht[qq];
         }
         return;
     }
 #pragma unroll
-    for (int qq = 0; qq < rx.E; ++qq)
-        if (rx.act[qq]) X[threadIdx.x + qq * NT] = xr[qq];
+    for (int qq = 0; qq < rx.E; ++qq) X[threadIdx.x + qq * NT] = xr[qq];
     __syncthreads();
-    // w VX x and w VY x once per position (y0-1+jj, x0-1+ii), jj < TY+1,
-    // ii < TX+1; zero outside the slice
+    // w, w VX x and w VY x once per position; zero outside the slice
     const T del2 = (T)(prm.delta * prm.delta);
     {
         constexpr int N = PW * PH, E = cdiv(N, NT);
@@ -219,17 +241,18 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
             if (e < N) {
                 const int jj = e / PW, ii = e - jj * PW;
                 const int j = y0 - 1 + jj, i = x0 - 1 + ii;
-                T px = 0, py = 0;
+                T px = 0, py = 0, w = 0;
                 if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
                     const T *xc = X + jj * XW + ii;
                     const T dxv = (i < g.nx - 1) ? xc[1] - xc[0] : T(0);
                     const T dyv = (j < g.ny - 1) ? xc[XW] - xc[0] : T(0);
-                    const T w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
+                    w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
                     px = w * dxv;
                     py = w * dyv;
                 }
                 PX[e] = px;
                 PY[e] = py;
+                WW[e] = w;
             }
         }
     }
@@ -237,57 +260,83 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
 
     const T lam = (T)prm.lambda, eta2 = (T)(2.0 * prm.eta), kap2 = (T)(2.0 * prm.kappa),
             lo = (T)prm.xmin, hi = (T)prm.xmax;
-    const T *dpv = s.dp[0];
-    double qs[NQE] = {0.0, 0.0, 0.0, 0.0};
+    double qs[NQG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) {
-        const int lj = out_row(e), li = tx;
-        const int j = y0 + lj, i = x0 + li;
-        if (i >= g.nx || j >= g.ny) continue;
-        const T *xc = X + (lj + 1) * XW + (li + 1);
-        const T xv = xc[0];
-        // VX^T(w VX x) + VY^T(w VY x) at (j, i); P is zero outside the slice
-        const int pc = (lj + 1) * PW + (li + 1);
-        const T tv = PX[pc - 1] - PX[pc] + PY[pc - PW] - PY[pc];
-        const T box = xv - clampv(xv, lo, hi);
-        T gv = ht[e] + lam * tv + eta2 * box;
-        const size_t o = vidx(g, k, j, i);
-        T dz = 0;
-        if (prm.kappa != 0.0) {
-            T zz = 0;
-            if (k >= 1) zz += xv - x[o - S];
-            if (k < g.nz - 1) {
-                dz = x[o + S] - xv;
-                zz -= dz;
+    for (int qq = 0; qq < rg.E; ++qq) {
+        const int e = threadIdx.x + qq * NT;
+        const int lj = e / GW, li = e - lj * GW;
+        const bool interior = lj < TY && li < TX;
+        T gv = 0;
+        if (rg.inb[qq]) {
+            const int j = y0 + lj, i = x0 + li;
+            const T *xc = X + (lj + 1) * XW + (li + 1);
+            const T xv = xc[0];
+            // VX^T(w VX x) + VY^T(w VY x) at (j, i); P is zero outside the slice
+            const int pc = (lj + 1) * PW + (li + 1);
+            const T tv = PX[pc - 1] - PX[pc] + PY[pc - PW] - PY[pc];
+            const T box = xv - clampv(xv, lo, hi);
+            gv = ht[qq] + lam * tv + eta2 * box;
+            const size_t o = (size_t)k * S + rg.off[qq];
+            T dz = 0;
+            if (prm.kappa != 0.0) {
+                T zz = 0;
+                if (k >= 1) zz += xv - x[o - S];
+                if (k < g.nz - 1) {
+                    dz = x[o + S] - xv;
+                    zz -= dz;
+                }
+                gv += kap2 * zz;
             }
-            gv += kap2 * zz;
+            if (interior) {
+                if (block) {
+                    s.g[o] = gv;
+                    const double gd = (double)gv, dd = (double)dv[qq];
+                    qs[0] += gd * gd;
+                    qs[1] += gd * dd;
+                    qs[2] += dd * dd;
+                } else if (mode == GM_GRAD) {
+                    out[o] = gv;
+                } else {  // GM_EVAL: terms of f in double
+                    const double xd = (double)xv;
+                    const double dxd = (i < g.nx - 1) ? (double)xc[1] - xd : 0.0;
+                    const double dyd = (j < g.ny - 1) ? (double)xc[XW] - xd : 0.0;
+                    const double dzd = (double)dz;
+                    const double bx = xd - (xd < prm.xmin ? prm.xmin : (xd > prm.xmax ? prm.xmax : xd));
+                    const double gd = (double)gv;
+                    qs[0] += gd * gd;
+                    qs[1] += sqrt(dxd * dxd + dyd * dyd + prm.delta * prm.delta);
+                    qs[2] += bx * bx;
+                    qs[3] += dzd * dzd;
+                }
+            }
         }
-        if (mode == GM_BLOCK) {
-            s.g[o] = gv;
-            const double gd = (double)gv, dd = (double)dpv[o];
-            qs[0] += gd * gd;
-            qs[1] += gd * dd;
-            qs[2] += dd * dd;
-        } else if (mode == GM_GRAD) {
-            out[o] = gv;
-        } else {  // GM_EVAL: terms of f in double
-            const double xd = (double)xv;
-            const double dxd = (i < g.nx - 1) ? (double)xc[1] - xd : 0.0;
-            const double dyd = (j < g.ny - 1) ? (double)xc[XW] - xd : 0.0;
-            const double dzd = (double)dz;
-            const double bx = xd - (xd < prm.xmin ? prm.xmin : (xd > prm.xmax ? prm.xmax : xd));
-            const double gd = (double)gv;
-            qs[0] += gd * gd;
-            qs[1] += sqrt(dxd * dxd + dyd * dyd + prm.delta * prm.delta);
-            qs[2] += bx * bx;
-            qs[3] += dzd * dzd;
-        }
+        G[e] = gv;
+        D[e] = dv[qq];
     }
-    if (mode == GM_BLOCK) {
-        double q3[NQG] = {qs[0], qs[1], qs[2]};
-        wg_reduce_store<NQG>(q3, red, partials + slot_of() * NQG);
+    if (block) {
+        __syncthreads();
+        // sum_S w (VX d_a VX d_b + VY d_a VY d_b), d1 = -g, d2 = dp
+        const int tx = threadIdx.x & (TX - 1);
+#pragma unroll
+        for (int e = 0; e < RPT; ++e) {
+            const int lj = out_row(e), li = tx;
+            const int j = y0 + lj, i = x0 + li;
+            if (i >= g.nx || j >= g.ny) continue;
+            const double w = (double)WW[(lj + 1) * PW + (li + 1)];
+            const int c0 = lj * GW + li;
+            const double g0 = (double)G[c0], p0 = (double)D[c0];
+            const double dx1 = (i < g.nx - 1) ? g0 - (double)G[c0 + 1] : 0.0;
+            const double dy1 = (j < g.ny - 1) ? g0 - (double)G[c0 + GW] : 0.0;
+            const double dx2 = (i < g.nx - 1) ? (double)D[c0 + 1] - p0 : 0.0;
+            const double dy2 = (j < g.ny - 1) ? (double)D[c0 + GW] - p0 : 0.0;
+            qs[3] += w * (dx1 * dx1 + dy1 * dy1);
+            qs[4] += w * (dx1 * dx2 + dy1 * dy2);
+            qs[5] += w * (dx2 * dx2 + dy2 * dy2);
+        }
+        wg_reduce_store<NQG>(qs, red, partials + slot_of() * NQG);
     } else if (mode == GM_EVAL) {
-        wg_reduce_store<NQE>(qs, red, partials + slot_of() * NQE);
+        double q4[NQE] = {qs[0], qs[1], qs[2], qs[3]};
+        wg_reduce_store<NQE>(q4, red, partials + slot_of() * NQE);
     }
 }
 
@@ -295,19 +344,19 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
 // Direction pass, one output slice k per item, for the block S = [z0, z0+n):
 // with d1 = -g and d2 = dp (zero outside S),
 //   (H d)_k = XY_k( sum_c gz_k[c] d_{k-c} ),
-// the sums <Hd_a, Hd_b>, and on S the curvature sums
-// sum w (VX d_a VX d_b + VY d_a VY d_b) and <VZ d_a, VZ d_b> (a, b in {1, 2}).
+// the sums <Hd_a, Hd_b> and <VZ d_a, VZ d_b> (a, b in {1, 2}).
 // ---------------------------------------------------------------------------
 template <typename T, int KZ, int R>
 __global__ void __launch_bounds__(NT)
 k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double *__restrict__ partials)
 {
+    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W = TX + 2 * R, H = TY + 2 * R;
-    __shared__ T A1[W * H];
-    __shared__ T A2[W * H];
-    __shared__ T B1[TX * H];
-    __shared__ T B2[TX * H];
+    __shared__ T A1[padded<W, H>()];
+    __shared__ T A2[padded<W, H>()];
+    __shared__ T B1[padded<TX, H>()];
+    __shared__ T B2[padded<TX, H>()];
     __shared__ double red[(NT / 64) * NQD];
 
     const Item it = items[blockIdx.z];
@@ -334,18 +383,16 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
         const T wv = wz[c + RZ];
         const T *gs = gg + (size_t)sl * S, *ds = dpv + (size_t)sl * S;
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq)
-            if (rg.inb[qq]) {
-                v1[qq] -= wv * gs[rg.off[qq]];
-                v2[qq] += wv * ds[rg.off[qq]];
-            }
+        for (int qq = 0; qq < rg.E; ++qq) {
+            v1[qq] -= wv * gs[rg.off[qq]];
+            v2[qq] += wv * ds[rg.off[qq]];
+        }
     }
 #pragma unroll
-    for (int qq = 0; qq < rg.E; ++qq)
-        if (rg.act[qq]) {
-            A1[threadIdx.x + qq * NT] = v1[qq];
-            A2[threadIdx.x + qq * NT] = v2[qq];
-        }
+    for (int qq = 0; qq < rg.E; ++qq) {
+        A1[threadIdx.x + qq * NT] = rg.inb[qq] ? v1[qq] : T(0);
+        A2[threadIdx.x + qq * NT] = rg.inb[qq] ? v2[qq] : T(0);
+    }
     __syncthreads();
     xpass<T, R, W, TX, H, R, false>(A1, B1, wx);
     xpass<T, R, W, TX, H, R, false>(A2, B2, wx);
@@ -359,7 +406,6 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     for (int v = 0; v < NQD; ++v) qs[v] = 0.0;
     const bool ink = (k >= z0 && k < z1);
     const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
-    const T del2 = (T)(prm.delta * prm.delta);
 #pragma unroll
     for (int e = 0; e < RPT; ++e) {
         const int j = y0 + out_row(e), i = x0 + tx;
@@ -368,24 +414,9 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
         qs[0] += a * a;
         qs[1] += a * b;
         qs[2] += b * b;
-        const size_t o = vidx(g, k, j, i);
-        if (ink) {
-            const bool lastx = (i == g.nx - 1), lasty = (j == g.ny - 1);
-            const T xv = s.x[o];
-            const T dxx = lastx ? T(0) : s.x[o + 1] - xv;
-            const T dyx = lasty ? T(0) : s.x[o + g.nx] - xv;
-            const double w = (double)inv_sqrt(dxx * dxx + dyx * dyx + del2);
-            const double g0 = (double)gg[o], p0 = (double)dpv[o];
-            const double dx1 = lastx ? 0.0 : g0 - (double)gg[o + 1];
-            const double dy1 = lasty ? 0.0 : g0 - (double)gg[o + g.nx];
-            const double dx2 = lastx ? 0.0 : (double)dpv[o + 1] - p0;
-            const double dy2 = lasty ? 0.0 : (double)dpv[o + g.nx] - p0;
-            qs[3] += w * (dx1 * dx1 + dy1 * dy1);
-            qs[4] += w * (dx1 * dx2 + dy1 * dy2);
-            qs[5] += w * (dx2 * dx2 + dy2 * dy2);
-        }
         if (zterm) {
             // VZ d at slice k: d_{k+1} - d_k with d zero outside S
+            const size_t o = vidx(g, k, j, i);
             double z1v = 0.0, z2v = 0.0;
             if (k + 1 >= z0 && k + 1 < z1) {
                 z1v -= (double)gg[o + S];
@@ -395,9 +426,9 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
                 z1v += (double)gg[o];
                 z2v -= (double)dpv[o];
             }
-            qs[6] += z1v * z1v;
-            qs[7] += z1v * z2v;
-            qs[8] += z2v * z2v;
+            qs[3] += z1v * z1v;
+            qs[4] += z1v * z2v;
+            qs[5] += z2v * z2v;
         }
     }
     wg_reduce_store<NQD>(qs, red, partials + slot_of() * NQD);
@@ -420,11 +451,12 @@ __global__ void __launch_bounds__(NT)
 k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
          const Item *__restrict__ items, const double *__restrict__ u, int mode)
 {
+    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W1 = TX + 4 * R, H1 = TY + 4 * R;  // z-combined source, 2R halo
     constexpr int W2 = TX + 2 * R, H2 = TY + 2 * R;  // H v, R halo
-    __shared__ T A[W1 * H1];                         // z-combined source, later H v
-    __shared__ T B[W2 * H1];                         // forward x pass, later adjoint x pass
+    __shared__ T A[padded<W1, H1>()];                // z-combined source, later H v
+    __shared__ T B[padded<W2, H1>()];                // forward x pass, later adjoint x pass
 
     const Item it = items[blockIdx.z];
     const int m = it.k, z0 = it.z0, z1 = it.z0 + it.n;
@@ -459,18 +491,16 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
                 const T *gs = gg + (size_t)sl * S, *ds = dpi + (size_t)sl * S;
 #pragma unroll
                 for (int qq = 0; qq < rg.E; ++qq)
-                    if (rg.inb[qq]) v[qq] += wv * (u2 * ds[rg.off[qq]] - u1 * gs[rg.off[qq]]);
+                    v[qq] += wv * (u2 * ds[rg.off[qq]] - u1 * gs[rg.off[qq]]);
             } else {
                 if (sl < 0 || sl >= g.nz) continue;
                 const T *ss = src + (size_t)sl * S;
 #pragma unroll
-                for (int qq = 0; qq < rg.E; ++qq)
-                    if (rg.inb[qq]) v[qq] += wv * ss[rg.off[qq]];
+                for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ss[rg.off[qq]];
             }
         }
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq)
-            if (rg.act[qq]) A[threadIdx.x + qq * NT] = v[qq];
+        for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
     }
     // the data term of a refresh is needed on the R halo; load it early
     Region<W2, H2, R, R> r2(g, x0, y0);
@@ -478,7 +508,7 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     if (!upd) {
         const T *ys = s.y + (size_t)m * S;
 #pragma unroll
-        for (int qq = 0; qq < r2.E; ++qq) yv[qq] = r2.inb[qq] ? ys[r2.off[qq]] : T(0);
+        for (int qq = 0; qq < r2.E; ++qq) yv[qq] = ys[r2.off[qq]];
     }
     __syncthreads();
     // 2. forward x pass: all H1 rows, the W2 columns of the R-halo tile
@@ -487,17 +517,16 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     // 3. forward y pass on the R-halo tile into A (H v), zero outside the slice
 #pragma unroll
     for (int qq = 0; qq < r2.E; ++qq) {
-        if (!r2.act[qq]) continue;
         const int e = threadIdx.x + qq * NT;
-        const int r = e / W2, c = e - r * W2;
+        int r = e / W2;
+        const int c = e - r * W2;
+        if (qq == r2.E - 1) r = r < H2 ? r : H2 - 1;
+        const T *col = B + (r + R) * W2 + c;
         T acc = 0;
-        if (r2.inb[qq]) {
-            const T *col = B + (r + R) * W2 + c;
 #pragma unroll
-            for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[-b * W2];
-            if (!upd) acc -= yv[qq];
-        }
-        A[e] = acc;
+        for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[-b * W2];
+        if (!upd) acc -= yv[qq];
+        A[e] = r2.inb[qq] ? acc : T(0);
     }
     __syncthreads();
     // 4. adjoint x pass over the R-halo rows into B
@@ -532,10 +561,11 @@ __global__ void __launch_bounds__(NT)
 k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, T *__restrict__ out,
     const Item *__restrict__ items, double *__restrict__ partials)
 {
+    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W = TX + 2 * R, H = TY + 2 * R;
-    __shared__ T A[W * H];
-    __shared__ T B[TX * H];
+    __shared__ T A[padded<W, H>()];
+    __shared__ T B[padded<TX, H>()];
     __shared__ double red[NT / 64];
     const Item it = items[blockIdx.z];
     const int k = it.k;
@@ -558,12 +588,10 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
             const T wv = wz[c + RZ];
             const T *ss = in + (size_t)sl * S;
 #pragma unroll
-            for (int qq = 0; qq < rg.E; ++qq)
-                if (rg.inb[qq]) v[qq] += wv * ss[rg.off[qq]];
+            for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ss[rg.off[qq]];
         }
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq)
-            if (rg.act[qq]) A[threadIdx.x + qq * NT] = v[qq];
+        for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
     }
     __syncthreads();
     xpass<T, R, W, TX, H, R, false>(A, B, wx);
@@ -594,8 +622,8 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
 {
     constexpr int K = 2 * R + 1;
     constexpr int W = TX + 2 * R, H = TY + 2 * R;
-    __shared__ T A[W * H];
-    __shared__ T B[TX * H];
+    __shared__ T A[padded<W, H>()];
+    __shared__ T B[padded<TX, H>()];
     const Item it = items[blockIdx.z];
     const int m = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
@@ -608,10 +636,9 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
         const T *im = in + (size_t)m * g.nx * g.ny;
         T v[rg.E];
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) v[qq] = rg.inb[qq] ? im[rg.off[qq]] : T(0);
+        for (int qq = 0; qq < rg.E; ++qq) v[qq] = im[rg.off[qq]];
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq)
-            if (rg.act[qq]) A[threadIdx.x + qq * NT] = v[qq];
+        for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
     }
     __syncthreads();
     xpass<T, R, W, TX, H, R, true>(A, B, wx);
@@ -635,8 +662,10 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(NT)
 k_solve(Params prm, const BlockRange *__restrict__ brs, int ntiles, const double *__restrict__ pg,
-        const double *__restrict__ pd, double *__restrict__ u, double *__restrict__ info)
+        const double *__restrict__ pd, double *__restrict__ u, double *__restrict__ info,
+        const int *__restrict__ stop)
 {
+    if (stop && *stop) return;
     constexpr int NV = NQG + NQD;
     __shared__ double red[NT / 64][NV];
     __shared__ double tot[NV];
@@ -675,12 +704,14 @@ k_solve(Params prm, const BlockRange *__restrict__ brs, int ntiles, const double
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        // gradient pass: <g,g>, <g,dp>, <dp,dp>, then the TV curvature sums;
+        // direction pass: <Hd_a,Hd_b>, then <VZ d_a, VZ d_b>
         const double gg = tot[0], gd = tot[1], dd = tot[2];
-        const double *h = tot + NQG;
+        const double *w = tot + 3, *h = tot + NQG, *z = tot + NQG + 3;
         const double e2 = 2.0 * prm.eta, k2 = 2.0 * prm.kappa, lam = prm.lambda;
-        const double b11 = h[0] + e2 * gg + lam * h[3] + k2 * h[6];
-        const double b12 = h[1] - e2 * gd + lam * h[4] + k2 * h[7];
-        const double b22 = h[2] + e2 * dd + lam * h[5] + k2 * h[8];
+        const double b11 = h[0] + e2 * gg + lam * w[0] + k2 * z[0];
+        const double b12 = h[1] - e2 * gd + lam * w[1] + k2 * z[1];
+        const double b22 = h[2] + e2 * dd + lam * w[2] + k2 * z[2];
         const double c1 = -gg, c2 = gd;
         const double det = b11 * b22 - b12 * b12, tr = b11 + b22;
         double p11, p12, p22;
@@ -722,6 +753,33 @@ k_sum(const double *__restrict__ partials, int nslot, int nq, double *__restrict
         }
         if (threadIdx.x == 0) out[v] = red[0];
         __syncthreads();
+    }
+}
+
+// Stop test on the device: ||grad f|| from the evaluation slots (fixed-order
+// sum), recorded in *gnorm; when it is at most thr, *stop is raised and the
+// sweep number recorded, and every later pass of the run returns at entry.
+__global__ void __launch_bounds__(NT)
+k_check(const double *__restrict__ partials, int nslot, double thr, int sweep, int *stop,
+        int *stop_sweep, double *gnorm)
+{
+    __shared__ double red[NT];
+    if (*stop) return;
+    double sv = 0.0;
+    for (int t = threadIdx.x; t < nslot; t += NT) sv += partials[(size_t)t * NQE];
+    red[threadIdx.x] = sv;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double gn = sqrt(red[0]);
+        *gnorm = gn;
+        if (gn <= thr) {
+            *stop = 1;
+            *stop_sweep = sweep;
+        }
     }
 }
 
@@ -812,10 +870,18 @@ hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out
 }
 
 hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles, const double *pg,
-                        const double *pd, double *u, double *info, hipStream_t st)
+                        const double *pd, double *u, double *info, const int *stop, hipStream_t st)
 {
     if (nbr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_solve, dim3(nbr), dim3(NT), 0, st, prm, br, ntiles, pg, pd, u, info);
+    hipLaunchKernelGGL(k_solve, dim3(nbr), dim3(NT), 0, st, prm, br, ntiles, pg, pd, u, info, stop);
+    return hipGetLastError();
+}
+
+hipError_t launch_check(const double *partials, int nslot, double thr, int sweep, int *stop,
+                        int *stop_sweep, double *gnorm, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(NT), 0, st, partials, nslot, thr, sweep, stop, stop_sweep,
+                       gnorm);
     return hipGetLastError();
 }
 

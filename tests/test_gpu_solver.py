@@ -141,9 +141,9 @@ def test_profile_counts_launches(orc):
         n, ms, by = prof[k]
         assert n == 3 * nc and ms > 0 and by > 0
     assert prof["eval"][0] == 0
-    # bytes of one sweep: grad reads r on the halo'd blocks and x, dp; writes g
+    # direction pass of one sweep reads g and dp once on every block slice
     A = 64 * 64 * 8
-    assert prof["dirs"][2] == 3 * 3 * 16 * A
+    assert prof["dirs"][2] == 3 * 2 * 16 * A
     assert g.get_profile()["grad"][0] == 0
 
 
