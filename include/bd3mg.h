@@ -192,7 +192,7 @@ bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
 /* Kernel kinds reported by bd3mg_get_profile. */
 typedef enum {
     BD3MG_K_GRAD = 0,    /* gradient pass of a colour of blocks */
-    BD3MG_K_DIRS = 1,    /* direction pass (H d1, H d2, inner products) */
+    BD3MG_K_DIRS = 1,    /* direction pass (H d1, H d2, inner products) and the 2x2 solve */
     BD3MG_K_SOLVE = 2,   /* per-block 2x2 solve */
     BD3MG_K_UPDATE = 3,  /* update pass (x, dprev, r) */
     BD3MG_K_EVAL = 4,    /* whole-volume refresh of q and ||grad f|| checks */

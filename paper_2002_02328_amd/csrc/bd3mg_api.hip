@@ -292,12 +292,13 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     double sl = 0.0;
     for (int b : blocks) {
         const int z0 = p->z0[b], n = p->nsl[b];
+        const int bri = (int)br.size() - grp.br_off;
         BlockRange r{b, (int)gi.size() - grp.g_off, 0, (int)di.size() - grp.d_off, 0};
-        for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n});
+        for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n, bri, 0});
         for (int k = std::max(0, z0 - rd); k < std::min(p->nz, z0 + n + rz); ++k)
-            di.push_back(Item{k, b, z0, n});
+            di.push_back(Item{k, b, z0, n, bri, 0});
         for (int k = std::max(0, z0 - rz); k < std::min(p->nz, z0 + n + rz); ++k) {
-            ui.push_back(Item{k, b, z0, n});
+            ui.push_back(Item{k, b, z0, n, bri, 0});
             halo[k] = 1;
         }
         r.gn = (int)gi.size() - grp.g_off - r.g0;
@@ -592,7 +593,7 @@ bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *
         if (hipMalloc(v, p->N * p->esz) != hipSuccess) return bail(BD3MG_ERR_NOMEM, "volume allocation failed");
     // every slice of the volume as a work item, and the evaluation sums
     std::vector<Item> vol;
-    for (int k = 0; k < nz; ++k) vol.push_back(Item{k, -1, 0, nz});
+    for (int k = 0; k < nz; ++k) vol.push_back(Item{k, -1, 0, nz, -1, 0});
     const size_t nslot = (size_t)p->ntiles * nz;
     if (hipMalloc(&p->d_vol, vol.size() * sizeof(Item)) != hipSuccess ||
         hipMalloc(&p->d_pe, nslot * NQE * sizeof(double)) != hipSuccess ||

@@ -33,6 +33,8 @@ struct Item {
     int block;
     int z0;
     int n;
+    int bri;  // index of the block's BlockRange in its launch group (-1: none)
+    int pad;
 };
 
 // Work items of one block inside the item lists of a launch group.

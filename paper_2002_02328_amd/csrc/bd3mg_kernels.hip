@@ -341,6 +341,100 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
 }
 
 // ---------------------------------------------------------------------------
+// Per block: fixed-order reduction of its gradient and direction slots, then
+// the 2x2 system of the memory-gradient subspace (Sec. 2.3, eq. "minimizer"):
+//   B = D^T A_S D with D = [d1 | d2], d1 = -g, d2 = dp,
+//   c = D^T g = (-<g,g>, <dp,g>),  u = -B^+ c.
+// B^+ is the exact inverse when det > 1e-12 B11 B22, else the rank-one
+// pseudo-inverse B / tr(B)^2 (zero when tr(B) = 0).
+// ---------------------------------------------------------------------------
+// Fixed-order reduction of one block's slots and the 2x2 solve; all NT
+// threads of the workgroup take part.
+__device__ __forceinline__ void solve_block(const Params &prm, const BlockRange &br, int ntiles,
+                                            const double *__restrict__ pg, const double *__restrict__ pd,
+                                            double *__restrict__ u, double *__restrict__ info)
+{
+    constexpr int NV = NQG + NQD;
+    __shared__ double red[NT / 64][NV];
+    __shared__ double tot[NV];
+    // each thread sums its slots in order, then one tree over the threads
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+    {
+        const double *p = pg + (size_t)br.g0 * ntiles * NQG;
+        const int n = br.gn * ntiles;
+        for (int t = threadIdx.x; t < n; t += NT)
+#pragma unroll
+            for (int v = 0; v < NQG; ++v) acc[v] += p[(size_t)t * NQG + v];
+    }
+    {
+        const double *p = pd + (size_t)br.d0 * ntiles * NQD;
+        const int n = br.dn * ntiles;
+        for (int t = threadIdx.x; t < n; t += NT)
+#pragma unroll
+            for (int v = 0; v < NQD; ++v) acc[NQG + v] += p[(size_t)t * NQD + v];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double sv = acc[v];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sv += __shfl_down(sv, off, 64);
+        if (lane == 0) red[wave][v] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double sv = 0.0;
+        for (int w = 0; w < NT / 64; ++w) sv += red[w][threadIdx.x];
+        tot[threadIdx.x] = sv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // gradient pass: <g,g>, <g,dp>, <dp,dp>, then the TV curvature sums;
+        // direction pass: <Hd_a,Hd_b>, then <VZ d_a, VZ d_b>
+        const double gg = tot[0], gd = tot[1], dd = tot[2];
+        const double *w = tot + 3, *h = tot + NQG, *z = tot + NQG + 3;
+        const double e2 = 2.0 * prm.eta, k2 = 2.0 * prm.kappa, lam = prm.lambda;
+        const double b11 = h[0] + e2 * gg + lam * w[0] + k2 * z[0];
+        const double b12 = h[1] - e2 * gd + lam * w[1] + k2 * z[1];
+        const double b22 = h[2] + e2 * dd + lam * w[2] + k2 * z[2];
+        const double c1 = -gg, c2 = gd;
+        const double det = b11 * b22 - b12 * b12, tr = b11 + b22;
+        double p11, p12, p22;
+        if (det > 1e-12 * b11 * b22) {
+            p11 = b22 / det;
+            p12 = -b12 / det;
+            p22 = b11 / det;
+        } else if (tr > 0.0) {
+            const double t2 = tr * tr;
+            p11 = b11 / t2;
+            p12 = b12 / t2;
+            p22 = b22 / t2;
+        } else {
+            p11 = p12 = p22 = 0.0;
+        }
+        const double u1 = -(p11 * c1 + p12 * c2);
+        const double u2 = -(p12 * c1 + p22 * c2);
+        u[2 * br.block] = u1;
+        u[2 * br.block + 1] = u2;
+        if (info) {
+            double *o = info + 8 * br.block;
+            o[0] = b11; o[1] = b12; o[2] = b22; o[3] = c1; o[4] = c2; o[5] = u1; o[6] = u2; o[7] = gg;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(NT)
+k_solve(Params prm, const BlockRange *__restrict__ brs, int ntiles, const double *__restrict__ pg,
+        const double *__restrict__ pd, double *__restrict__ u, double *__restrict__ info,
+        const int *__restrict__ stop)
+{
+    if (stop && *stop) return;
+    solve_block(prm, brs[blockIdx.x], ntiles, pg, pd, u, info);
+}
+
+// ---------------------------------------------------------------------------
 // Direction pass, one output slice k per item, for the block S = [z0, z0+n):
 // with d1 = -g and d2 = dp (zero outside S),
 //   (H d)_k = XY_k( sum_c gz_k[c] d_{k-c} ),
@@ -649,92 +743,6 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
     for (int e = 0; e < RPT; ++e) {
         const int j = y0 + out_row(e), i = x0 + tx;
         if (i < g.nx && j < g.ny) out[vidx(g, m, j, i)] = v[e];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Per block: fixed-order reduction of its gradient and direction slots, then
-// the 2x2 system of the memory-gradient subspace (Sec. 2.3, eq. "minimizer"):
-//   B = D^T A_S D with D = [d1 | d2], d1 = -g, d2 = dp,
-//   c = D^T g = (-<g,g>, <dp,g>),  u = -B^+ c.
-// B^+ is the exact inverse when det > 1e-12 B11 B22, else the rank-one
-// pseudo-inverse B / tr(B)^2 (zero when tr(B) = 0).
-// ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(NT)
-k_solve(Params prm, const BlockRange *__restrict__ brs, int ntiles, const double *__restrict__ pg,
-        const double *__restrict__ pd, double *__restrict__ u, double *__restrict__ info,
-        const int *__restrict__ stop)
-{
-    if (stop && *stop) return;
-    constexpr int NV = NQG + NQD;
-    __shared__ double red[NT / 64][NV];
-    __shared__ double tot[NV];
-    const BlockRange br = brs[blockIdx.x];
-    // each thread sums its slots in order, then one tree over the threads
-    double acc[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-    {
-        const double *p = pg + (size_t)br.g0 * ntiles * NQG;
-        const int n = br.gn * ntiles;
-        for (int t = threadIdx.x; t < n; t += NT)
-#pragma unroll
-            for (int v = 0; v < NQG; ++v) acc[v] += p[(size_t)t * NQG + v];
-    }
-    {
-        const double *p = pd + (size_t)br.d0 * ntiles * NQD;
-        const int n = br.dn * ntiles;
-        for (int t = threadIdx.x; t < n; t += NT)
-#pragma unroll
-            for (int v = 0; v < NQD; ++v) acc[NQG + v] += p[(size_t)t * NQD + v];
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        double sv = acc[v];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) sv += __shfl_down(sv, off, 64);
-        if (lane == 0) red[wave][v] = sv;
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        double sv = 0.0;
-        for (int w = 0; w < NT / 64; ++w) sv += red[w][threadIdx.x];
-        tot[threadIdx.x] = sv;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // gradient pass: <g,g>, <g,dp>, <dp,dp>, then the TV curvature sums;
-        // direction pass: <Hd_a,Hd_b>, then <VZ d_a, VZ d_b>
-        const double gg = tot[0], gd = tot[1], dd = tot[2];
-        const double *w = tot + 3, *h = tot + NQG, *z = tot + NQG + 3;
-        const double e2 = 2.0 * prm.eta, k2 = 2.0 * prm.kappa, lam = prm.lambda;
-        const double b11 = h[0] + e2 * gg + lam * w[0] + k2 * z[0];
-        const double b12 = h[1] - e2 * gd + lam * w[1] + k2 * z[1];
-        const double b22 = h[2] + e2 * dd + lam * w[2] + k2 * z[2];
-        const double c1 = -gg, c2 = gd;
-        const double det = b11 * b22 - b12 * b12, tr = b11 + b22;
-        double p11, p12, p22;
-        if (det > 1e-12 * b11 * b22) {
-            p11 = b22 / det;
-            p12 = -b12 / det;
-            p22 = b11 / det;
-        } else if (tr > 0.0) {
-            const double t2 = tr * tr;
-            p11 = b11 / t2;
-            p12 = b12 / t2;
-            p22 = b22 / t2;
-        } else {
-            p11 = p12 = p22 = 0.0;
-        }
-        const double u1 = -(p11 * c1 + p12 * c2);
-        const double u2 = -(p12 * c1 + p22 * c2);
-        u[2 * br.block] = u1;
-        u[2 * br.block + 1] = u2;
-        if (info) {
-            double *o = info + 8 * br.block;
-            o[0] = b11; o[1] = b12; o[2] = b22; o[3] = c1; o[4] = c2; o[5] = u1; o[6] = u2; o[7] = gg;
-        }
     }
 }
 
