@@ -186,8 +186,29 @@ bd3mg_status bd3mg_block_step(bd3mg_problem p, int block, double *info);
  * never; default 0 for FP64, 64 for FP32), bounding the drift of the
  * incrementally updated q.  BD3MG_OPT_PROFILE: 1 records HIP events around
  * every kernel launch of bd3mg_run on the problem's stream (0 = off). */
-typedef enum { BD3MG_OPT_REFRESH_EVERY = 0, BD3MG_OPT_PROFILE = 1 } bd3mg_option;
+typedef enum {
+    BD3MG_OPT_REFRESH_EVERY = 0,
+    BD3MG_OPT_PROFILE = 1,
+    /* Tile height (rows of a 64-column workgroup tile: 16 or 32; FP64 takes 16
+     * only) of the direction pass, the update pass, and the whole-volume H and
+     * adjoint-blur passes.  Taller tiles recompute less halo; shorter tiles give
+     * more workgroups.  Defaults: 32 for FP32, 16 for FP64.  Results are
+     * bitwise reproducible for a fixed setting; changing it changes the order
+     * of the partial sums (rounding only). */
+    BD3MG_OPT_TILE_ROWS_DIRS = 2,
+    BD3MG_OPT_TILE_ROWS_UPDATE = 3,
+    BD3MG_OPT_TILE_ROWS_AUX = 4
+} bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
+
+/* Autotuner: times `sweeps` sweeps (after one warm-up sweep) for every
+ * combination of tile heights of the direction and update passes on this
+ * problem, keeps the fastest, and restores the solver state it started from
+ * (x, previous steps, q, sweep count), so the call does not advance the
+ * method.  chosen (may be NULL) receives {rows of the direction pass, rows of
+ * the update pass}; ms (may be NULL) the best time per sweep in milliseconds.
+ * ERR_STATE: PSF, data or blocks not set. */
+bd3mg_status bd3mg_autotune(bd3mg_problem p, int sweeps, int *chosen, double *ms);
 
 /* Kernel kinds reported by bd3mg_get_profile. */
 typedef enum {

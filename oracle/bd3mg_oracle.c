@@ -68,6 +68,30 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Reusable zero-filled scratch volumes.  A buffer handed out by scratch_get
+ * is all zeros; its user zeroes the slices it wrote before scratch_put, so the
+ * oracle does not clear whole volumes on every block update.  (Storage only:
+ * no arithmetic depends on it.) */
+enum { SCR_R, SCR_HU, SCR_HV, SCR_G, SCR_D1, SCR_D2, SCR_COUNT };
+static double *scr_buf[SCR_COUNT];
+static size_t scr_cap[SCR_COUNT];
+
+static double *scratch_get(int slot, size_t n)
+{
+    if (scr_cap[slot] < n) {
+        free(scr_buf[slot]);
+        scr_buf[slot] = (double *)calloc(n, sizeof(double));
+        scr_cap[slot] = n;
+    }
+    return scr_buf[slot];
+}
+
+/* Zero slices [k0, k1) (of S voxels each) of a scratch buffer. */
+static void scratch_clear(double *b, int k0, int k1, size_t S)
+{
+    if (k1 > k0) memset(b + (size_t)k0 * S, 0, (size_t)(k1 - k0) * S * sizeof(double));
+}
+
 /* ------------------------------------------------------------------------ */
 /* PSF tables.  Sec. 3.1: a depth-variant Gaussian blur.  Each 1-D factor is
  * exp(-a^2 / (2 sigma_k^2)) on a in [-r, r], normalised to sum 1 (so each
@@ -364,12 +388,12 @@ void orc_grad_slices(const orc_problem *p, const double *x, double *g, int k0, i
     if (k1 > p->nz) k1 = p->nz;
     if (k0 >= k1) return;
     int r0 = k0 - rz < 0 ? 0 : k0 - rz, r1 = k1 + rz > p->nz ? p->nz : k1 + rz;
-    double *r = (double *)calloc(N, sizeof(double));
+    double *r = scratch_get(SCR_R, N);
     orc_H(p, x, r, r0, r1);
     size_t S = nslice(p);
     for (size_t q = (size_t)r0 * S; q < (size_t)r1 * S; ++q) r[q] -= p->y[q];
     orc_HT(p, r, g, k0, k1);
-    free(r);
+    scratch_clear(r, r0, r1, S);
 #pragma omp parallel for schedule(static)
     for (int k = k0; k < k1; ++k)
         for (int j = 0; j < p->ny; ++j)
@@ -435,13 +459,13 @@ double orc_majorant_form(const orc_problem *p, const double *x, const double *u,
     if (z0 < 0) z0 = 0;
     if (z1 > p->nz) z1 = p->nz;
     int h0 = z0 - rz < 0 ? 0 : z0 - rz, h1 = z1 + rz > p->nz ? p->nz : z1 + rz;
-    double *hu = (double *)calloc(N, sizeof(double));
-    double *hv = (double *)calloc(N, sizeof(double));
+    double *hu = scratch_get(SCR_HU, N);
+    double *hv = scratch_get(SCR_HV, N);
     orc_H(p, u, hu, h0, h1);
     orc_H(p, v, hv, h0, h1);
     double quad = dot_slices(p, hu, hv, h0, h1);
-    free(hu);
-    free(hv);
+    scratch_clear(hu, h0, h1, nslice(p));
+    scratch_clear(hv, h0, h1, nslice(p));
     double box = dot_slices(p, u, v, z0, z1);
     int nzs = z1 - z0;
     double *part = (double *)calloc((size_t)(nzs > 0 ? nzs : 1), sizeof(double));
@@ -538,9 +562,9 @@ void orc_block_step(const orc_problem *p, double *x, double *dprev, int z0, int 
 {
     size_t N = nvox(p), S = nslice(p);
     size_t off = (size_t)z0 * S, cnt = (size_t)n * S;
-    double *g = (double *)calloc(N, sizeof(double));
-    double *d1 = (double *)calloc(N, sizeof(double));
-    double *d2 = (double *)calloc(N, sizeof(double));
+    double *g = scratch_get(SCR_G, N);
+    double *d1 = scratch_get(SCR_D1, N);
+    double *d2 = scratch_get(SCR_D2, N);
     /* (2)-(3): gradient on the block, subspace directions [-g | d] */
     orc_grad_slices(p, x, g, z0, z0 + n);
     for (size_t q = off; q < off + cnt; ++q) {
@@ -569,9 +593,9 @@ void orc_block_step(const orc_problem *p, double *x, double *dprev, int z0, int 
         info[3] = c1; info[4] = c2; info[5] = u1; info[6] = u2;
         info[7] = -c1;
     }
-    free(g);
-    free(d1);
-    free(d2);
+    scratch_clear(g, z0, z0 + n, S);
+    scratch_clear(d1, z0, z0 + n, S);
+    scratch_clear(d2, z0, z0 + n, S);
 }
 
 static double norm_grad(const orc_problem *p, const double *x)

@@ -21,6 +21,7 @@ SCHED_COLORED, SCHED_SEQUENTIAL = 0, 1
 OP_H, OP_HT, OP_GRAD = 0, 1, 2
 OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_HIP, ERR_NOT_CONVERGED = range(6)
 OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
+OPT_TILE_ROWS_DIRS, OPT_TILE_ROWS_UPDATE, OPT_TILE_ROWS_AUX = 2, 3, 4
 KERNEL_KINDS = ("grad", "dirs", "solve", "update", "eval")
 
 # Every function the header declares, with its C signature.
@@ -45,6 +46,7 @@ SIGNATURES = {
     "bd3mg_set_state": ([_dp, _dp, _dp, _dp, C.c_longlong, _i], C.c_int),
     "bd3mg_set_option": ([_dp, _i, C.c_longlong], C.c_int),
     "bd3mg_get_profile": ([_dp, _dp, _dp, _dp, _i], C.c_int),
+    "bd3mg_autotune": ([_dp, _i, _dp, _dp], C.c_int),
     "bd3mg_eval": ([_dp, _dp, _dp], C.c_int),
     "bd3mg_apply": ([_dp, _i, _dp, _dp, _i], C.c_int),
     "bd3mg_block_step": ([_dp, _i, _dp], C.c_int),
@@ -226,6 +228,13 @@ class Problem:
 
     def set_option(self, option, value):
         _check(load().bd3mg_set_option(self._h, option, int(value)))
+
+    def autotune(self, sweeps=5):
+        """Pick the fastest tile heights on this problem; returns ((dirs, update), ms/sweep)."""
+        ch = np.zeros(2, np.int32)
+        ms = C.c_double()
+        _check(load().bd3mg_autotune(self._h, int(sweeps), ch.ctypes.data, C.byref(ms)))
+        return (int(ch[0]), int(ch[1])), ms.value
 
     def get_profile(self, reset=False):
         """{kind: (launches, ms, algorithmic bytes)} of the profiled runs."""

@@ -372,7 +372,8 @@ bd3mg_status build_schedule(bd3mg_problem p)
     }
     ST_TRY(realloc_dev((void **)&p->d_pg, &p->pg_cap, (size_t)maxg * p->ntiles * NQG * sizeof(double),
                        "gradient partial sums"));
-    ST_TRY(realloc_dev((void **)&p->d_pd, &p->pd_cap, (size_t)maxd * p->ntiles * NQD * sizeof(double),
+    ST_TRY(realloc_dev((void **)&p->d_pd, &p->pd_cap,
+                       (size_t)maxd * tiles_of(p->geom, 16) * NQD * sizeof(double),
                        "direction partial sums"));
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->sched_dirty = false;
@@ -429,7 +430,8 @@ bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, doub
         ST_TRY(ensure_tmp(p, 1));
         HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, (T *)p->tmp[0], p->d_vol, p->nz, p->d_pr,
                             p->stream));
-        HIP_TRY(launch_sum(p->d_pr, nslot, 1, p->d_sum + NQE, p->stream));
+        HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, p->geom.ty_aux) * p->nz, 1, p->d_sum + NQE,
+                           p->stream));
     }
     double q[NQE + 1] = {0, 0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(q, p->d_sum, (f ? NQE + 1 : NQE) * sizeof(double), hipMemcpyDeviceToHost,
@@ -487,8 +489,9 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
     HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, it + gr.d_off, gr.d_cnt, p->d_pd, p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
-    HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles, p->d_pg, p->d_pd, p->d_u,
-                         p->d_info, stop, p->stream));
+    HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,
+                         tiles_of(p->geom, p->geom.ty_dirs), p->d_pg, p->d_pd, p->d_u, p->d_info, stop,
+                         p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
     HIP_TRY(launch_update<T>(p->geom, s, nullptr, s.q, it + gr.u_off, gr.u_cnt, p->d_u, UM_UPDATE,
@@ -579,6 +582,10 @@ bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *
     p->geom.nz = nz;
     p->geom.ntx = (nx + TX - 1) / TX;
     p->geom.nty = (ny + TY - 1) / TY;
+    {
+        const int ty = precision == BD3MG_FP64 ? 16 : 32;
+        p->geom.ty_dirs = p->geom.ty_update = p->geom.ty_aux = ty;
+    }
     auto bail = [&](bd3mg_status st, const char *what) {
         bd3mg_destroy(p);
         return fail(st, "%s", what);
@@ -904,9 +911,71 @@ bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value)
         ST_TRY(prof_collect(p));
         p->profile = value != 0;
         return BD3MG_OK;
+    case BD3MG_OPT_TILE_ROWS_DIRS:
+    case BD3MG_OPT_TILE_ROWS_UPDATE:
+    case BD3MG_OPT_TILE_ROWS_AUX: {
+        if (value != 16 && !(value == 32 && p->prec == BD3MG_FP32))
+            return fail(BD3MG_ERR_ARG, "tile rows must be 16 (or 32 in FP32), got %lld", value);
+        int *t = option == BD3MG_OPT_TILE_ROWS_DIRS     ? &p->geom.ty_dirs
+                 : option == BD3MG_OPT_TILE_ROWS_UPDATE ? &p->geom.ty_update
+                                                        : &p->geom.ty_aux;
+        *t = (int)value;
+        return BD3MG_OK;
+    }
     default:
         return fail(BD3MG_ERR_ARG, "unknown option %d", option);
     }
+}
+
+bd3mg_status bd3mg_autotune(bd3mg_problem p, int sweeps, int *chosen, double *ms_out)
+{
+    ST_TRY(validate_handle(p));
+    if (sweeps < 1) return fail(BD3MG_ERR_ARG, "sweeps < 1");
+    ST_TRY(ensure_ready(p));
+    ST_TRY(ensure_tmp(p, 3));
+    // save the state
+    const size_t vb = p->N * p->esz;
+    HIP_TRY(hipMemcpyAsync(p->tmp[0], p->x, vb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->tmp[1], p->dpb[p->cur], vb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->tmp[2], p->q, vb, hipMemcpyDeviceToDevice, p->stream));
+    const int cur0 = p->cur;
+    const long long sw0 = p->sweeps_done;
+    const bool prof0 = p->profile;
+    p->profile = false;
+    std::vector<int> cand = {16};
+    if (p->prec == BD3MG_FP32) cand.push_back(32);
+    double best = -1.0;
+    int bd = p->geom.ty_dirs, bu = p->geom.ty_update;
+    for (int td : cand)
+        for (int tu : cand) {
+            p->geom.ty_dirs = td;
+            p->geom.ty_update = tu;
+            bd3mg_result r;
+            ST_TRY(bd3mg_run(p, 1, 0.0, 0, nullptr));
+            ST_TRY(bd3mg_run(p, sweeps, 0.0, 0, &r));
+            const double t = r.seconds * 1e3 / sweeps;
+            if (best < 0.0 || t < best) {
+                best = t;
+                bd = td;
+                bu = tu;
+            }
+        }
+    p->geom.ty_dirs = bd;
+    p->geom.ty_update = bu;
+    p->profile = prof0;
+    // restore the state
+    p->cur = cur0;
+    HIP_TRY(hipMemcpyAsync(p->x, p->tmp[0], vb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->dpb[p->cur], p->tmp[1], vb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipMemcpyAsync(p->q, p->tmp[2], vb, hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->sweeps_done = sw0;
+    if (chosen) {
+        chosen[0] = bd;
+        chosen[1] = bu;
+    }
+    if (ms_out) *ms_out = best;
+    return BD3MG_OK;
 }
 
 bd3mg_status bd3mg_get_profile(bd3mg_problem p, long long *launches, double *ms, double *bytes,

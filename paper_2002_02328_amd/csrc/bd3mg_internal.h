@@ -52,8 +52,14 @@ struct Geom {
     int nx, ny, nz;
     int rx, ry, rz;
     int R;         // in-slice radius of the device tables: max(rx, ry, 1)
-    int ntx, nty;  // tiles per slice
+    int ntx, nty;  // tiles per slice of the gradient pass (TX x TY)
+    // tile heights (16 or 32 rows) of the direction pass, the update pass and
+    // the whole-volume H / adjoint-blur passes
+    int ty_dirs, ty_update, ty_aux;
 };
+
+// Tiles per slice of a pass with tile height ty.
+inline int tiles_of(const Geom &g, int ty) { return g.ntx * ((g.ny + ty - 1) / ty); }
 
 // Device state of a problem, in storage type T.  q holds, slice by slice,
 // q_m = XY^T_m (H x - y)_m: the residual blurred in-slice by the adjoint of
@@ -104,8 +110,8 @@ hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out
 
 // Per block range: fixed-order reduction of the block's slots, the 2x2
 // majorant system, its pseudo-inverse and the step coefficients u.
-hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles,
-                        const double *pg, const double *pd, double *u, double *info,
+hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles_g,
+                        int ntiles_d, const double *pg, const double *pd, double *u, double *info,
                         const int *stop, hipStream_t st);
 
 // Device stop test after an evaluation pass (see k_check).

@@ -30,7 +30,7 @@ namespace bd3mg {
 
 namespace {
 
-constexpr int RPT = TY / (NT / TX);  // outputs (rows) per thread: 4
+constexpr int RPT = TY / (NT / TX);  // outputs (rows) per thread of a TY-row tile: 4
 
 __device__ __forceinline__ size_t vidx(const Geom &g, int k, int j, int i)
 {
@@ -101,13 +101,13 @@ __device__ __forceinline__ void xpass(const T *I, T *O, const T (&wx)[2 * R + 1]
 }
 
 // y pass into registers: v[e] at tile row out_row(e), column threadIdx.x % TX,
-// reading rows (out_row + OFF -/+ b) of B (rows of width WB).
-template <typename T, int R, int WB, int OFF, bool ADJ>
-__device__ __forceinline__ void ypass_out(const T *B, T (&v)[RPT], const T (&wy)[2 * R + 1])
+// reading rows (out_row + OFF -/+ b) of B (rows of width WB); NR rows per thread.
+template <typename T, int R, int WB, int OFF, bool ADJ, int NR>
+__device__ __forceinline__ void ypass_out(const T *B, T (&v)[NR], const T (&wy)[2 * R + 1])
 {
     const int i = threadIdx.x & (TX - 1);
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) {
+    for (int e = 0; e < NR; ++e) {
         const T *col = B + (out_row(e) + OFF) * WB + i;
         T acc = 0;
 #pragma unroll
@@ -350,7 +350,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
 // ---------------------------------------------------------------------------
 // Fixed-order reduction of one block's slots and the 2x2 solve; all NT
 // threads of the workgroup take part.
-__device__ __forceinline__ void solve_block(const Params &prm, const BlockRange &br, int ntiles,
+__device__ __forceinline__ void solve_block(const Params &prm, const BlockRange &br, int ntg, int ntd,
                                             const double *__restrict__ pg, const double *__restrict__ pd,
                                             double *__restrict__ u, double *__restrict__ info)
 {
@@ -362,15 +362,15 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     {
-        const double *p = pg + (size_t)br.g0 * ntiles * NQG;
-        const int n = br.gn * ntiles;
+        const double *p = pg + (size_t)br.g0 * ntg * NQG;
+        const int n = br.gn * ntg;
         for (int t = threadIdx.x; t < n; t += NT)
 #pragma unroll
             for (int v = 0; v < NQG; ++v) acc[v] += p[(size_t)t * NQG + v];
     }
     {
-        const double *p = pd + (size_t)br.d0 * ntiles * NQD;
-        const int n = br.dn * ntiles;
+        const double *p = pd + (size_t)br.d0 * ntd * NQD;
+        const int n = br.dn * ntd;
         for (int t = threadIdx.x; t < n; t += NT)
 #pragma unroll
             for (int v = 0; v < NQD; ++v) acc[NQG + v] += p[(size_t)t * NQD + v];
@@ -426,12 +426,12 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
 }
 
 __global__ void __launch_bounds__(NT)
-k_solve(Params prm, const BlockRange *__restrict__ brs, int ntiles, const double *__restrict__ pg,
+k_solve(Params prm, const BlockRange *__restrict__ brs, int ntg, int ntd, const double *__restrict__ pg,
         const double *__restrict__ pd, double *__restrict__ u, double *__restrict__ info,
         const int *__restrict__ stop)
 {
     if (stop && *stop) return;
-    solve_block(prm, brs[blockIdx.x], ntiles, pg, pd, u, info);
+    solve_block(prm, brs[blockIdx.x], ntg, ntd, pg, pd, u, info);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,13 +440,14 @@ k_solve(Params prm, const BlockRange *__restrict__ brs, int ntiles, const double
 //   (H d)_k = XY_k( sum_c gz_k[c] d_{k-c} ),
 // the sums <Hd_a, Hd_b> and <VZ d_a, VZ d_b> (a, b in {1, 2}).
 // ---------------------------------------------------------------------------
-template <typename T, int KZ, int R>
+template <typename T, int KZ, int R, int TYK>
 __global__ void __launch_bounds__(NT)
 k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double *__restrict__ partials)
 {
+    constexpr int NRK = TYK / (NT / TX);
     if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
-    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    constexpr int W = TX + 2 * R, H = TYK + 2 * R;
     __shared__ T A1[padded<W, H>()];
     __shared__ T A2[padded<W, H>()];
     __shared__ T B1[padded<TX, H>()];
@@ -455,7 +456,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
 
     const Item it = items[blockIdx.z];
     const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
     const T *__restrict__ gg = s.g;
@@ -491,9 +492,9 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     xpass<T, R, W, TX, H, R, false>(A1, B1, wx);
     xpass<T, R, W, TX, H, R, false>(A2, B2, wx);
     __syncthreads();
-    T h1[RPT], h2[RPT];
-    ypass_out<T, R, TX, R, false>(B1, h1, wy);
-    ypass_out<T, R, TX, R, false>(B2, h2, wy);
+    T h1[NRK], h2[NRK];
+    ypass_out<T, R, TX, R, false, NRK>(B1, h1, wy);
+    ypass_out<T, R, TX, R, false, NRK>(B2, h2, wy);
 
     double qs[NQD];
 #pragma unroll
@@ -501,7 +502,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     const bool ink = (k >= z0 && k < z1);
     const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) {
+    for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
         const double a = (double)h1[e], b = (double)h2[e];
@@ -540,21 +541,22 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
 // are read from dp[0] and written to dp[1], so a workgroup reading its
 // neighbours' halo never sees a half-updated step.
 // ---------------------------------------------------------------------------
-template <typename T, int KZ, int R>
+template <typename T, int KZ, int R, int TYK>
 __global__ void __launch_bounds__(NT)
 k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
          const Item *__restrict__ items, const double *__restrict__ u, int mode)
 {
+    constexpr int NRK = TYK / (NT / TX);
     if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
-    constexpr int W1 = TX + 4 * R, H1 = TY + 4 * R;  // z-combined source, 2R halo
-    constexpr int W2 = TX + 2 * R, H2 = TY + 2 * R;  // H v, R halo
+    constexpr int W1 = TX + 4 * R, H1 = TYK + 4 * R;  // z-combined source, 2R halo
+    constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R;  // H v, R halo
     __shared__ T A[padded<W1, H1>()];                // z-combined source, later H v
     __shared__ T B[padded<W2, H1>()];                // forward x pass, later adjoint x pass
 
     const Item it = items[blockIdx.z];
     const int m = it.k, z0 = it.z0, z1 = it.z0 + it.n;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
     const T *wz = s.gz + (size_t)m * KZ;
@@ -627,10 +629,10 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     xpass<T, R, W2, TX, H2, R, true>(A, B, wx);
     __syncthreads();
     // 5. adjoint y pass into registers
-    T v[RPT];
-    ypass_out<T, R, TX, R, true>(B, v, wy);
+    T v[NRK];
+    ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) {
+    for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
         const size_t o = vidx(g, m, j, i);
@@ -650,20 +652,21 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
 // ---------------------------------------------------------------------------
 // out_k = (H in)_k - sub_k per item; optional per-slot sums of out^2.
 // ---------------------------------------------------------------------------
-template <typename T, int KZ, int R>
+template <typename T, int KZ, int R, int TYK>
 __global__ void __launch_bounds__(NT)
 k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, T *__restrict__ out,
     const Item *__restrict__ items, double *__restrict__ partials)
 {
+    constexpr int NRK = TYK / (NT / TX);
     if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
-    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    constexpr int W = TX + 2 * R, H = TYK + 2 * R;
     __shared__ T A[padded<W, H>()];
     __shared__ T B[padded<TX, H>()];
     __shared__ double red[NT / 64];
     const Item it = items[blockIdx.z];
     const int k = it.k;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
     const T *wz = s.gz + (size_t)k * KZ;
@@ -690,11 +693,11 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
     __syncthreads();
     xpass<T, R, W, TX, H, R, false>(A, B, wx);
     __syncthreads();
-    T h[RPT];
-    ypass_out<T, R, TX, R, false>(B, h, wy);
+    T h[NRK];
+    ypass_out<T, R, TX, R, false, NRK>(B, h, wy);
     double ss[1] = {0.0};
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) {
+    for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row(e), i = x0 + tx;
         if (i < g.nx && j < g.ny) {
             const size_t o = vidx(g, k, j, i);
@@ -709,18 +712,19 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
 // ---------------------------------------------------------------------------
 // out_m = XY^T_m in_m per item (adjoint in-slice blur with slice m's factors).
 // ---------------------------------------------------------------------------
-template <typename T, int R>
+template <typename T, int R, int TYK>
 __global__ void __launch_bounds__(NT)
 k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
         const Item *__restrict__ items)
 {
+    constexpr int NRK = TYK / (NT / TX);
     constexpr int K = 2 * R + 1;
-    constexpr int W = TX + 2 * R, H = TY + 2 * R;
+    constexpr int W = TX + 2 * R, H = TYK + 2 * R;
     __shared__ T A[padded<W, H>()];
     __shared__ T B[padded<TX, H>()];
     const Item it = items[blockIdx.z];
     const int m = it.k;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     T wx[K], wy[K];
     load_taps<T, R>(wx, s.gx + (size_t)m * K);
@@ -737,10 +741,10 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
     __syncthreads();
     xpass<T, R, W, TX, H, R, true>(A, B, wx);
     __syncthreads();
-    T v[RPT];
-    ypass_out<T, R, TX, R, true>(B, v, wy);
+    T v[NRK];
+    ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) {
+    for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row(e), i = x0 + tx;
         if (i < g.nx && j < g.ny) out[vidx(g, m, j, i)] = v[e];
     }
@@ -821,7 +825,25 @@ __global__ void __launch_bounds__(NT) k_copy(const uint4 *__restrict__ src, uint
     default: return hipErrorInvalidValue;          \
     }
 
-static dim3 grid_of(const Geom &g, int nitems) { return dim3(g.ntx, g.nty, nitems); }
+static dim3 grid_of(const Geom &g, int nitems, int ty = TY)
+{
+    return dim3(g.ntx, (g.ny + ty - 1) / ty, nitems);
+}
+
+// Tile heights: 16 or 32 rows in single precision; double precision keeps 16
+// (two 32-row double tiles of the direction pass would not fit the LDS budget).
+#define BD3MG_TY_SWITCH(ty, CALL)                                  \
+    if constexpr (sizeof(T) == 8) {                                \
+        if (ty != 16) return hipErrorInvalidValue;                 \
+        constexpr int TYK = 16;                                    \
+        CALL;                                                      \
+    } else {                                                       \
+        switch (ty) {                                              \
+        case 16: { constexpr int TYK = 16; CALL; } break;          \
+        case 32: { constexpr int TYK = 32; CALL; } break;          \
+        default: return hipErrorInvalidValue;                      \
+        }                                                          \
+    }
 
 template <typename T>
 hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *q, const T *x,
@@ -839,9 +861,9 @@ hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, c
                        int nitems, double *partials, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R,
-                    hipLaunchKernelGGL((k_dirs<T, KZ, R>), grid_of(g, nitems), dim3(NT), 0, st, g,
-                                       prm, s, items, partials)));
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
+                    hipLaunchKernelGGL((k_dirs<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                                       st, g, prm, s, items, partials))));
     return hipGetLastError();
 }
 
@@ -850,9 +872,9 @@ hipError_t launch_update(const Geom &g, const DevState<T> &s, const T *src, T *q
                          int nitems, const double *u, int mode, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R,
-                    hipLaunchKernelGGL((k_update<T, KZ, R>), grid_of(g, nitems), dim3(NT), 0, st, g,
-                                       s, src, qout, items, u, mode)));
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
+                    hipLaunchKernelGGL((k_update<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                                       st, g, s, src, qout, items, u, mode))));
     return hipGetLastError();
 }
 
@@ -861,9 +883,9 @@ hipError_t launch_H(const Geom &g, const DevState<T> &s, const T *in, const T *s
                     const Item *items, int nitems, double *partials, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R,
-                    hipLaunchKernelGGL((k_H<T, KZ, R>), grid_of(g, nitems), dim3(NT), 0, st, g, s,
-                                       in, sub, out, items, partials)));
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_aux,
+                    hipLaunchKernelGGL((k_H<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
+                                       g, s, in, sub, out, items, partials))));
     return hipGetLastError();
 }
 
@@ -872,16 +894,19 @@ hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out
                         int nitems, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    BD3MG_R_SWITCH(g.R, hipLaunchKernelGGL((k_blurT<T, R>), grid_of(g, nitems), dim3(NT), 0, st, g,
-                                           s, in, out, items));
+    BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_aux,
+                   hipLaunchKernelGGL((k_blurT<T, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
+                                      g, s, in, out, items)));
     return hipGetLastError();
 }
 
-hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles, const double *pg,
-                        const double *pd, double *u, double *info, const int *stop, hipStream_t st)
+hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles_g, int ntiles_d,
+                        const double *pg, const double *pd, double *u, double *info, const int *stop,
+                        hipStream_t st)
 {
     if (nbr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_solve, dim3(nbr), dim3(NT), 0, st, prm, br, ntiles, pg, pd, u, info, stop);
+    hipLaunchKernelGGL(k_solve, dim3(nbr), dim3(NT), 0, st, prm, br, ntiles_g, ntiles_d, pg, pd, u, info,
+                       stop);
     return hipGetLastError();
 }
 

@@ -32,10 +32,11 @@ def cases():
 
 
 @pytest.mark.parametrize("shape,ks", cases())
-@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
-def test_H_HT_parity(orc, shape, ks, prec):
+@pytest.mark.parametrize("prec,rows", [(binding.FP64, 16), (binding.FP32, 16), (binding.FP32, 32)])
+def test_H_HT_parity(orc, shape, ks, prec, rows):
     g, o, y = pair(orc, shape, prec, seed=sum(shape) + sum(ks), kx=ks[0], ky=ks[1], kz=ks[2],
                    tables="asym")
+    g.set_option(binding.OPT_TILE_ROWS_AUX, rows)
     rng = np.random.default_rng(7)
     v = rng.standard_normal(shape)
     if prec == binding.FP32:
@@ -48,11 +49,12 @@ def test_H_HT_parity(orc, shape, ks, prec):
 
 
 @pytest.mark.parametrize("shape,ks", cases()[:6])
-@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
+@pytest.mark.parametrize("prec,rows", [(binding.FP64, 16), (binding.FP32, 16), (binding.FP32, 32)])
 @pytest.mark.parametrize("kappa", [0.0, 0.05])
-def test_grad_parity(orc, shape, ks, prec, kappa):
+def test_grad_parity(orc, shape, ks, prec, rows, kappa):
     g, o, y = pair(orc, shape, prec, seed=3 + sum(shape), kx=ks[0], ky=ks[1], kz=ks[2],
                    lam=0.02, delta=0.05, eta=0.5, kappa=kappa)
+    g.set_option(binding.OPT_TILE_ROWS_UPDATE, rows)
     rng = np.random.default_rng(11)
     x = rng.uniform(-0.2, 1.2, size=shape)
     if prec == binding.FP32:

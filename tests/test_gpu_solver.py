@@ -211,3 +211,33 @@ def test_errors_through_the_interface(orc):
     with pytest.raises(binding.Bd3mgError) as e:
         g.set_psf_separable(np.ones((4, 11)), np.ones((4, 3)), np.ones((4, 3)))
     assert e.value.status == binding.ERR_ARG
+
+
+def test_tile_heights_agree_and_autotune_keeps_state(orc):
+    g, o, y, w = _c1(orc, inputs.small_plain_fp64(), _c1_y(orc), binding.FP32)
+    nc, order, color = g.get_schedule()
+    res = {}
+    for ty in (16, 32):
+        for opt in (binding.OPT_TILE_ROWS_DIRS, binding.OPT_TILE_ROWS_UPDATE, binding.OPT_TILE_ROWS_AUX):
+            g.set_option(opt, ty)
+        g.set_x0(None)
+        g.run(20)
+        res[ty] = g.get_x()
+    assert rel(res[16], res[32]) <= 1e-5
+    x = y.copy()
+    d = np.zeros(w.shape)
+    o.run(x, d, w.nslices, order, 20, history=False)
+    assert rel(res[32], x) <= 2e-4
+    # the autotuner leaves the solver state where it was
+    before = g.get_state()
+    (td, tu), ms = g.autotune(2)
+    assert td in (16, 32) and tu in (16, 32) and ms > 0
+    after = g.get_state()
+    for a, b in zip(before[:3], after[:3]):
+        assert np.array_equal(a, b)
+    assert before[3] == after[3]
+    with pytest.raises(binding.Bd3mgError):
+        g.set_option(binding.OPT_TILE_ROWS_DIRS, 24)
+    g64 = binding.Problem(8, 8, 4, binding.FP64)
+    with pytest.raises(binding.Bd3mgError):
+        g64.set_option(binding.OPT_TILE_ROWS_UPDATE, 32)
