@@ -1,6 +1,11 @@
 import os
 import sys
 
+# The oracle's OpenMP loops are short on test-sized volumes; a few passive
+# threads keep them fast even when other work shares the host.
+os.environ.setdefault("OMP_NUM_THREADS", "2")
+os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
