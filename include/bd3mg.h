@@ -236,6 +236,34 @@ bd3mg_status bd3mg_get_profile(bd3mg_problem p, long long *launches, double *ms,
  * buffers.  ERR_ARG: bytes < 1 MiB or iters < 1. */
 bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent problems (own sizes, PSF, data, parameters and
+ * block partitions) advanced together.  Each problem's sweep is captured on
+ * its own stream into one HIP graph (fork/join), so one graph launch runs two
+ * sweeps of every problem with the problems as parallel branches.
+ * ------------------------------------------------------------------------- */
+typedef struct bd3mg_batch_s *bd3mg_batch;
+
+/* Group n problems (each fully set up: PSF, data, blocks) into a batch.  The
+ * batch keeps the handles, which must outlive it and must not be run on their
+ * own while it exists.  ERR_ARG: n < 1 or a NULL or repeated handle;
+ * ERR_STATE: a problem not set up. */
+bd3mg_status bd3mg_batch_create(int n, const bd3mg_problem *probs, bd3mg_batch *out);
+bd3mg_status bd3mg_batch_destroy(bd3mg_batch b);
+
+/* Run bd3mg_autotune on every problem of the batch (tile heights per shape). */
+bd3mg_status bd3mg_batch_tune(bd3mg_batch b);
+
+/* Advance every problem by max_sweeps sweeps (graph launches of two sweeps,
+ * then one direct sweep when max_sweeps is odd).  With grad_rtol > 0 the
+ * problems are checked every check_every sweeps (rounded up to an even
+ * number); a converged problem stops and the graph is rebuilt for the rest.
+ * results[n] (may be NULL) receive per-problem outcomes, f and ||grad f||
+ * evaluated at the end.  ERR_NOT_CONVERGED when some problem missed the
+ * tolerance (states still valid). */
+bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, int check_every,
+                             bd3mg_result *results);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,10 @@ SIGNATURES = {
     "bd3mg_apply": ([_dp, _i, _dp, _dp, _i], C.c_int),
     "bd3mg_block_step": ([_dp, _i, _dp], C.c_int),
     "bd3mg_probe_copy": ([C.c_size_t, _i, _dp, _dp], C.c_int),
+    "bd3mg_batch_create": ([_i, _dp, C.POINTER(_dp)], C.c_int),
+    "bd3mg_batch_destroy": ([_dp], C.c_int),
+    "bd3mg_batch_tune": ([_dp], C.c_int),
+    "bd3mg_batch_run": ([_dp, _i, _d, _i, _dp], C.c_int),
 }
 
 
@@ -269,3 +273,35 @@ class Problem:
         info = np.zeros(8)
         _check(load().bd3mg_block_step(self._h, b, info.ctypes.data))
         return info
+
+
+class Batch:
+    """Several fully set-up problems advanced together (one HIP graph launch
+    runs two sweeps of every problem).  Keeps references to its problems."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (_dp * len(self.problems))(*[p._h for p in self.problems])
+        h = _dp()
+        _check(load().bd3mg_batch_create(len(self.problems), arr, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bd3mg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tune(self):
+        _check(load().bd3mg_batch_tune(self._h))
+
+    def run(self, max_sweeps, grad_rtol=0.0, check_every=0):
+        res = (Result * len(self.problems))()
+        _check(load().bd3mg_batch_run(self._h, int(max_sweeps), float(grad_rtol), int(check_every), res),
+               allow=(ERR_NOT_CONVERGED,))
+        return [r.as_dict() for r in res]

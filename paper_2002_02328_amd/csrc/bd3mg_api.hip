@@ -1081,3 +1081,213 @@ bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms)
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+struct bd3mg_batch_s {
+    std::vector<bd3mg_problem> probs;
+    hipStream_t s0 = nullptr;
+    hipEvent_t fork = nullptr, ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> join;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<char> captured;  // problems in the graph
+    std::vector<int> cap_cur;    // their previous-step buffer at capture
+};
+
+namespace {
+
+void batch_drop_graph(bd3mg_batch b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Capture two sweeps of every active problem, each problem on its own stream
+// between a fork and a join event of the batch stream, into one graph.
+bd3mg_status batch_capture(bd3mg_batch b, const std::vector<char> &active)
+{
+    batch_drop_graph(b);
+    HIP_TRY(hipStreamBeginCapture(b->s0, hipStreamCaptureModeRelaxed));
+    bd3mg_status st = BD3MG_OK;
+    if (hipEventRecord(b->fork, b->s0) != hipSuccess) st = fail(BD3MG_ERR_HIP, "fork record failed");
+    for (size_t i = 0; i < b->probs.size() && st == BD3MG_OK; ++i) {
+        if (!active[i]) continue;
+        bd3mg_problem p = b->probs[i];
+        if (hipStreamWaitEvent(p->stream, b->fork, 0) != hipSuccess) {
+            st = fail(BD3MG_ERR_HIP, "fork wait failed");
+            break;
+        }
+        for (int sw = 0; sw < 2 && st == BD3MG_OK; ++sw) {
+            for (int c = 0; c < p->ncolors && st == BD3MG_OK; ++c) st = phase(p, p->groups[c], false);
+            p->cur ^= 1;
+        }
+        if (st == BD3MG_OK && (hipEventRecord(b->join[i], p->stream) != hipSuccess ||
+                               hipStreamWaitEvent(b->s0, b->join[i], 0) != hipSuccess))
+            st = fail(BD3MG_ERR_HIP, "join failed");
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->s0, &g);
+    if (st != BD3MG_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(BD3MG_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->captured = active;
+    for (size_t i = 0; i < b->probs.size(); ++i) b->cap_cur[i] = b->probs[i]->cur;
+    return BD3MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bd3mg_status bd3mg_batch_create(int n, const bd3mg_problem *probs, bd3mg_batch *out)
+{
+    if (!out) return fail(BD3MG_ERR_ARG, "null output handle");
+    *out = nullptr;
+    if (n < 1 || !probs) return fail(BD3MG_ERR_ARG, "need n >= 1 problems");
+    for (int i = 0; i < n; ++i) {
+        if (!probs[i]) return fail(BD3MG_ERR_ARG, "problem %d is null", i);
+        for (int j = 0; j < i; ++j)
+            if (probs[j] == probs[i]) return fail(BD3MG_ERR_ARG, "problem %d repeated", i);
+        ST_TRY(ensure_ready(probs[i]));
+    }
+    bd3mg_batch b = new (std::nothrow) bd3mg_batch_s;
+    if (!b) return fail(BD3MG_ERR_NOMEM, "batch handle");
+    b->probs.assign(probs, probs + n);
+    b->join.assign(n, nullptr);
+    b->captured.assign(n, 0);
+    b->cap_cur.assign(n, -1);
+    bool ok = hipStreamCreateWithFlags(&b->s0, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreate(&b->ev0) == hipSuccess && hipEventCreate(&b->ev1) == hipSuccess;
+    for (int i = 0; i < n && ok; ++i)
+        ok = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        bd3mg_batch_destroy(b);
+        return fail(BD3MG_ERR_HIP, "batch stream or events");
+    }
+    *out = b;
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_batch_destroy(bd3mg_batch b)
+{
+    if (!b) return BD3MG_OK;
+    if (b->s0) (void)hipStreamSynchronize(b->s0);
+    batch_drop_graph(b);
+    for (hipEvent_t e : b->join)
+        if (e) (void)hipEventDestroy(e);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->s0) (void)hipStreamDestroy(b->s0);
+    delete b;
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_batch_tune(bd3mg_batch b)
+{
+    if (!b) return fail(BD3MG_ERR_ARG, "null batch");
+    for (bd3mg_problem p : b->probs) ST_TRY(bd3mg_autotune(p, 3, nullptr, nullptr));
+    batch_drop_graph(b);  // tile heights are baked into the captured launches
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, int check_every,
+                             bd3mg_result *results)
+{
+    if (!b) return fail(BD3MG_ERR_ARG, "null batch");
+    if (max_sweeps < 0 || check_every < 0) return fail(BD3MG_ERR_ARG, "negative sweep count");
+    const int n = (int)b->probs.size();
+    for (bd3mg_problem p : b->probs) ST_TRY(ensure_ready(p));
+    const bool stopping = grad_rtol > 0.0;
+    int ce = check_every > 0 ? check_every : 16;
+    ce += ce & 1;  // checks fall between graph launches of two sweeps
+    std::vector<char> active(n, 1), conv(n, 0);
+    std::vector<int> done(n, 0);
+    HIP_TRY(hipEventRecord(b->ev0, b->s0));
+    int s = 0;
+    auto sync_all = [&]() -> bd3mg_status {
+        HIP_TRY(hipStreamSynchronize(b->s0));
+        return BD3MG_OK;
+    };
+    for (; s + 2 <= max_sweeps; s += 2) {
+        bool any = false;
+        for (int i = 0; i < n; ++i) any = any || active[i];
+        if (!any) break;
+        bool recapture = !b->exec || b->captured != active;
+        for (int i = 0; i < n && !recapture; ++i)
+            if (active[i] && b->cap_cur[i] != b->probs[i]->cur) recapture = true;
+        if (recapture) ST_TRY(batch_capture(b, active));
+        HIP_TRY(hipGraphLaunch(b->exec, b->s0));
+        bool need_sync = stopping && ((s + 2) % ce == 0);
+        for (int i = 0; i < n; ++i) {
+            if (!active[i]) continue;
+            bd3mg_problem p = b->probs[i];
+            done[i] += 2;
+            p->sweeps_done += 2;
+            if (p->refresh_every > 0 && p->sweeps_done / p->refresh_every != (p->sweeps_done - 2) / p->refresh_every)
+                need_sync = true;
+        }
+        if (!need_sync) continue;
+        ST_TRY(sync_all());
+        for (int i = 0; i < n; ++i) {
+            if (!active[i]) continue;
+            bd3mg_problem p = b->probs[i];
+            if (p->refresh_every > 0 && p->sweeps_done / p->refresh_every != (p->sweeps_done - 2) / p->refresh_every)
+                ST_TRY(refresh(p, p->x, p->q));
+            if (stopping && (s + 2) % ce == 0) {
+                double gn = 0.0;
+                ST_TRY(eval_at(p, p->x, p->q, nullptr, &gn));
+                if (gn <= grad_rtol * p->gnorm_ref) {
+                    conv[i] = 1;
+                    active[i] = 0;
+                }
+            }
+        }
+        for (int i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(b->probs[i]->stream));
+    }
+    ST_TRY(sync_all());
+    if (s < max_sweeps) {  // one more sweep, launched directly
+        for (int i = 0; i < n; ++i) {
+            if (!active[i]) continue;
+            bd3mg_problem p = b->probs[i];
+            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], false));
+            p->cur ^= 1;
+            done[i] += 1;
+            p->sweeps_done += 1;
+        }
+    }
+    HIP_TRY(hipEventRecord(b->ev1, b->s0));
+    for (int i = 0; i < n; ++i) HIP_TRY(hipStreamSynchronize(b->probs[i]->stream));
+    HIP_TRY(hipEventSynchronize(b->ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+    bool all = true;
+    for (int i = 0; i < n; ++i) {
+        bd3mg_problem p = b->probs[i];
+        double f = 0.0, gn = 0.0;
+        ST_TRY(eval_at(p, p->x, p->q, &f, &gn));
+        if (stopping && !conv[i] && gn <= grad_rtol * p->gnorm_ref) conv[i] = 1;
+        all = all && (conv[i] || !stopping);
+        if (results) {
+            results[i].sweeps = done[i];
+            results[i].converged = conv[i];
+            results[i].f = f;
+            results[i].grad_norm = gn;
+            results[i].grad_norm_ref = p->gnorm_ref;
+            results[i].seconds = ms * 1e-3;
+        }
+    }
+    if (!all) return fail(BD3MG_ERR_NOT_CONVERGED, "some problems of the batch did not converge");
+    return BD3MG_OK;
+}
+
+}  // extern "C"

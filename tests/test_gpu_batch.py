@@ -1,0 +1,116 @@
+"""GPU parity of batched BD3MG: many problems of uneven sizes advanced together
+through one graph launch per two sweeps.
+
+The batch runs the same kernels with the same arguments as single-problem runs,
+so a batched run must equal the single runs bitwise; against the FP64 oracle
+the usual FP64 / FP32 bounds apply (see test_gpu_solver).
+"""
+import numpy as np
+import pytest
+
+from paper_2002_02328_amd import binding, inputs
+from gpu_common import rel, rounded
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(orc, w, prec):
+    gxy = rounded(orc.gauss_table(w.sigma_xy, w.kxy), prec)
+    gz = rounded(orc.gauss_table(w.sigma_z, w.kz), prec)
+    y = rounded(orc.Problem(np.zeros(w.shape), gxy, gxy, gz).H(w.xbar) + w.noise, prec)
+    nz, ny, nx = w.shape
+    g = binding.Problem(nx, ny, nz, prec)
+    g.set_psf_separable(gxy, gxy, gz)
+    g.set_params(w.lam, w.delta, w.eta, w.kappa)
+    g.set_data(y)
+    g.set_blocks(w.nslices)
+    g.set_x0(None)
+    o = orc.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
+    return g, o, y
+
+
+def small_members():
+    return [inputs.tiny((9, 40, 70), 31, kxy=5, kz=5, nblocks=3),
+            inputs.tiny((6, 70, 33), 32, kxy=3, kz=3, nblocks=2),
+            inputs.tiny((12, 17, 130), 33, kxy=7, kz=5, nblocks=4),
+            inputs.tiny((5, 64, 64), 34, kxy=9, kz=1, nblocks=5)]
+
+
+@pytest.mark.parametrize("sweeps", [6, 7])
+def test_batch_equals_single_runs_bitwise(orc, sweeps):
+    ws = small_members()
+    single = []
+    for w in ws:
+        g, o, y = setup(orc, w, binding.FP32)
+        g.run(sweeps, check_every=0)
+        single.append(g.get_x())
+    probs = [setup(orc, w, binding.FP32)[0] for w in ws]
+    b = binding.Batch(probs)
+    res = b.run(sweeps)
+    for g, xs, r in zip(probs, single, res):
+        assert r["sweeps"] == sweeps
+        assert np.array_equal(g.get_x(), xs)
+    # a second run continues from the state, as single runs do
+    b.run(2)
+    assert all(g.get_state()[3] == sweeps + 2 for g in probs)
+
+
+def test_batch_fp64_matches_oracle(orc):
+    ws = small_members()[:3]
+    made = [setup(orc, w, binding.FP64) for w in ws]
+    b = binding.Batch([m[0] for m in made])
+    b.run(9)
+    for (g, o, y), w in zip(made, ws):
+        nc, order, _ = g.get_schedule()
+        x = y.copy()
+        d = np.zeros(w.shape)
+        o.run(x, d, w.nslices, order, 9, history=False)
+        assert rel(g.get_x(), x) <= 1e-11
+
+
+def test_batch_stops_converged_problems(orc):
+    ws = small_members()[:3]
+    made = [setup(orc, w, binding.FP64) for w in ws]
+    b = binding.Batch([m[0] for m in made])
+    res = b.run(400, grad_rtol=1e-3, check_every=4)
+    for (g, o, y), w, r in zip(made, ws, res):
+        assert r["converged"] == 1
+        assert r["grad_norm"] <= 1e-3 * r["grad_norm_ref"]
+        assert r["sweeps"] % 4 == 0 and r["sweeps"] < 400
+        # same state as a single run of that many sweeps
+        g2 = setup(orc, w, binding.FP64)[0]
+        g2.run(r["sweeps"], check_every=0)
+        assert np.array_equal(g2.get_x(), g.get_x())
+
+
+def test_batched_uneven_volumes_full_size(orc):
+    """The 16-problem batch (128..256 x 128..256 x 32..96, PSF 7x7x7, 4..16
+    blocks), tuned and run for 50 sweeps: equal to single runs with the same
+    tile heights, and the smallest problem against the oracle."""
+    ws = [inputs.batch_member(p) for p in range(16)]
+    made = [setup(orc, w, binding.FP32) for w in ws]
+    probs = [m[0] for m in made]
+    b = binding.Batch(probs)
+    b.tune()
+    res = b.run(50)
+    assert all(r["sweeps"] == 50 for r in res)
+    nvox = sum(int(np.prod(w.shape)) for w in ws)
+    print("batch: %d volumes, %d voxels, 50 sweeps in %.4f s: %.3e voxel-iterations/s"
+          % (len(ws), nvox, res[0]["seconds"], nvox * 50 / res[0]["seconds"]))
+    # single runs (tile heights as tuned) give the same iterates
+    for i in (0, 7, 15):
+        g = probs[i]
+        xb = g.get_x()
+        g.set_x0(None)
+        g.run(50, check_every=0)
+        assert np.array_equal(g.get_x(), xb), i
+    # smallest problem against the FP64 oracle (3 sweeps)
+    i = int(np.argmin([np.prod(w.shape) for w in ws]))
+    g, o, y = made[i]
+    g.set_x0(None)
+    g.run(3, check_every=0)
+    nc, order, _ = g.get_schedule()
+    x = y.copy()
+    d = np.zeros(ws[i].shape)
+    o.run(x, d, ws[i].nslices, order, 3, history=False)
+    assert rel(g.get_x(), x) <= 2e-5
