@@ -15,6 +15,7 @@ time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y, and the FP64 CPU oracle
 timed on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -38,6 +39,24 @@ def make_problem(binding, w):
     g.set_data(y.astype(g.dtype))
     g.set_blocks(w.nslices)
     return g
+
+
+def measured_traffic(workload, kernel, tile_rows):
+    """HBM bytes per launch of the dominant kernel from the committed PMC record
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when the kernel sources or the tile variant differ from those measured."""
+    path = os.path.join(ROOT, "profiles", "traffic_update.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(workload)
+    if not rec or rec["kernel"] != kernel or rec["tile_rows_update"] != tile_rows:
+        return None
+    h = hashlib.sha256()
+    for f in ("bd3mg_kernels.hip", "bd3mg_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2002_02328_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != rec["kernel_source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
 
 
 def cpu_baseline(w, budget_s):
@@ -77,7 +96,7 @@ def main():
     ap.add_argument("--max-sweeps-to-tol", type=int, default=20000)
     ap.add_argument("--no-tol", action="store_true", help="skip the time-to-tolerance run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -139,7 +158,8 @@ def main():
                    "reductions": "f64", "step": "one sweep (every block updated once)",
                    "tile_rows": {"dirs": td, "update": tu}},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(w.name, dom, tu),
                      "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n},
         "kernels": kernels,
         "sweep_algorithmic_GBps": all_bytes / (total_ms * 1e-3) / 1e9,

@@ -64,6 +64,13 @@ def lib():
         L.orc_run.argtypes = [P, dp, dp, C.c_int, dp, dp, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_run.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
+        L.orcnet_num_params.argtypes = [C.c_int, C.c_int]
+        L.orcnet_num_params.restype = C.c_size_t
+        L.orcnet_round_bf16.argtypes = [C.c_double]
+        L.orcnet_round_bf16.restype = C.c_double
+        L.orcnet_forward.argtypes = [C.c_int, C.c_int, dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
+        L.orcnet_loss_grad.argtypes = [C.c_int, C.c_int, dp, dp, dp, C.c_int, C.c_int, C.c_int, C.c_int, dp]
+        L.orcnet_loss_grad.restype = C.c_double
         _lib = L
     return _lib
 
@@ -216,3 +223,60 @@ def color_schedule(nslices, min_gap):
     color = np.zeros(ns.size, dtype=np.int32)
     nc = lib().orc_color_schedule(int(ns.size), _ptr(ns), int(min_gap), _ptr(order), _ptr(color))
     return int(nc), order, color
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start: the three-level 3D U-Net of convnet_oracle.c.
+# Volumes are [C][D][H][W] (a [D][H][W] array is one channel); parameters are
+# one flat float64 array, layer by layer: weights [Cout][Cin][kd][kh][kw], then
+# bias [Cout].  bf16=True rounds stored activations and weights to bfloat16.
+
+NET_LAYERS = 11
+
+
+def net_layer_shapes(c: int, cin: int = 1):
+    """(cout, cin, k) of every layer, in parameter order."""
+    return [(c, cin, 3), (c, c, 3), (2 * c, c, 3), (2 * c, 2 * c, 3), (4 * c, 2 * c, 3),
+            (4 * c, 4 * c, 3), (2 * c, 4 * c, 3), (2 * c, 4 * c, 3), (c, 2 * c, 3), (c, 2 * c, 3),
+            (1, c, 1)]
+
+
+def net_num_params(c: int, cin: int = 1) -> int:
+    return int(lib().orcnet_num_params(c, cin))
+
+
+def round_bf16(v: float) -> float:
+    return float(lib().orcnet_round_bf16(float(v)))
+
+
+def _vol(x, cin):
+    x = _f64(x)
+    if x.ndim == 3:
+        x = x[None]
+    assert x.ndim == 4 and x.shape[0] == cin, x.shape
+    assert all(s % 4 == 0 for s in x.shape[1:]), "volume sides must be multiples of 4"
+    return np.ascontiguousarray(x)
+
+
+def net_forward(params, x, c: int, cin: int = 1, bf16: bool = False) -> np.ndarray:
+    """x0 = x[channel 0] + net(x); returns [D][H][W]."""
+    params = _f64(params)
+    assert params.size == net_num_params(c, cin)
+    x = _vol(x, cin)
+    _, D, H, W = x.shape
+    out = np.empty((D, H, W))
+    lib().orcnet_forward(c, cin, _ptr(params), _ptr(x), D, H, W, int(bf16), _ptr(out))
+    return out
+
+
+def net_loss_grad(params, x, target, c: int, cin: int = 1, bf16: bool = False):
+    """Mean squared error of x[0] + net(x) against target, and its gradient
+    with respect to the flat parameters."""
+    params = _f64(params)
+    assert params.size == net_num_params(c, cin)
+    x = _vol(x, cin)
+    _, D, H, W = x.shape
+    t = _f64(target).reshape(D, H, W)
+    g = np.empty(params.size)
+    loss = lib().orcnet_loss_grad(c, cin, _ptr(params), _ptr(x), _ptr(t), D, H, W, int(bf16), _ptr(g))
+    return float(loss), g

@@ -1,0 +1,139 @@
+"""Pins of the warm-start network oracle (convnet_oracle.c) against facts that
+do not come from the oracle itself:
+
+* torch's CPU float64 convolution, pooling, nearest upsampling and autograd
+  (an independent library implementation of the same network);
+* central finite differences of the loss;
+* closed forms: zero weights give x0 = y exactly, a head bias alone shifts it;
+* bfloat16 rounding against torch's conversion and hand-worked ties.
+"""
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+import oracle
+
+
+def torch_net(params, x, c, cin):
+    """The same U-Net written with torch.nn.functional (float64, CPU)."""
+    shapes = oracle.net_layer_shapes(c, cin)
+    ws, bs, off = [], [], 0
+    for co, ci, k in shapes:
+        nw = co * ci * k ** 3
+        ws.append(params[off:off + nw].reshape(co, ci, k, k, k))
+        bs.append(params[off + nw:off + nw + co])
+        off += nw + co
+
+    def conv(i, t, relu=True):
+        k = shapes[i][2]
+        o = F.conv3d(t, ws[i], bs[i], padding=k // 2)
+        return F.relu(o) if relu else o
+
+    t = x[None]
+    a1 = conv(0, t)
+    s1 = conv(1, a1)
+    a2 = conv(2, F.avg_pool3d(s1, 2))
+    s2 = conv(3, a2)
+    a3 = conv(4, F.avg_pool3d(s2, 2))
+    b3 = conv(5, a3)
+    c2 = conv(6, F.interpolate(b3, scale_factor=2, mode="nearest"))
+    e2 = conv(7, torch.cat([c2, s2], 1))
+    c1 = conv(8, F.interpolate(e2, scale_factor=2, mode="nearest"))
+    e1 = conv(9, torch.cat([c1, s1], 1))
+    h = conv(10, e1, relu=False)
+    return (t[:, 0:1] + h)[0, 0]
+
+
+def random_params(c, cin, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for co, ci, k in oracle.net_layer_shapes(c, cin):
+        fan = ci * k ** 3
+        out.append(rng.standard_normal(co * ci * k ** 3) * scale * np.sqrt(2.0 / fan))
+        out.append(rng.uniform(-0.1, 0.1, co))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("c,cin,shape", [(2, 1, (4, 8, 12)), (4, 1, (8, 8, 8)), (3, 2, (8, 4, 12))])
+def test_forward_and_gradient_match_torch_autograd(orc, c, cin, shape):
+    rng = np.random.default_rng(sum(shape) + c)
+    p = random_params(c, cin, seed=c + 10 * cin)
+    x = rng.uniform(0, 1, (cin,) + shape)
+    tgt = rng.uniform(0, 1, shape)
+    out = oracle.net_forward(p, x, c, cin)
+    pt = torch.tensor(p, requires_grad=True)
+    ot = torch_net(pt, torch.tensor(x), c, cin)
+    assert np.max(np.abs(out - ot.detach().numpy())) <= 1e-12 * max(1.0, np.max(np.abs(out)))
+    loss, g = oracle.net_loss_grad(p, x, tgt, c, cin)
+    lt = ((ot - torch.tensor(tgt)) ** 2).mean()
+    lt.backward()
+    gt = pt.grad.numpy()
+    assert abs(loss - lt.item()) <= 1e-12 * lt.item()
+    assert np.linalg.norm(g - gt) <= 1e-11 * np.linalg.norm(gt)
+    # every layer's weights and biases receive gradient
+    off = 0
+    for co, ci, k in oracle.net_layer_shapes(c, cin):
+        nw = co * ci * k ** 3
+        assert np.any(g[off:off + nw] != 0) and np.any(g[off + nw:off + nw + co] != 0)
+        off += nw + co
+
+
+def test_gradient_central_differences(orc):
+    c, cin, shape = 2, 1, (4, 8, 8)
+    rng = np.random.default_rng(5)
+    p = random_params(c, cin, seed=3)
+    x = rng.uniform(0, 1, shape)
+    tgt = rng.uniform(0, 1, shape)
+    loss, g = oracle.net_loss_grad(p, x, tgt, c, cin)
+    idx = rng.choice(p.size, 60, replace=False)
+    # every layer's bias and the head
+    idx = np.concatenate([idx, [p.size - 1, p.size - 2]])
+    eps = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += eps
+        pm[i] -= eps
+        fd = (oracle.net_loss_grad(pp, x, tgt, c, cin)[0] - oracle.net_loss_grad(pm, x, tgt, c, cin)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(abs(g[i]), 1e-3 * np.abs(g).max()), i
+
+
+def test_zero_network_is_identity_and_head_bias_shifts(orc):
+    c, cin, shape = 2, 1, (4, 4, 8)
+    x = np.random.default_rng(1).uniform(-1, 1, shape)
+    p = np.zeros(oracle.net_num_params(c, cin))
+    assert np.array_equal(oracle.net_forward(p, x, c, cin), x)
+    p[-1] = 0.25
+    assert np.array_equal(oracle.net_forward(p, x, c, cin), x + 0.25)
+    # a constant target offset: the loss is the squared shift and only the
+    # head bias sees gradient once every hidden activation is zero
+    loss, g = oracle.net_loss_grad(p, x, x, c, cin)
+    assert loss == pytest.approx(0.0625, rel=1e-15)
+    assert g[-1] == pytest.approx(0.5, rel=1e-14)
+    assert np.count_nonzero(g) == 1
+
+
+def test_round_bf16_matches_torch_and_ties_to_even(orc):
+    rng = np.random.default_rng(0)
+    v = np.concatenate([rng.standard_normal(2000) * 10.0 ** rng.integers(-8, 8, 2000),
+                        [0.0, -0.0, 1.0, 65504.0, 3.0e38, 1e-40]])
+    ours = np.array([oracle.round_bf16(a) for a in v])
+    ref = torch.tensor(v, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(ours, ref)
+    u = 2.0 ** -7  # spacing of bfloat16 on [1, 2)
+    assert oracle.round_bf16(1 + u / 2) == 1.0             # tie, even neighbour below
+    assert oracle.round_bf16(1 + 3 * u / 2) == 1 + 2 * u   # tie, even neighbour above
+    assert oracle.round_bf16(1 + u / 2 + 2 ** -20) == 1 + u
+
+
+def test_bf16_network_is_close_to_fp64(orc):
+    c, cin, shape = 4, 1, (8, 8, 8)
+    rng = np.random.default_rng(8)
+    p = random_params(c, cin, seed=9)
+    x = rng.uniform(0, 1, shape)
+    a = oracle.net_forward(p, x, c, cin)
+    b = oracle.net_forward(p, x, c, cin, bf16=True)
+    h = a - x
+    # ten or so roundings of relative size 2^-9 along each path
+    assert np.max(np.abs(a - b)) <= 20 * 2.0 ** -9 * np.max(np.abs(h)) + 2.0 ** -9
+    assert np.max(np.abs(a - b)) > 0

@@ -12,6 +12,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "bd3mg_oracle.c")
+NET_SRC = os.path.join(ROOT, "oracle", "convnet_oracle.c")
 
 MUTATIONS = {
     "box-gradient-factor": ("acc += 2.0 * p->eta * (x[v]", "acc += 1.0 * p->eta * (x[v]"),
@@ -34,19 +35,44 @@ MUTATIONS = {
     "z-penalty-factor": ("acc += 2.0 * p->kappa * zz;", "acc += p->kappa * zz;"),
 }
 
+NET_MUTATIONS = {
+    "net-skip-concat-dropped": ("memcpy(A->cat1 + c * V1, A->s1, c * V1 * sizeof(double));",
+                                "memset(A->cat1 + c * V1, 0, c * V1 * sizeof(double));"),
+    "net-pool-divisor": ("out[(((size_t)c * d + z) * h + y) * w + x] = s / 8.0;",
+                         "out[(((size_t)c * d + z) * h + y) * w + x] = s / 4.0;"),
+    "net-conv-tap-flipped": ("const int zz = z + a - r, yy = y + bb - r, xx = x + cc - r;\n"
+                             "                                    if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;\n"
+                             "                                    const double wv",
+                             "const int zz = z - a + r, yy = y + bb - r, xx = x + cc - r;\n"
+                             "                                    if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;\n"
+                             "                                    const double wv"),
+    "net-relu-mask-on-wrong-tensor": ("relu_bwd(A.c1, gc1, c * V1);", "relu_bwd(A.e1, gc1, c * V1);"),
+    "net-skip-gradient-dropped": ("for (size_t i = 0; i < 2 * c * V2; ++i) gs2[i] += gcat2[2 * c * V2 + i];",
+                                  "(void)gcat2;"),
+    "net-bf16-ties-away": ("u += 0x7fffu + lsb;", "u += 0x8000u; (void)lsb;"),
+}
 
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
-def test_pins_catch_planted_mistake(name, tmp_path):
-    old, new = MUTATIONS[name]
-    src = open(SRC).read()
+PIN_FILES = {SRC: "test_oracle_pins.py", NET_SRC: "test_oracle_convnet.py"}
+
+
+def _cases():
+    return [(SRC, n, MUTATIONS[n]) for n in sorted(MUTATIONS)] + \
+           [(NET_SRC, n, NET_MUTATIONS[n]) for n in sorted(NET_MUTATIONS)]
+
+
+@pytest.mark.parametrize("path,name,edit", _cases(), ids=[c[1] for c in _cases()])
+def test_pins_catch_planted_mistake(path, name, edit, tmp_path):
+    old, new = edit
+    src = open(path).read()
     assert src.count(old) == 1, name
     mut = tmp_path / "mut.c"
     mut.write_text(src.replace(old, new))
+    others = [s for s in PIN_FILES if s != path]
     lib = tmp_path / "libmut.so"
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                    "-o", str(lib), str(mut), "-lm"], check=True)
+                    "-o", str(lib), str(mut)] + others + ["-lm"], check=True)
     env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                          os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                          os.path.join(ROOT, "tests", PIN_FILES[path])],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert res.returncode != 0, "pins did not catch mutation %s\n%s" % (name, res.stdout[-2000:])
