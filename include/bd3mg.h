@@ -264,6 +264,81 @@ bd3mg_status bd3mg_batch_tune(bd3mg_batch b);
 bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, int check_every,
                              bd3mg_result *results);
 
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start (an addition to the paper's method, which starts from a
+ * given x^0; Sec. 2.3 leaves the start point free).  A three-level 3D U-Net
+ * maps the observation y to a start point x^0 = y + net(y) that is close to
+ * the minimiser, so that BD3MG needs fewer sweeps to reach a tolerance.
+ *
+ * Network (base width c = 16, one input channel; every convolution 3x3x3 with
+ * zero padding and a bias, followed by ReLU, except the head):
+ *   a1 = conv(y; 1->c)     s1 = conv(a1; c->c)      p1 = avgpool2(s1)
+ *   a2 = conv(p1; c->2c)   s2 = conv(a2; 2c->2c)    p2 = avgpool2(s2)
+ *   a3 = conv(p2; 2c->4c)  b3 = conv(a3; 4c->4c)
+ *   c2 = conv(up2(b3); 4c->2c)   e2 = conv([c2, s2]; 4c->2c)
+ *   c1 = conv(up2(e2); 2c->c)    e1 = conv([c1, s1]; 2c->c)
+ *   x0 = y + conv1x1(e1; c->1)   (no ReLU)
+ * avgpool2 averages 2x2x2 cells, up2 repeats every voxel over a 2x2x2 cell,
+ * [a, b] stacks channels.  Volume sides must be multiples of 4.
+ *
+ * Parameters: one float array, layer by layer in the order above, each layer
+ * its weights [cout][cin][kd][kh][kw] followed by its bias [cout] (353,281
+ * values for c = 16).  Arithmetic: activations and weights are stored as
+ * bfloat16 (round to nearest even) and multiplied on the matrix cores with
+ * float accumulation; biases, the head and its residual add are float; the
+ * input y of the first layer is rounded to bfloat16, the residual uses y as
+ * given.  Training: mean squared error of x0 against a target x*, averaged
+ * over every voxel of the batch, and Adam (beta1 0.9, beta2 0.999, eps 1e-8)
+ * on float master parameters.
+ *
+ * Batches of nb volumes are float arrays [nb][nz][ny][nx].  The handle owns
+ * device buffers sized for the last batch shape it saw and reallocates them
+ * when the shape changes.
+ * ------------------------------------------------------------------------- */
+typedef struct bd3mg_net_s *bd3mg_net;
+
+/* levels must be 3, base_channels 16 and in_channels 1 (ERR_ARG otherwise).
+ * The parameters start at zero (x0 = y) until set or loaded. */
+bd3mg_status bd3mg_net_create(int levels, int base_channels, int in_channels, bd3mg_net *out);
+bd3mg_status bd3mg_net_destroy(bd3mg_net n);
+bd3mg_status bd3mg_net_num_params(bd3mg_net n, size_t *count);
+
+/* Host arrays of exactly num_params floats.  set_params resets Adam.
+ * ERR_ARG: wrong count or a non-finite value. */
+bd3mg_status bd3mg_net_set_params(bd3mg_net n, const float *params, size_t count);
+bd3mg_status bd3mg_net_get_params(bd3mg_net n, float *params, size_t count);
+
+/* Serialised parameters: six uint32 (magic "BD3N", version 1, levels, base
+ * channels, input channels, parameter count) followed by the float
+ * parameters, little endian.  save with blob == NULL stores the size in
+ * *bytes; otherwise *bytes is the capacity on entry and the size written on
+ * return.  load checks the header against the handle (ERR_ARG on mismatch)
+ * and resets Adam. */
+bd3mg_status bd3mg_net_save(bd3mg_net n, void *blob, size_t *bytes);
+bd3mg_status bd3mg_net_load(bd3mg_net n, const void *blob, size_t bytes);
+
+/* x0 = y + net(y) for a batch of nb volumes (float, host or device). */
+bd3mg_status bd3mg_net_forward(bd3mg_net n, int nb, int nx, int ny, int nz, const float *y,
+                               float *x0, int on_device);
+
+/* Start a problem from the network: like bd3mg_set_x0 with x0 = y + net(y),
+ * y the problem's data (FP64 problems are rounded to float for the network
+ * and the result widened back).  ERR_STATE: the problem has no data;
+ * ERR_ARG: sides not multiples of 4. */
+bd3mg_status bd3mg_net_infer(bd3mg_net n, bd3mg_problem p);
+
+/* Loss (mean squared error of x0 against xstar) and its gradient with respect
+ * to the parameters (host array of num_params floats, same layout), without
+ * changing the parameters. */
+bd3mg_status bd3mg_net_grad(bd3mg_net n, int nb, int nx, int ny, int nz, const float *y,
+                            const float *xstar, int on_device, float *grad, double *loss);
+
+/* One Adam step with learning rate lr on the batch (y, xstar).  *loss (may
+ * be NULL) receives the loss before the step. */
+bd3mg_status bd3mg_net_train_step(bd3mg_net n, int nb, int nx, int ny, int nz, const float *y,
+                                  const float *xstar, int on_device, float lr, double *loss);
+
 #ifdef __cplusplus
 }
 #endif

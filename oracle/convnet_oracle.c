@@ -25,9 +25,11 @@
  *
  * Tensors are [C][D][H][W].  Parameters are one flat array, layer by layer in
  * the order above: weights [Cout][Cin][kd][kh][kw] then bias [Cout].
- * With bf16 != 0, every stored activation and every weight is rounded to the
- * nearest bfloat16 (ties to even) before use, the storage format of the
- * device implementation; sums stay in FP64.
+ * With bf16 != 0, the copy of the input fed to the first layer, every stored
+ * hidden activation and every weight is rounded to the nearest bfloat16 (ties
+ * to even) before use, the storage format of the device implementation; the
+ * residual add uses the input as given, biases are not rounded, sums stay in
+ * FP64.
  */
 #include <math.h>
 #include <stdint.h>
@@ -237,7 +239,7 @@ static void net_init(net_t *n, int c, int cin0, const double *params, int bf16)
 
 /* Activations of one forward pass. */
 typedef struct {
-    double *in, *a1, *s1, *p1, *a2, *s2, *p2, *a3, *b3, *u2, *c2, *cat2, *e2, *u1, *c1, *cat1, *e1, *h;
+    double *in, *inq, *a1, *s1, *p1, *a2, *s2, *p2, *a3, *b3, *u2, *c2, *cat2, *e2, *u1, *c1, *cat1, *e1, *h;
 } acts_t;
 
 static double *zalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
@@ -246,6 +248,7 @@ static void acts_alloc(acts_t *A, int c, int cin0, int D, int H, int W)
 {
     const size_t V1 = (size_t)D * H * W, V2 = V1 / 8, V3 = V1 / 64;
     A->in = zalloc(cin0 * V1);
+    A->inq = zalloc(cin0 * V1);
     A->a1 = zalloc(c * V1);
     A->s1 = zalloc(c * V1);
     A->p1 = zalloc(c * V2);
@@ -283,8 +286,11 @@ static void forward(const net_t *n, acts_t *A, int c, int cin0, int D, int H, in
 {
     const int D2 = D / 2, H2 = H / 2, W2 = W / 2, D3 = D / 4, H3 = H / 4, W3 = W / 4;
     const size_t V1 = (size_t)D * H * W, V2 = V1 / 8;
-    round_all(A->in, cin0 * V1, bf16);
-    layer_fwd(n, 0, A->in, D, H, W, A->a1, bf16);
+    /* the first layer sees the input in storage precision; the residual
+       x0 = in + h keeps the input as given */
+    memcpy(A->inq, A->in, cin0 * V1 * sizeof(double));
+    round_all(A->inq, cin0 * V1, bf16);
+    layer_fwd(n, 0, A->inq, D, H, W, A->a1, bf16);
     layer_fwd(n, 1, A->a1, D, H, W, A->s1, bf16);
     pool_fwd(A->s1, c, D, H, W, A->p1);
     round_all(A->p1, c * V2, bf16);
@@ -387,7 +393,7 @@ double orcnet_loss_grad(int c, int cin0, const double *params, const double *in,
     relu_bwd(A.s1, gs1, c * V1);
     conv_bwd(&n.L[1], n.w[1], A.a1, gs1, D, H, W, ga1, gw[1], gb[1]);
     relu_bwd(A.a1, ga1, c * V1);
-    conv_bwd(&n.L[0], n.w[0], A.in, ga1, D, H, W, NULL, gw[0], gb[0]);
+    conv_bwd(&n.L[0], n.w[0], A.inq, ga1, D, H, W, NULL, gw[0], gb[0]);
 
     double *tofree[] = {gh, ge1, gcat1, gu1, ge2, gcat2, gu2, gb3, ga3, gp2, gs2, ga2, gp1, gs1, ga1, gc1, gc2};
     for (size_t i = 0; i < sizeof(tofree) / sizeof(tofree[0]); ++i) free(tofree[i]);

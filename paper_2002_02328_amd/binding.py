@@ -55,6 +55,17 @@ SIGNATURES = {
     "bd3mg_batch_destroy": ([_dp], C.c_int),
     "bd3mg_batch_tune": ([_dp], C.c_int),
     "bd3mg_batch_run": ([_dp, _i, _d, _i, _dp], C.c_int),
+    "bd3mg_net_create": ([_i, _i, _i, C.POINTER(_dp)], C.c_int),
+    "bd3mg_net_destroy": ([_dp], C.c_int),
+    "bd3mg_net_num_params": ([_dp, C.POINTER(C.c_size_t)], C.c_int),
+    "bd3mg_net_set_params": ([_dp, _dp, C.c_size_t], C.c_int),
+    "bd3mg_net_get_params": ([_dp, _dp, C.c_size_t], C.c_int),
+    "bd3mg_net_save": ([_dp, _dp, C.POINTER(C.c_size_t)], C.c_int),
+    "bd3mg_net_load": ([_dp, _dp, C.c_size_t], C.c_int),
+    "bd3mg_net_forward": ([_dp, _i, _i, _i, _i, _dp, _dp, _i], C.c_int),
+    "bd3mg_net_infer": ([_dp, _dp], C.c_int),
+    "bd3mg_net_grad": ([_dp, _i, _i, _i, _i, _dp, _dp, _i, _dp, _dp], C.c_int),
+    "bd3mg_net_train_step": ([_dp, _i, _i, _i, _i, _dp, _dp, _i, C.c_float, _dp], C.c_int),
 }
 
 
@@ -305,3 +316,97 @@ class Batch:
         _check(load().bd3mg_batch_run(self._h, int(max_sweeps), float(grad_rtol), int(check_every), res),
                allow=(ERR_NOT_CONVERGED,))
         return [r.as_dict() for r in res]
+
+
+class Net:
+    """Handle of the warm-start network x0 = y + net(y) (three-level 3D U-Net,
+    16 base channels, bf16 matrix-core kernels).  Volumes are float32 arrays
+    (nb, nz, ny, nx) or (nz, ny, nx) on the host, or device addresses with
+    on_device=True and an explicit shape."""
+
+    def __init__(self, levels=3, base_channels=16, in_channels=1):
+        h = _dp()
+        _check(load().bd3mg_net_create(levels, base_channels, in_channels, C.byref(h)))
+        self._h = h
+        n = C.c_size_t()
+        _check(load().bd3mg_net_num_params(self._h, C.byref(n)))
+        self.num_params = n.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().bd3mg_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32).ravel()
+        _check(load().bd3mg_net_set_params(self._h, p.ctypes.data, p.size))
+
+    def get_params(self):
+        p = np.empty(self.num_params, dtype=np.float32)
+        _check(load().bd3mg_net_get_params(self._h, p.ctypes.data, p.size))
+        return p
+
+    def save(self):
+        n = C.c_size_t()
+        _check(load().bd3mg_net_save(self._h, None, C.byref(n)))
+        buf = (C.c_char * n.value)()
+        _check(load().bd3mg_net_save(self._h, buf, C.byref(n)))
+        return bytes(buf[:n.value])
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(load().bd3mg_net_load(self._h, buf, len(blob)))
+
+    @staticmethod
+    def _batch(a, shape, on_device):
+        if on_device:
+            nb, nz, ny, nx = shape
+            return C.c_void_p(int(a)), None, (nb, nz, ny, nx)
+        arr = np.ascontiguousarray(a, dtype=np.float32)
+        if arr.ndim == 3:
+            arr = arr[None]
+        if arr.ndim != 4:
+            raise ValueError("expected (nb, nz, ny, nx) or (nz, ny, nx)")
+        return C.c_void_p(arr.ctypes.data), arr, arr.shape
+
+    def forward(self, y, on_device=False, shape=None, out=None):
+        ptr, keep, (nb, nz, ny, nx) = self._batch(y, shape, on_device)
+        if on_device:
+            _check(load().bd3mg_net_forward(self._h, nb, nx, ny, nz, ptr, C.c_void_p(int(out)), 1))
+            return out
+        res = np.empty((nb, nz, ny, nx), dtype=np.float32)
+        _check(load().bd3mg_net_forward(self._h, nb, nx, ny, nz, ptr, res.ctypes.data, 0))
+        return res if np.ndim(y) == 4 else res[0]
+
+    def infer(self, problem):
+        """Set problem's start point to y + net(y)."""
+        _check(load().bd3mg_net_infer(self._h, problem._h))
+
+    def grad(self, y, xstar, on_device=False, shape=None):
+        py, ky, sh = self._batch(y, shape, on_device)
+        pt, kt, sh2 = self._batch(xstar, shape, on_device)
+        if sh != sh2:
+            raise ValueError("y and xstar shapes differ")
+        nb, nz, ny, nx = sh
+        g = np.empty(self.num_params, dtype=np.float32)
+        loss = C.c_double()
+        _check(load().bd3mg_net_grad(self._h, nb, nx, ny, nz, py, pt, int(on_device), g.ctypes.data,
+                                     C.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, y, xstar, lr, on_device=False, shape=None, want_loss=True):
+        py, ky, sh = self._batch(y, shape, on_device)
+        pt, kt, sh2 = self._batch(xstar, shape, on_device)
+        if sh != sh2:
+            raise ValueError("y and xstar shapes differ")
+        nb, nz, ny, nx = sh
+        loss = C.c_double()
+        _check(load().bd3mg_net_train_step(self._h, nb, nx, ny, nz, py, pt, int(on_device), float(lr),
+                                           C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbd3mg.so")
-SOURCES = ["csrc/bd3mg_kernels.hip", "csrc/bd3mg_api.hip"]
+SOURCES = ["csrc/bd3mg_kernels.hip", "csrc/bd3mg_api.hip", "csrc/net_kernels.hip", "csrc/net_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

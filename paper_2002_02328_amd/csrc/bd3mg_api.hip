@@ -21,7 +21,7 @@
 
 using namespace bd3mg;
 
-namespace {
+namespace bd3mg {
 
 thread_local std::string g_err;
 
@@ -36,21 +36,7 @@ bd3mg_status fail(bd3mg_status st, const char *fmt, ...)
     return st;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail(BD3MG_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),       \
-                        __FILE__, __LINE__);                                                 \
-    } while (0)
-
-#define ST_TRY(expr)                                   \
-    do {                                               \
-        bd3mg_status s_ = (expr);                      \
-        if (s_ != BD3MG_OK) return s_;                 \
-    } while (0)
-
-}  // namespace
+}  // namespace bd3mg
 
 struct bd3mg_problem_s {
     int nx = 0, ny = 0, nz = 0, prec = 0;
@@ -535,6 +521,13 @@ bd3mg_status validate_handle(bd3mg_problem p)
 }
 
 }  // namespace
+
+bd3mg_status bd3mg::problem_view(bd3mg_problem p, ProblemView *v)
+{
+    ST_TRY(validate_handle(p));
+    *v = ProblemView{p->nx, p->ny, p->nz, p->prec, p->data_set, p->y, p->stream};
+    return BD3MG_OK;
+}
 
 extern "C" {
 

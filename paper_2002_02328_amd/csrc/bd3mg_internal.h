@@ -6,7 +6,36 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "../../include/bd3mg.h"
+
 namespace bd3mg {
+
+// Records the thread-local message returned by bd3mg_last_error and returns st.
+bd3mg_status fail(bd3mg_status st, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::bd3mg::fail(BD3MG_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                 __FILE__, __LINE__);                                        \
+    } while (0)
+
+#define ST_TRY(expr)                                   \
+    do {                                               \
+        bd3mg_status s_ = (expr);                      \
+        if (s_ != BD3MG_OK) return s_;                 \
+    } while (0)
+
+// What the warm-start network needs of a problem: its size, precision, data
+// on the device and stream.
+struct ProblemView {
+    int nx, ny, nz, prec;
+    bool data_set;
+    const void *y;
+    hipStream_t stream;
+};
+bd3mg_status problem_view(bd3mg_problem p, ProblemView *v);
 
 // Output tile of one workgroup: TX columns (one wavefront wide) by TY rows;
 // each of the NT threads owns TY / (NT / TX) = 4 outputs of a column.

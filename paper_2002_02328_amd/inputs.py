@@ -182,6 +182,50 @@ def tiny(shape, seed, kxy=3, kz=3, nblocks=None, lam=0.01, delta=0.05, eta=0.01,
                     lam, delta, eta, kappa, nsl, sweeps=10, fp64=True)
 
 
+def warmstart_train_member(t, seed_base=5_000_000):
+    """Training pair t of the learned warm start: a 128x128x32 volume with 25
+    ellipsoids (the ellipsoid density of the 256x256x64 volume), the 256x256x64
+    workload's PSF law and criterion parameters, 8 uneven blocks of 2..6 slices."""
+    base = seed_base + 10 * t
+    shape = (32, 128, 128)
+    rp, rn, rb = _seeds(base)
+    xbar = ellipsoid_phantom(shape, 25, rp)
+    noise = 0.02 * rn.standard_normal(shape)
+    return Workload("warmstart-train-%d" % t, shape, xbar, noise,
+                    linear_schedule(32, 0.5, 3.0), linear_schedule(32, 1.0, 2.0), 7, 7,
+                    0.01, 0.02, 0.01, 0.0, uneven_partition(32, 8, 2, 6, rb), grad_rtol=1e-4)
+
+
+def warmstart_eval_member(e, seed_base=6000):
+    """Evaluation volume e of the learned warm start: a fresh draw of the
+    256x256x64 workload (same law as plain-fp32-256x256x64, other seeds)."""
+    return mid_fp32(seed=seed_base + 10 * e)
+
+
+def net_layer_shapes(c=16, cin=1):
+    """(cout, cin, k) of every layer of the warm-start U-Net, in parameter order."""
+    return [(c, cin, 3), (c, c, 3), (2 * c, c, 3), (2 * c, 2 * c, 3), (4 * c, 2 * c, 3),
+            (4 * c, 4 * c, 3), (2 * c, 4 * c, 3), (2 * c, 4 * c, 3), (c, 2 * c, 3), (c, 2 * c, 3),
+            (1, c, 1)]
+
+
+def net_init_params(seed, c=16, cin=1, head_scale=0.1, bias=0.0):
+    """Seeded starting parameters of the warm-start network (flat float64, the
+    parameter layout of the library): weights N(0, 2 / fan_in), the head's
+    scaled by head_scale so that x0 starts near y, biases constant."""
+    rng = np.random.default_rng(seed)
+    out = []
+    shapes = net_layer_shapes(c, cin)
+    for i, (co, ci, k) in enumerate(shapes):
+        fan = ci * k ** 3
+        w = rng.standard_normal(co * ci * k ** 3) * np.sqrt(2.0 / fan)
+        if i == len(shapes) - 1:
+            w *= head_scale
+        out.append(w)
+        out.append(np.full(co, bias))
+    return np.concatenate(out)
+
+
 WORKLOADS = {
     "plain-fp64-64x64x16": small_plain_fp64,
     "plain-fp32-256x256x64": mid_fp32,

@@ -137,3 +137,39 @@ def test_bf16_network_is_close_to_fp64(orc):
     # ten or so roundings of relative size 2^-9 along each path
     assert np.max(np.abs(a - b)) <= 20 * 2.0 ** -9 * np.max(np.abs(h)) + 2.0 ** -9
     assert np.max(np.abs(a - b)) > 0
+
+
+def _mutant(p, c, cin, layer, how):
+    """Parameters that make the correct network compute what a plausible
+    implementation mistake would: a kernel flipped along z, the two halves of
+    a channel stack swapped, or a square layer's channels transposed."""
+    q = p.copy()
+    off = 0
+    for i, (co, ci, k) in enumerate(oracle.net_layer_shapes(c, cin)):
+        nw = co * ci * k ** 3
+        if i == layer:
+            w = q[off:off + nw].reshape(co, ci, k, k, k)
+            if how == "flip-z":
+                w = w[:, :, ::-1]
+            elif how == "swap-stack":
+                w = np.concatenate([w[:, ci // 2:], w[:, :ci // 2]], axis=1)
+            elif how == "transpose":
+                w = w.transpose(1, 0, 2, 3, 4)
+            q[off:off + nw] = np.ascontiguousarray(w).ravel()
+        off += nw + co
+    return q
+
+
+@pytest.mark.parametrize("layer,how", [(5, "flip-z"), (1, "flip-z"), (9, "swap-stack"),
+                                       (7, "swap-stack"), (3, "transpose")])
+def test_parity_tolerance_discriminates(orc, layer, how):
+    """The GPU network tests accept |h_gpu - h_ref| / |h_ref| <= 2^-6; each
+    mistake above moves the output at least four times that far on the same
+    inputs and parameters."""
+    from paper_2002_02328_amd import inputs
+    c, cin = 16, 1
+    p = inputs.net_init_params(11, c, cin, head_scale=0.3, bias=0.02).astype(np.float32).astype(np.float64)
+    y = np.random.default_rng(3).uniform(0, 1, (8, 20, 36)).astype(np.float32).astype(np.float64)
+    h = oracle.net_forward(p, y, c, cin, bf16=True) - y
+    hm = oracle.net_forward(_mutant(p, c, cin, layer, how), y, c, cin, bf16=True) - y
+    assert np.linalg.norm(hm - h) / np.linalg.norm(h) >= 4 * 2.0 ** -6
