@@ -11,8 +11,9 @@ is formed with the library's own H on the GPU.
 Prints one JSON line: voxel-iterations/s over exactly --steps sweeps (after
 --warmup untimed sweeps), the roofline figure of the dominant kernel (HIP
 events on the library's stream, algorithmic bytes from the library), the
-time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y, and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y and from the learned
+warm start x0 = y + net(y) (network inference inside the clock), and the FP64
+CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -28,6 +29,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel-iterations/s + time-to-f-tolerance (plain vs warm-started), % HBM peak"
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+WEIGHTS = os.path.join(ROOT, "paper_2002_02328_amd", "weights", "warmstart_c16.bin")
+
+
+def net_flops(nvox, c=16):
+    """Multiply-add flops of one forward pass of the warm-start U-Net (3x3x3
+    convolutions at full, half and quarter resolution, 1x1x1 head)."""
+    full = [(1, c), (c, c), (2 * c, c), (2 * c, c)]
+    half = [(c, 2 * c), (2 * c, 2 * c), (4 * c, 2 * c), (4 * c, 2 * c)]
+    quarter = [(2 * c, 4 * c), (4 * c, 4 * c)]
+    per = sum(2 * 27 * a * b for a, b in full) + sum(2 * 27 * a * b for a, b in half) / 8.0 \
+        + sum(2 * 27 * a * b for a, b in quarter) / 64.0 + 2 * c
+    return per * nvox
 
 
 def make_problem(binding, w):
@@ -167,15 +181,41 @@ def main():
     }
 
     if not args.no_tol:
-        g.set_x0(None)
-        t0 = time.perf_counter()
-        res = g.run(args.max_sweeps_to_tol, grad_rtol=args.tol, check_every=1)
-        t1 = time.perf_counter()
-        out["time_to_tol"] = {"plain_x0_y": {"seconds": t1 - t0, "sweeps": res["sweeps"],
-                                             "converged": bool(res["converged"]),
-                                             "grad_rel": res["grad_norm"] / res["grad_norm_ref"],
-                                             "f": res["f"], "tol": args.tol},
-                              "warm_started": None}
+        net = None
+        if os.path.exists(WEIGHTS):
+            net = binding.Net()
+            net.load(open(WEIGHTS, "rb").read())
+            net.infer(g)  # sizes the network's buffers for this volume (untimed)
+
+        def to_tol(tol, warm):
+            g.set_x0(None)
+            t0 = time.perf_counter()
+            if warm:
+                net.infer(g)  # x0 = y + net(y), inside the clock
+            res = g.run(args.max_sweeps_to_tol, grad_rtol=tol, check_every=1)
+            t1 = time.perf_counter()
+            return {"seconds": t1 - t0, "sweeps": res["sweeps"], "converged": bool(res["converged"]),
+                    "grad_rel": res["grad_norm"] / res["grad_norm_ref"], "f": res["f"], "tol": tol}
+
+        tt = {"plain_x0_y": to_tol(args.tol, False), "warm_started": None}
+        if net is not None:
+            tt["warm_started"] = to_tol(args.tol, True)
+            tt["speedup"] = tt["plain_x0_y"]["seconds"] / tt["warm_started"]["seconds"]
+            loose = {"plain_x0_y": to_tol(1e-4, False), "warm_started": to_tol(1e-4, True)}
+            loose["speedup"] = loose["plain_x0_y"]["seconds"] / loose["warm_started"]["seconds"]
+            tt["at_1e-4"] = loose
+            # network inference alone (bf16 matrix cores), averaged over repeats
+            reps = 10
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                net.infer(g)
+            ms = 1e3 * (time.perf_counter() - t0) / reps
+            flop = net_flops(nvox)
+            tt["inference"] = {"ms": ms, "TFLOP/s": flop / (ms * 1e-3) / 1e12,
+                               "frac_bf16_peak": flop / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+                               "flop": flop, "weights": os.path.relpath(WEIGHTS, ROOT)}
+            net.close()
+        out["time_to_tol"] = tt
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
