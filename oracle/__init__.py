@@ -29,6 +29,7 @@ class _Problem(C.Structure):
         ("lam", C.c_double), ("delta", C.c_double), ("eta", C.c_double),
         ("kappa", C.c_double), ("xmin", C.c_double), ("xmax", C.c_double),
         ("dense", C.c_int),
+        ("mu", C.c_double),
     ]
 
 
@@ -63,6 +64,10 @@ def lib():
         L.orc_block_step.argtypes = [P, dp, dp, C.c_int, C.c_int, dp]
         L.orc_run.argtypes = [P, dp, dp, C.c_int, dp, dp, C.c_int, C.c_double, C.c_double, dp, dp]
         L.orc_run.restype = C.c_int
+        L.orc_run_round.argtypes = [P, dp, dp, C.c_int, dp, C.c_int, C.c_double, C.c_double, dp, dp]
+        L.orc_run_round.restype = C.c_int
+        L.orc_lipschitz_bound.argtypes = [P]
+        L.orc_lipschitz_bound.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
         L.orcnet_num_params.argtypes = [C.c_int, C.c_int]
         L.orcnet_num_params.restype = C.c_size_t
@@ -104,7 +109,7 @@ class Problem:
     """
 
     def __init__(self, y, gx, gy, gz, lam=0.0, delta=1.0, eta=0.0, kappa=0.0,
-                 xmin=0.0, xmax=1.0, dense=False):
+                 xmin=0.0, xmax=1.0, dense=False, mu=0.0):
         self.y = _f64(y)
         assert self.y.ndim == 3
         self.nz, self.ny, self.nx = self.y.shape
@@ -114,11 +119,12 @@ class Problem:
         self.lam, self.delta, self.eta, self.kappa = float(lam), float(delta), float(eta), float(kappa)
         self.xmin, self.xmax = float(xmin), float(xmax)
         self.dense = bool(dense)
+        self.mu = float(mu)
         self._s = _Problem(self.nx, self.ny, self.nz,
                            self.gx.shape[1], self.gy.shape[1], self.gz.shape[1],
                            self.gx.ctypes.data, self.gy.ctypes.data, self.gz.ctypes.data,
                            self.y.ctypes.data, self.lam, self.delta, self.eta, self.kappa,
-                           self.xmin, self.xmax, int(self.dense))
+                           self.xmin, self.xmax, int(self.dense), self.mu)
 
     @property
     def shape(self):
@@ -207,6 +213,31 @@ class Problem:
         if history:
             return s, fh[:s], gh[:s]
         return s, None, None
+
+    def run_round(self, x, dprev, nslices, max_sweeps, grad_rtol=0.0, gnorm_ref=None,
+                  history=True):
+        """Asynchronous rounds: every block steps from the same snapshot (each
+        majorant inflated by the problem's mu Id); x, dprev updated in place.
+
+        Returns (sweeps, f_hist, g_hist)."""
+        assert x.dtype == np.float64 and x.flags.c_contiguous
+        assert dprev.dtype == np.float64 and dprev.flags.c_contiguous
+        ns = np.ascontiguousarray(nslices, dtype=np.int32)
+        assert ns.sum() == self.nz
+        if gnorm_ref is None:
+            gnorm_ref = self.grad_norm(self.y) if grad_rtol > 0 else 0.0
+        fh = np.full(max_sweeps, np.nan) if history else None
+        gh = np.full(max_sweeps, np.nan) if history else None
+        s = lib().orc_run_round(self._p(), _ptr(x), _ptr(dprev), int(ns.size), _ptr(ns),
+                                int(max_sweeps), float(grad_rtol), float(gnorm_ref),
+                                _ptr(fh) if history else None, _ptr(gh) if history else None)
+        if history:
+            return s, fh[:s], gh[:s]
+        return s, None, None
+
+    def lipschitz_bound(self):
+        """Upper bound of the Lipschitz constant of grad f from the tables."""
+        return float(lib().orc_lipschitz_bound(self._p()))
 
 
 def pinv2(b11, b12, b22):

@@ -52,6 +52,7 @@ typedef struct {
     const double *y;             /* observation, [nz][ny][nx] */
     double lambda, delta, eta, kappa, xmin, xmax;
     int dense;                   /* 1: triple-sum definition of H; 0: separable twin */
+    double mu;                   /* curvature inflation of every block majorant (Assumption C); 0: none */
 } orc_problem;
 
 #define VOX(p, k, j, i) (((size_t)(k) * (size_t)(p)->ny + (size_t)(j)) * (size_t)(p)->nx + (size_t)(i))
@@ -72,7 +73,7 @@ int orc_num_threads(void)
  * is all zeros; its user zeroes the slices it wrote before scratch_put, so the
  * oracle does not clear whole volumes on every block update.  (Storage only:
  * no arithmetic depends on it.) */
-enum { SCR_R, SCR_HU, SCR_HV, SCR_G, SCR_D1, SCR_D2, SCR_COUNT };
+enum { SCR_R, SCR_HU, SCR_HV, SCR_G, SCR_D1, SCR_D2, SCR_DN, SCR_COUNT };
 static double *scr_buf[SCR_COUNT];
 static size_t scr_cap[SCR_COUNT];
 
@@ -558,36 +559,44 @@ int orc_color_schedule(int nblocks, const int *nslices, int min_gap, int *order,
  *   dprev  : full-size volume holding each block's previous step on its own
  *            slices; updated in place on S;
  *   info   : optional, receives {B11, B12, B22, c1, c2, u1, u2, ||g||^2}.   */
-void orc_block_step(const orc_problem *p, double *x, double *dprev, int z0, int n, double *info)
+/* One block's memory-gradient MM step at the point x (Sec. 2.3, box "Worker";
+ * eq. "minimizer"): g = grad f(x) on S, D = [-g | d_prev], B = D^T A_S(x) D
+ * with A_S the principal submatrix of the majorant, plus mu Id when the
+ * problem's mu > 0 (the curvature inflation of Assumption C), u = -B^+ D^T g,
+ * d' = D u.
+ * d' is written to dout on S only; x and dprev are not changed. */
+static void block_direction(const orc_problem *p, const double *x, const double *dprev, int z0, int n,
+                            double *dout, double *info)
 {
     size_t N = nvox(p), S = nslice(p);
     size_t off = (size_t)z0 * S, cnt = (size_t)n * S;
     double *g = scratch_get(SCR_G, N);
     double *d1 = scratch_get(SCR_D1, N);
     double *d2 = scratch_get(SCR_D2, N);
-    /* (2)-(3): gradient on the block, subspace directions [-g | d] */
+    /* gradient on the block, subspace directions [-g | d] */
     orc_grad_slices(p, x, g, z0, z0 + n);
     for (size_t q = off; q < off + cnt; ++q) {
         d1[q] = -g[q];
         d2[q] = dprev[q];
     }
-    /* (4): D^T A_S D and D^T grad */
+    /* D^T A_S D and D^T grad */
     double B[3];
     B[0] = orc_majorant_form(p, x, d1, d1, z0, z0 + n);
     B[1] = orc_majorant_form(p, x, d1, d2, z0, z0 + n);
     B[2] = orc_majorant_form(p, x, d2, d2, z0, z0 + n);
+    if (p->mu > 0.0) {
+        B[0] += p->mu * dot_slices(p, d1, d1, z0, z0 + n);
+        B[1] += p->mu * dot_slices(p, d1, d2, z0, z0 + n);
+        B[2] += p->mu * dot_slices(p, d2, d2, z0, z0 + n);
+    }
     double c1 = dot_slices(p, d1, g, z0, z0 + n);
     double c2 = dot_slices(p, d2, g, z0, z0 + n);
     double P[3];
     orc_pinv2(B, P);
-    /* (6): u = -(D^T A D)^+ D^T grad, d' = D u */
+    /* u = -(D^T A D)^+ D^T grad, d' = D u */
     double u1 = -(P[0] * c1 + P[1] * c2);
     double u2 = -(P[1] * c1 + P[2] * c2);
-    for (size_t q = off; q < off + cnt; ++q) {
-        double dn = u1 * d1[q] + u2 * d2[q];
-        x[q] += dn;
-        dprev[q] = dn;
-    }
+    for (size_t q = off; q < off + cnt; ++q) dout[q] = u1 * d1[q] + u2 * d2[q];
     if (info) {
         info[0] = B[0]; info[1] = B[1]; info[2] = B[2];
         info[3] = c1; info[4] = c2; info[5] = u1; info[6] = u2;
@@ -596,6 +605,21 @@ void orc_block_step(const orc_problem *p, double *x, double *dprev, int z0, int 
     scratch_clear(g, z0, z0 + n, S);
     scratch_clear(d1, z0, z0 + n, S);
     scratch_clear(d2, z0, z0 + n, S);
+}
+
+/* Block update without delay: the step of block [z0, z0+n) at the current x,
+ * applied at once (x += d', d_prev = d' on the block). */
+void orc_block_step(const orc_problem *p, double *x, double *dprev, int z0, int n, double *info)
+{
+    size_t N = nvox(p), S = nslice(p);
+    size_t off = (size_t)z0 * S, cnt = (size_t)n * S;
+    double *dn = scratch_get(SCR_DN, N);
+    block_direction(p, x, dprev, z0, n, dn, info);
+    for (size_t q = off; q < off + cnt; ++q) {
+        x[q] += dn[q];
+        dprev[q] = dn[q];
+    }
+    scratch_clear(dn, z0, z0 + n, S);
 }
 
 static double norm_grad(const orc_problem *p, const double *x)
@@ -609,6 +633,68 @@ static double norm_grad(const orc_problem *p, const double *x)
 }
 
 double orc_grad_norm(const orc_problem *p, const double *x) { return norm_grad(p, x); }
+
+/* Asynchronous rounds (Sec. 2.4-2.5): every block computes its step from the
+ * same snapshot x^k (the delays of a round are at most tau = nblocks - 1
+ * block updates, Assumption B), then all steps are applied.  The problem's mu
+ * inflates each block's majorant by mu Id (Assumption C).  Stops as orc_run
+ * does. */
+int orc_run_round(const orc_problem *p, double *x, double *dprev, int nblocks, const int *nslices,
+                  int max_sweeps, double grad_rtol, double gnorm_ref, double *f_hist, double *g_hist)
+{
+    size_t N = nvox(p);
+    double *dn = (double *)calloc(N, sizeof(double));
+    int s;
+    for (s = 0; s < max_sweeps; ++s) {
+        int z0 = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            block_direction(p, x, dprev, z0, nslices[b], dn, NULL);
+            z0 += nslices[b];
+        }
+        for (size_t q = 0; q < N; ++q) {
+            x[q] += dn[q];
+            dprev[q] = dn[q];
+        }
+        double gn = -1.0;
+        if (f_hist) f_hist[s] = orc_f(p, x);
+        if (g_hist || grad_rtol > 0.0) gn = norm_grad(p, x);
+        if (g_hist) g_hist[s] = gn;
+        if (grad_rtol > 0.0 && gn <= grad_rtol * gnorm_ref) { ++s; break; }
+    }
+    free(dn);
+    return s;
+}
+
+/* A Lipschitz constant of grad f (Assumption A) bounded from the tables:
+ * ||H^T H|| <= ||H||_1 ||H||_inf (H >= 0, the in-slice factors sum to 1, so
+ * the row sums are the z weights of the output slice and the column sums
+ * those gathered from the slices an input slice reaches), plus 2 eta for the
+ * box term, lambda ||D||^2 / delta with ||D||^2 <= 8 for the two in-slice
+ * forward differences (omega <= 1 / delta), and 2 kappa ||V^Z||^2 <= 8 kappa. */
+double orc_lipschitz_bound(const orc_problem *p)
+{
+    int rz = p->kz / 2;
+    double rmax = 0.0, cmax = 0.0;
+    for (int k = 0; k < p->nz; ++k) {
+        double r = 0.0, c = 0.0;
+        for (int t = -rz; t <= rz; ++t) {
+            if (k - t >= 0 && k - t < p->nz) r += fabs(p->gz[(size_t)k * p->kz + t + rz]);
+            if (k + t >= 0 && k + t < p->nz) c += fabs(p->gz[(size_t)(k + t) * p->kz + t + rz]);
+        }
+        if (r > rmax) rmax = r;
+        if (c > cmax) cmax = c;
+    }
+    double sx = 0.0, sy = 0.0;
+    for (int k = 0; k < p->nz; ++k) {
+        double ax = 0.0, ay = 0.0;
+        for (int a = 0; a < p->kx; ++a) ax += fabs(p->gx[(size_t)k * p->kx + a]);
+        for (int a = 0; a < p->ky; ++a) ay += fabs(p->gy[(size_t)k * p->ky + a]);
+        if (ax > sx) sx = ax;
+        if (ay > sy) sy = ay;
+    }
+    double hh = rmax * cmax * sx * sx * sy * sy;
+    return hh + 2.0 * p->eta + 8.0 * p->lambda / p->delta + 8.0 * p->kappa;
+}
 
 /* ------------------------------------------------------------------------ */
 /* BD3MG driver with no delay (delta_k = 0, Sec. 2.4): blocks are visited in

@@ -33,6 +33,13 @@ MUTATIONS = {
     "coloring-gap-off-by-one": ("if (gap < min_gap) { ok = 0; break; }",
                                 "if (gap < min_gap - 1) { ok = 0; break; }"),
     "z-penalty-factor": ("acc += 2.0 * p->kappa * zz;", "acc += p->kappa * zz;"),
+    "inflation-dropped": ("B[0] += p->mu * dot_slices(p, d1, d1, z0, z0 + n);",
+                          "B[0] += 0.0 * dot_slices(p, d1, d1, z0, z0 + n);"),
+    "round-applies-in-sequence": ("            block_direction(p, x, dprev, z0, nslices[b], dn, NULL);\n",
+                                  "            block_direction(p, x, dprev, z0, nslices[b], dn, NULL);\n"
+                                  "            for (size_t q = (size_t)z0 * nslice(p); q < (size_t)(z0 + nslices[b]) * nslice(p); ++q)"
+                                  " { x[q] += dn[q]; dprev[q] = dn[q]; dn[q] = 0.0; }\n"),
+    "lipschitz-tv-term": ("8.0 * p->lambda / p->delta", "p->lambda / p->delta"),
 }
 
 NET_MUTATIONS = {
@@ -52,7 +59,7 @@ NET_MUTATIONS = {
     "net-bf16-ties-away": ("u += 0x7fffu + lsb;", "u += 0x8000u; (void)lsb;"),
 }
 
-PIN_FILES = {SRC: "test_oracle_pins.py", NET_SRC: "test_oracle_convnet.py"}
+PIN_FILES = {SRC: ["test_oracle_pins.py", "test_oracle_round.py"], NET_SRC: ["test_oracle_convnet.py"]}
 
 
 def _cases():
@@ -72,7 +79,7 @@ def test_pins_catch_planted_mistake(path, name, edit, tmp_path):
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
                     "-o", str(lib), str(mut)] + others + ["-lm"], check=True)
     env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
-    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                          os.path.join(ROOT, "tests", PIN_FILES[path])],
+    res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] +
+                         [os.path.join(ROOT, "tests", f) for f in PIN_FILES[path]],
                          cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert res.returncode != 0, "pins did not catch mutation %s\n%s" % (name, res.stdout[-2000:])
