@@ -66,7 +66,14 @@ typedef enum {
      * Sec. 3.1 applied in colour-major order (Sec. 2.4, delta_k = 0). */
     BD3MG_SCHED_COLORED = 0,
     /* One block at a time in z order (the natural sequential rule). */
-    BD3MG_SCHED_SEQUENTIAL = 1
+    BD3MG_SCHED_SEQUENTIAL = 1,
+    /* Asynchronous rounds: every block computes its step from the same
+     * snapshot of x, then all steps are applied (Sec. 2.4: block updates with
+     * delays of at most tau = nblocks - 1, Assumption B).  Without inflation
+     * of the majorant this can diverge when blocks interact through H (thin
+     * blocks, wide z blur); Assumption C asks for curvature beyond
+     * L sqrt(tau), see bd3mg_set_inflation and bd3mg_lipschitz_bound. */
+    BD3MG_SCHED_ROUND = 2
 } bd3mg_schedule;
 
 typedef enum { BD3MG_OP_H = 0, BD3MG_OP_HT = 1, BD3MG_OP_GRAD = 2 } bd3mg_op;
@@ -115,6 +122,19 @@ bd3mg_status bd3mg_set_psf_gaussian(bd3mg_problem p, int kxy, int kz,
  * first call: lambda = eta = kappa = 0, delta = 1, [xmin, xmax] = [0, 1]. */
 bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, double eta,
                               double kappa, double xmin, double xmax);
+
+/* Curvature inflation (Sec. 2.5, Assumption C): every block step uses the
+ * majorant A_S(x) + mu Id instead of A_S(x), for every schedule.  mu = 0
+ * (the default) is the paper's majorant.  ERR_ARG: mu < 0 or not finite. */
+bd3mg_status bd3mg_set_inflation(bd3mg_problem p, double mu);
+
+/* An upper bound L of the Lipschitz constant of grad f (Assumption A) from
+ * the PSF tables and parameters: ||H||_1 ||H||_inf + 2 eta + 8 lambda / delta
+ * + 8 kappa (the in-slice difference operators have ||D||^2 <= 8 and
+ * omega <= 1 / delta).  With tau = nblocks - 1, mu = L (2 sqrt(tau) + 1)
+ * satisfies Assumption C for BD3MG_SCHED_ROUND whatever the point (a
+ * sufficient, conservative reading).  ERR_STATE: PSF not set. */
+bd3mg_status bd3mg_lipschitz_bound(bd3mg_problem p, double *L);
 
 /* Observation y (eq. "model"), nz*ny*nx elements of the storage type. */
 bd3mg_status bd3mg_set_data(bd3mg_problem p, const void *y, int on_device);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libbd3mg.so")
 
 FP64, FP32 = 0, 1
-SCHED_COLORED, SCHED_SEQUENTIAL = 0, 1
+SCHED_COLORED, SCHED_SEQUENTIAL, SCHED_ROUND = 0, 1, 2
 OP_H, OP_HT, OP_GRAD = 0, 1, 2
 OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_HIP, ERR_NOT_CONVERGED = range(6)
 OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
@@ -55,6 +55,8 @@ SIGNATURES = {
     "bd3mg_batch_destroy": ([_dp], C.c_int),
     "bd3mg_batch_tune": ([_dp], C.c_int),
     "bd3mg_batch_run": ([_dp, _i, _d, _i, _dp], C.c_int),
+    "bd3mg_set_inflation": ([_dp, _d], C.c_int),
+    "bd3mg_lipschitz_bound": ([_dp, _dp], C.c_int),
     "bd3mg_net_create": ([_i, _i, _i, C.POINTER(_dp)], C.c_int),
     "bd3mg_net_destroy": ([_dp], C.c_int),
     "bd3mg_net_num_params": ([_dp, C.POINTER(C.c_size_t)], C.c_int),
@@ -181,6 +183,14 @@ class Problem:
 
     def set_params(self, lam, delta, eta, kappa=0.0, xmin=0.0, xmax=1.0):
         _check(load().bd3mg_set_params(self._h, lam, delta, eta, kappa, xmin, xmax))
+
+    def set_inflation(self, mu):
+        _check(load().bd3mg_set_inflation(self._h, float(mu)))
+
+    def lipschitz_bound(self):
+        L = C.c_double()
+        _check(load().bd3mg_lipschitz_bound(self._h, C.byref(L)))
+        return L.value
 
     def set_data(self, y, on_device=False):
         ptr, keep = self._vol_in(y, on_device)

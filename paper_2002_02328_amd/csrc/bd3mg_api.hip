@@ -45,12 +45,13 @@ struct bd3mg_problem_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Geom geom{};
     int ntiles = 0;
-    Params prm{0.0, 1.0, 0.0, 0.0, 0.0, 1.0};
+    Params prm{0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0};
 
     // PSF
     bool psf_set = false;
     int kx = 0, ky = 0, kz = 0;
     void *d_gx = nullptr, *d_gy = nullptr, *d_gz = nullptr;
+    std::vector<double> hgx, hgy, hgz;  // the tables as given (for the Lipschitz bound)
 
     // volumes (storage type); q is the in-slice adjoint-blurred residual
     void *x = nullptr, *y = nullptr, *q = nullptr, *g = nullptr, *dpb[2] = {nullptr, nullptr};
@@ -66,6 +67,7 @@ struct bd3mg_problem_s {
     struct Group {
         int g_off, g_cnt, d_off, d_cnt, u_off, u_cnt, br_off, br_cnt;
         double bytes[4];  // algorithmic bytes of the gradient, direction, solve and update passes
+        bool round;       // update pass over every slice with per-slice block coefficients
     };
     std::vector<Group> groups;  // ncolors colour groups, then one group per block
     Item *d_items = nullptr;
@@ -73,6 +75,7 @@ struct bd3mg_problem_s {
     BlockRange *d_br = nullptr;
     size_t br_alloc = 0;
     Item *d_vol = nullptr;  // every slice of the volume, for whole-volume passes
+    int *d_sblk = nullptr;  // block of every slice
 
     // reductions
     double *d_pg = nullptr, *d_pd = nullptr, *d_pe = nullptr, *d_pr = nullptr;
@@ -122,6 +125,7 @@ DevState<T> dev_state(bd3mg_problem p)
     s.gx = (const T *)p->d_gx;
     s.gy = (const T *)p->d_gy;
     s.gz = (const T *)p->d_gz;
+    s.sblk = p->d_sblk;
     s.stop = nullptr;
     return s;
 }
@@ -237,6 +241,8 @@ void color_blocks(bd3mg_problem p)
     if (p->schedule == BD3MG_SCHED_SEQUENTIAL) {
         for (int b = 0; b < nb; ++b) p->color[b] = b;
         p->ncolors = nb;
+    } else if (p->schedule == BD3MG_SCHED_ROUND) {
+        p->ncolors = 1;  // every block in one round, all from the same snapshot
     } else {
         const int rz = p->kz / 2;
         const int min_gap = std::max(2 * rz, p->prm.kappa > 0.0 ? 1 : 0);
@@ -266,7 +272,7 @@ void color_blocks(bd3mg_problem p)
 // all clipped to the volume, block by block in z order.
 void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<Item> &gi,
                  std::vector<Item> &di, std::vector<Item> &ui, std::vector<BlockRange> &br,
-                 bd3mg_problem_s::Group &grp)
+                 bd3mg_problem_s::Group &grp, bool round = false)
 {
     const int rz = p->kz / 2;
     const int rd = std::max(rz, p->prm.kappa > 0.0 ? 1 : 0);
@@ -283,15 +289,27 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
         for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n, bri, 0});
         for (int k = std::max(0, z0 - rd); k < std::min(p->nz, z0 + n + rz); ++k)
             di.push_back(Item{k, b, z0, n, bri, 0});
-        for (int k = std::max(0, z0 - rz); k < std::min(p->nz, z0 + n + rz); ++k) {
-            ui.push_back(Item{k, b, z0, n, bri, 0});
-            halo[k] = 1;
-        }
+        if (!round)
+            for (int k = std::max(0, z0 - rz); k < std::min(p->nz, z0 + n + rz); ++k) {
+                ui.push_back(Item{k, b, z0, n, bri, 0});
+                halo[k] = 1;
+            }
         r.gn = (int)gi.size() - grp.g_off - r.g0;
         r.dn = (int)di.size() - grp.d_off - r.d0;
         br.push_back(r);
         sl += n;
     }
+    if (round) {
+        // one update item per slice of the volume; each source slice of the
+        // z-combine takes the coefficients of its own block
+        for (int k = 0; k < p->nz; ++k) {
+            int b = 0;
+            while (p->z0[b] + p->nsl[b] <= k) ++b;
+            ui.push_back(Item{k, b, p->z0[b], p->nsl[b], -1, 0});
+            halo[k] = 1;
+        }
+    }
+    grp.round = round;
     grp.g_cnt = (int)gi.size() - grp.g_off;
     grp.d_cnt = (int)di.size() - grp.d_off;
     grp.u_cnt = (int)ui.size() - grp.u_off;
@@ -324,7 +342,7 @@ bd3mg_status build_schedule(bd3mg_problem p)
         std::vector<int> blocks;
         for (int b : p->order)
             if (p->color[b] == c) blocks.push_back(b);
-        group_items(p, blocks, gi, di, ui, br, p->groups[c]);
+        group_items(p, blocks, gi, di, ui, br, p->groups[c], p->schedule == BD3MG_SCHED_ROUND);
     }
     for (int b = 0; b < nb; ++b) group_items(p, {b}, gi, di, ui, br, p->groups[p->ncolors + b]);
     // one device array: gradient items, then direction items, then update items
@@ -342,6 +360,14 @@ bd3mg_status build_schedule(bd3mg_problem p)
                            p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_br, br.data(), br.size() * sizeof(BlockRange), hipMemcpyHostToDevice,
                            p->stream));
+    {
+        std::vector<int> sblk(p->nz);
+        for (int b = 0; b < nb; ++b)
+            for (int k = p->z0[b]; k < p->z0[b] + p->nsl[b]; ++k) sblk[k] = b;
+        if (!p->d_sblk && hipMalloc(&p->d_sblk, p->nz * sizeof(int)) != hipSuccess)
+            return fail(BD3MG_ERR_NOMEM, "slice blocks");
+        HIP_TRY(hipMemcpy(p->d_sblk, sblk.data(), p->nz * sizeof(int), hipMemcpyHostToDevice));
+    }
     if (nb > p->nblocks_alloc) {
         if (p->d_u) HIP_TRY(hipFree(p->d_u));
         if (p->d_info) HIP_TRY(hipFree(p->d_info));
@@ -480,8 +506,8 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
                          p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
-    HIP_TRY(launch_update<T>(p->geom, s, nullptr, s.q, it + gr.u_off, gr.u_cnt, p->d_u, UM_UPDATE,
-                             p->stream));
+    HIP_TRY(launch_update<T>(p->geom, s, nullptr, s.q, it + gr.u_off, gr.u_cnt, p->d_u,
+                             gr.round ? UM_ROUND : UM_UPDATE, p->stream));
     if (prof) ST_TRY(prof_end(p));
     return BD3MG_OK;
 }
@@ -613,7 +639,7 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
     if (!p) return BD3MG_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2],
-                    p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_pg, p->d_pd,
+                    p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_sblk, p->d_pg, p->d_pd,
                     p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -663,6 +689,9 @@ bd3mg_status bd3mg_set_psf_separable(bd3mg_problem p, int kx, int ky, int kz, co
             HIP_TRY(hipMemcpy(*dst[t], f.data(), n * sizeof(float), hipMemcpyHostToDevice));
         }
     }
+    p->hgx.assign(gx, gx + (size_t)p->nz * kx);
+    p->hgy.assign(gy, gy + (size_t)p->nz * ky);
+    p->hgz.assign(gz, gz + (size_t)p->nz * kz);
     p->geom.R = R;
     p->kx = kx;
     p->ky = ky;
@@ -698,9 +727,44 @@ bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, doub
         return fail(BD3MG_ERR_ARG, "lambda, eta and kappa must be >= 0");
     if (xmin > xmax) return fail(BD3MG_ERR_ARG, "xmin > xmax");
     const bool kappa_changed = (kappa > 0.0) != (p->prm.kappa > 0.0);
-    p->prm = Params{lambda, delta, eta, kappa, xmin, xmax};
+    p->prm = Params{lambda, delta, eta, kappa, xmin, xmax, p->prm.mu};
     p->gnorm_ref_valid = false;
     if (kappa_changed) p->sched_dirty = true;
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_set_inflation(bd3mg_problem p, double mu)
+{
+    ST_TRY(validate_handle(p));
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(BD3MG_ERR_ARG, "mu must be finite and >= 0");
+    p->prm.mu = mu;
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_lipschitz_bound(bd3mg_problem p, double *L)
+{
+    ST_TRY(validate_handle(p));
+    if (!L) return fail(BD3MG_ERR_ARG, "null output");
+    if (!p->psf_set) return fail(BD3MG_ERR_STATE, "the PSF is not set");
+    // the tables in the storage precision, as the operator uses them
+    auto st = [&](double v) { return std::fabs(p->prec == BD3MG_FP64 ? v : (double)(float)v); };
+    const int rz = p->kz / 2, nz = p->nz;
+    double rmax = 0.0, cmax = 0.0, sx = 0.0, sy = 0.0;
+    for (int k = 0; k < nz; ++k) {
+        double r = 0.0, c = 0.0, ax = 0.0, ay = 0.0;
+        for (int t = -rz; t <= rz; ++t) {
+            if (k - t >= 0 && k - t < nz) r += st(p->hgz[(size_t)k * p->kz + t + rz]);
+            if (k + t >= 0 && k + t < nz) c += st(p->hgz[(size_t)(k + t) * p->kz + t + rz]);
+        }
+        for (int a = 0; a < p->kx; ++a) ax += st(p->hgx[(size_t)k * p->kx + a]);
+        for (int a = 0; a < p->ky; ++a) ay += st(p->hgy[(size_t)k * p->ky + a]);
+        rmax = std::max(rmax, r);
+        cmax = std::max(cmax, c);
+        sx = std::max(sx, ax);
+        sy = std::max(sy, ay);
+    }
+    const Params &q = p->prm;
+    *L = rmax * cmax * sx * sx * sy * sy + 2.0 * q.eta + 8.0 * q.lambda / q.delta + 8.0 * q.kappa;
     return BD3MG_OK;
 }
 
@@ -719,7 +783,8 @@ bd3mg_status bd3mg_set_blocks(bd3mg_problem p, int nblocks, const int *nslices, 
 {
     ST_TRY(validate_handle(p));
     if (nblocks < 1 || !nslices) return fail(BD3MG_ERR_ARG, "need nblocks >= 1 and slice counts");
-    if (schedule != BD3MG_SCHED_COLORED && schedule != BD3MG_SCHED_SEQUENTIAL)
+    if (schedule != BD3MG_SCHED_COLORED && schedule != BD3MG_SCHED_SEQUENTIAL &&
+        schedule != BD3MG_SCHED_ROUND)
         return fail(BD3MG_ERR_ARG, "unknown schedule %d", schedule);
     long sum = 0;
     for (int b = 0; b < nblocks; ++b) {

@@ -75,6 +75,7 @@ struct BlockRange {
 
 struct Params {
     double lambda, delta, eta, kappa, xmin, xmax;
+    double mu;  // curvature inflation of every block majorant (A_S + mu Id)
 };
 
 struct Geom {
@@ -99,6 +100,7 @@ struct DevState {
     const int *stop;           // when non-null and set, every pass returns at entry
     const T *gx, *gy;          // in-slice PSF tables [nz][2R + 1], centred, zero-padded
     const T *gz;               // z PSF table [nz][kz]
+    const int *sblk;           // block of every slice (round updates), else null
 };
 
 enum GradMode : int {
@@ -109,8 +111,10 @@ enum GradMode : int {
 };
 
 enum UpdateMode : int {
-    UM_UPDATE = 0,  // d' = -u1 g + u2 dp on the block: q += XY^T H d', x += d', dp[1] = d'
-    UM_REFRESH = 1  // q = XY^T (H src - y) on the items' slices
+    UM_UPDATE = 0,   // d' = -u1 g + u2 dp on the block: q += XY^T H d', x += d', dp[1] = d'
+    UM_REFRESH = 1,  // q = XY^T (H src - y) on the items' slices
+    UM_ROUND = 2     // every slice once, d' = -u1 g + u2 dp with the coefficients of
+                     // each slice's own block (s.sblk): q += XY^T H d', x += d', dp[1] = d'
 };
 
 template <typename T>

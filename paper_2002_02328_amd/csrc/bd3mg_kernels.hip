@@ -395,7 +395,7 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
         // direction pass: <Hd_a,Hd_b>, then <VZ d_a, VZ d_b>
         const double gg = tot[0], gd = tot[1], dd = tot[2];
         const double *w = tot + 3, *h = tot + NQG, *z = tot + NQG + 3;
-        const double e2 = 2.0 * prm.eta, k2 = 2.0 * prm.kappa, lam = prm.lambda;
+        const double e2 = 2.0 * prm.eta + prm.mu, k2 = 2.0 * prm.kappa, lam = prm.lambda;
         const double b11 = h[0] + e2 * gg + lam * w[0] + k2 * z[0];
         const double b12 = h[1] - e2 * gd + lam * w[1] + k2 * z[1];
         const double b22 = h[2] + e2 * dd + lam * w[2] + k2 * z[2];
@@ -535,6 +535,10 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
 //   d' = -u1 g + u2 dp on S;  q_m += XY^T_m (H d')_m  (m in S +- r_z);
 //   and for m in S: x_m += d'_m, dp[1]_m = d'_m.
 // UM_REFRESH: q_m = XY^T_m (H src - y)_m.
+// UM_ROUND (items: every slice once): as UM_UPDATE with the blocks of a round
+//   all at once, each source slice j scaled by the coefficients of its own
+//   block s.sblk[j] (the steps have disjoint supports, so H of their sum is
+//   the sum of their H).
 // (H v)_m is formed on the tile plus an R halo (z-combine on a 2R halo, x and
 // y passes), zeroed outside the slice (the adjoint blur sees zero padding),
 // then blurred back by the adjoint x and y passes of slice m.  Previous steps
@@ -563,11 +567,15 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     T wx[K], wy[K];
     load_taps<T, R>(wx, s.gx + (size_t)m * K);
     load_taps<T, R>(wy, s.gy + (size_t)m * K);
-    const bool upd = (mode == UM_UPDATE);
+    const bool upd = (mode == UM_UPDATE), rnd = (mode == UM_ROUND), refresh = (mode == UM_REFRESH);
     T u1 = 0, u2 = 0;
     if (upd) {
         u1 = (T)u[2 * it.block];
         u2 = (T)u[2 * it.block + 1];
+    } else if (rnd) {
+        const int b = s.sblk[m];
+        u1 = (T)u[2 * b];
+        u2 = (T)u[2 * b + 1];
     }
     const T *__restrict__ gg = s.g;
     const T *__restrict__ dpi = s.dp[0];
@@ -588,6 +596,13 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
 #pragma unroll
                 for (int qq = 0; qq < rg.E; ++qq)
                     v[qq] += wv * (u2 * ds[rg.off[qq]] - u1 * gs[rg.off[qq]]);
+            } else if (rnd) {
+                if (sl < 0 || sl >= g.nz) continue;
+                const int b = s.sblk[sl];
+                const T c1 = wv * (T)u[2 * b], c2 = wv * (T)u[2 * b + 1];
+                const T *gs = gg + (size_t)sl * S, *ds = dpi + (size_t)sl * S;
+#pragma unroll
+                for (int qq = 0; qq < rg.E; ++qq) v[qq] += c2 * ds[rg.off[qq]] - c1 * gs[rg.off[qq]];
             } else {
                 if (sl < 0 || sl >= g.nz) continue;
                 const T *ss = src + (size_t)sl * S;
@@ -601,7 +616,7 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     // the data term of a refresh is needed on the R halo; load it early
     Region<W2, H2, R, R> r2(g, x0, y0);
     T yv[r2.E];
-    if (!upd) {
+    if (refresh) {
         const T *ys = s.y + (size_t)m * S;
 #pragma unroll
         for (int qq = 0; qq < r2.E; ++qq) yv[qq] = ys[r2.off[qq]];
@@ -621,7 +636,7 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
         T acc = 0;
 #pragma unroll
         for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[-b * W2];
-        if (!upd) acc -= yv[qq];
+        if (refresh) acc -= yv[qq];
         A[e] = r2.inb[qq] ? acc : T(0);
     }
     __syncthreads();
@@ -636,9 +651,9 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
         const int j = y0 + out_row(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
         const size_t o = vidx(g, m, j, i);
-        if (upd) {
+        if (!refresh) {
             qout[o] += v[e];
-            if (m >= z0 && m < z1) {
+            if (rnd || (m >= z0 && m < z1)) {
                 const T d = u2 * dpi[o] - u1 * gg[o];
                 s.x[o] += d;
                 s.dp[1][o] = d;
