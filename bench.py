@@ -12,8 +12,9 @@ Prints one JSON line: voxel-iterations/s over exactly --steps sweeps (after
 --warmup untimed sweeps), the roofline figure of the dominant kernel (HIP
 events on the library's stream, algorithmic bytes from the library), the
 time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y and from the learned
-warm start x0 = y + net(y) (network inference inside the clock), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+warm start x0 = y + net(y) (network inference inside the clock), the same
+under the asynchronous-round schedule, and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -100,6 +101,53 @@ def cpu_baseline(w, budget_s):
             "seconds": t2 - t0}
 
 
+def round_schedule(binding, w, args):
+    """The same workload under asynchronous rounds (every block steps from one
+    snapshot; one gradient, direction, solve and update launch per sweep) with
+    the paper's majorant (no inflation): sweep throughput, per-kernel device
+    time, and time to the tolerance from x0 = y and from the warm start."""
+    nvox = int(np.prod(w.shape))
+    r = make_problem(binding, w)
+    r.set_blocks(w.nslices, binding.SCHED_ROUND)
+    r.set_x0(None)
+    (td, tu), _ = r.autotune(5)
+    r.set_x0(None)
+    r.run(args.warmup, check_every=0)
+    t0 = time.perf_counter()
+    r.run(args.steps, check_every=0)
+    secs = time.perf_counter() - t0
+    r.set_option(binding.OPT_PROFILE, 1)
+    r.run(args.steps, check_every=0)
+    prof = r.get_profile(reset=True)
+    r.set_option(binding.OPT_PROFILE, 0)
+    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
+                   "GB/s": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
+               for k, v in prof.items() if v[0] > 0 and k != "eval"}
+    out = {"value": nvox * args.steps / secs, "unit": "voxel-iterations/s",
+           "ms_per_step": 1e3 * secs / args.steps, "mu": 0.0, "tile_rows": {"dirs": td, "update": tu},
+           "kernels": kernels, "lipschitz_bound": r.lipschitz_bound()}
+    if not args.no_tol:
+        def to_tol(net):
+            r.set_x0(None)
+            t0 = time.perf_counter()
+            if net is not None:
+                net.infer(r)
+            res = r.run(args.max_sweeps_to_tol, grad_rtol=args.tol, check_every=1)
+            return {"seconds": time.perf_counter() - t0, "sweeps": res["sweeps"],
+                    "converged": bool(res["converged"]), "grad_rel": res["grad_norm"] / res["grad_norm_ref"],
+                    "f": res["f"], "tol": args.tol}
+        tt = {"plain_x0_y": to_tol(None), "warm_started": None}
+        if os.path.exists(WEIGHTS):
+            net = binding.Net()
+            net.load(open(WEIGHTS, "rb").read())
+            net.infer(r)
+            tt["warm_started"] = to_tol(net)
+            net.close()
+        out["time_to_tol"] = tt
+    r.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +159,7 @@ def main():
     ap.add_argument("--no-tol", action="store_true", help="skip the time-to-tolerance run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--no-round", action="store_true", help="skip the asynchronous-round schedule")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -216,6 +265,9 @@ def main():
                                "flop": flop, "weights": os.path.relpath(WEIGHTS, ROOT)}
             net.close()
         out["time_to_tol"] = tt
+
+    if not args.no_round:
+        out["round_schedule"] = round_schedule(binding, w, args)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
