@@ -309,14 +309,19 @@ __global__ void __launch_bounds__(NTH) k_wgrad(WgArgs a)
     if (tid < COUT) a.partb[(size_t)blockIdx.x * COUT + tid] = bsum;
 }
 
+// One wavefront per output element: lane l sums partials w = l, l + 64, ...
+// in order, then a fixed shuffle tree; the same order on every run.
 __global__ void __launch_bounds__(NTH) k_wreduce(const float *__restrict__ part, int nwg, int ne,
                                                  float *__restrict__ out)
 {
-    const int e = blockIdx.x * NTH + threadIdx.x;
+    const int e = blockIdx.x * (NTH / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (e >= ne) return;
     float s = 0.f;
-    for (int w = 0; w < nwg; ++w) s += part[(size_t)w * ne + e];
-    out[e] = s;
+    for (int w = lane; w < nwg; w += 64) s += part[(size_t)w * ne + e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) out[e] = s;
 }
 
 // First layer (one input channel): one thread per voxel, 27 taps x 16 outputs.
@@ -472,17 +477,21 @@ __global__ void __launch_bounds__(NTH) k_head_bwd(Vol v, const bf16_t *__restric
     if (tid < NHP) part[(size_t)blockIdx.x * NHP + tid] = red[tid][0];
 }
 
-__global__ void k_head_reduce(const double *__restrict__ part, int nwg, float *__restrict__ gw,
-                              double *__restrict__ sq)
+// One wavefront per quantity, as k_wreduce.
+__global__ void __launch_bounds__(64) k_head_reduce(const double *__restrict__ part, int nwg,
+                                                    float *__restrict__ gw, double *__restrict__ sq)
 {
-    const int j = threadIdx.x;
-    if (j >= NHP) return;
+    const int j = blockIdx.x, lane = threadIdx.x;
     double s = 0.0;
-    for (int w = 0; w < nwg; ++w) s += part[(size_t)w * NHP + j];
-    if (j < NHP - 1)
-        gw[j] = (float)s;
-    else
-        *sq = s;
+    for (int w = lane; w < nwg; w += 64) s += part[(size_t)w * NHP + j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+    if (lane == 0) {
+        if (j < NHP - 1)
+            gw[j] = (float)s;
+        else
+            *sq = s;
+    }
 }
 
 // v is the fine grid; one thread per (coarse voxel, 8 channels)
@@ -683,8 +692,9 @@ hipError_t wgrad3(int cin, int cout, int src, Vol v, const bf16_t *g, ConvIn in,
 hipError_t wreduce(const float *part, int nwg, int ne, float *out, const float *partb, int nbias,
                    float *outb, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_wreduce, dim3(blocks_for(ne)), dim3(NTH), 0, st, part, nwg, ne, out);
-    hipLaunchKernelGGL(k_wreduce, dim3(blocks_for(nbias)), dim3(NTH), 0, st, partb, nwg, nbias, outb);
+    constexpr int EPB = NTH / 64;  // elements per block, one wavefront each
+    hipLaunchKernelGGL(k_wreduce, dim3((ne + EPB - 1) / EPB), dim3(NTH), 0, st, part, nwg, ne, out);
+    hipLaunchKernelGGL(k_wreduce, dim3((nbias + EPB - 1) / EPB), dim3(NTH), 0, st, partb, nwg, nbias, outb);
     return hipGetLastError();
 }
 
@@ -728,7 +738,7 @@ hipError_t head_bwd(Vol v, const bf16_t *e1, const float *x0, const float *t, co
 
 hipError_t head_reduce(const double *part, int nwg, float *gw17, double *sq, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_head_reduce, dim3(1), dim3(64), 0, st, part, nwg, gw17, sq);
+    hipLaunchKernelGGL(k_head_reduce, dim3(NHP), dim3(64), 0, st, part, nwg, gw17, sq);
     return hipGetLastError();
 }
 
