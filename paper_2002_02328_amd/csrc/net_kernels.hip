@@ -324,27 +324,32 @@ __global__ void __launch_bounds__(NTH) k_wreduce(const float *__restrict__ part,
     if (lane == 0) out[e] = s;
 }
 
-// First layer (one input channel): one thread per voxel, 27 taps x 16 outputs.
+// First layer (one input channel), one thread per voxel of a CTZ x CTY x CTX
+// tile: the haloed input tile is rounded to bf16 once into LDS, then 27 taps
+// x 16 outputs per voxel (weights read as uniform scalars).
 __global__ void __launch_bounds__(NTH) k_conv0(Vol v, const float *__restrict__ y,
                                                const float *__restrict__ w0,
-                                               const float *__restrict__ b0, bf16_t *__restrict__ out)
+                                               const float *__restrict__ b0, bf16_t *__restrict__ out,
+                                               int ntx, int nty, int ntz)
 {
-    const size_t i = (size_t)blockIdx.x * NTH + threadIdx.x;
-    if (i >= v.voxels()) return;
-    size_t t = i;
-    const int x = t % v.W;
-    t /= v.W;
-    const int yy = t % v.H;
-    t /= v.H;
-    const int z = t % v.D;
-    const int b = t / v.D;
+    constexpr int HY = CTY + 2, HX = CTX + 2;
+    constexpr int NH = (CTZ + 2) * HY * HX;
+    __shared__ float yh[NH];
+    const Tile T = tile_of(blockIdx.x, ntx, nty, ntz);
+    for (int u = threadIdx.x; u < NH; u += NTH) {
+        const int hz = u / (HY * HX), rem = u - hz * (HY * HX), hy = rem / HX, hx = rem - hy * HX;
+        const int z = T.z0 + hz - 1, yy = T.y0 + hy - 1, x = T.x0 + hx - 1;
+        const bool ok = z >= 0 && z < v.D && yy >= 0 && yy < v.H && x >= 0 && x < v.W;
+        yh[u] = ok ? bf_val(bf_bits(y[vox_of(v, T.b, z, yy, x)])) : 0.f;
+    }
+    __syncthreads();
+    const int zl = threadIdx.x / (CTY * CTX), yl = (threadIdx.x / CTX) % CTY, xl = threadIdx.x % CTX;
+    const int z = T.z0 + zl, yy = T.y0 + yl, x = T.x0 + xl;
+    if (z >= v.D || yy >= v.H || x >= v.W) return;
     float in[27];
 #pragma unroll
-    for (int tap = 0; tap < 27; ++tap) {
-        const int zz = z + tap / 9 - 1, y2 = yy + (tap / 3) % 3 - 1, x2 = x + tap % 3 - 1;
-        const bool ok = zz >= 0 && zz < v.D && y2 >= 0 && y2 < v.H && x2 >= 0 && x2 < v.W;
-        in[tap] = ok ? bf_val(bf_bits(y[vox_of(v, b, zz, y2, x2)])) : 0.f;
-    }
+    for (int tap = 0; tap < 27; ++tap)
+        in[tap] = yh[((zl + tap / 9) * HY + yl + (tap / 3) % 3) * HX + xl + tap % 3];
     uint32_t o[8];
 #pragma unroll
     for (int c = 0; c < 16; c += 2) {
@@ -356,6 +361,7 @@ __global__ void __launch_bounds__(NTH) k_conv0(Vol v, const float *__restrict__ 
         }
         o[c / 2] = pack2(fmaxf(s0, 0.f), fmaxf(s1, 0.f));
     }
+    const size_t i = vox_of(v, T.b, z, yy, x);
     *(u32x4 *)(out + i * 16) = u32x4{o[0], o[1], o[2], o[3]};
     *(u32x4 *)(out + i * 16 + 8) = u32x4{o[4], o[5], o[6], o[7]};
 }
@@ -700,8 +706,10 @@ hipError_t wreduce(const float *part, int nwg, int ne, float *out, const float *
 
 hipError_t conv0_fwd(Vol v, const float *y, const float *w0, const float *b0, bf16_t *out, hipStream_t st)
 {
-    if (v.voxels() == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_conv0, dim3(blocks_for(v.voxels())), dim3(NTH), 0, st, v, y, w0, b0, out);
+    int ntx, nty, ntz, ntiles;
+    tiles(v, ntx, nty, ntz, ntiles);
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_conv0, dim3(ntiles), dim3(NTH), 0, st, v, y, w0, b0, out, ntx, nty, ntz);
     return hipGetLastError();
 }
 
