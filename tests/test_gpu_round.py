@@ -15,10 +15,10 @@ from gpu_common import rel, rounded
 pytestmark = pytest.mark.gpu
 
 
-def setup(shape, seed, prec, kxy, kz, nslices, schedule, mu=0.0, sigma_z=(2.0, 2.0)):
+def setup(shape, seed, prec, kxy, kz, nslices, schedule, mu=0.0, sigma_z=(2.0, 2.0), kappa=0.0):
     nz, ny, nx = shape
     w = inputs.tiny(shape, seed, kxy=kxy, kz=kz, nblocks=len(nslices), sigma_z=sigma_z,
-                    lam=0.01, delta=0.05, eta=0.01)
+                    lam=0.01, delta=0.05, eta=0.01, kappa=kappa)
     gxy = rounded(oracle.gauss_table(w.sigma_xy, w.kxy), prec)
     gz = rounded(oracle.gauss_table(w.sigma_z, w.kz), prec)
     y = rounded(oracle.Problem(np.zeros(shape), gxy, gxy, gz).H(w.xbar) + w.noise, prec)
@@ -33,13 +33,16 @@ def setup(shape, seed, prec, kxy, kz, nslices, schedule, mu=0.0, sigma_z=(2.0, 2
     return g, o, y
 
 
-@pytest.mark.parametrize("shape,nslices,kxy,kz,mu", [
-    ((8, 16, 16), [2, 2, 2, 2], 3, 5, 0.0),
-    ((9, 21, 70), [1, 3, 2, 3], 5, 7, 0.5),
-    ((12, 33, 65), [4, 1, 1, 6], 7, 3, 0.2),
+@pytest.mark.parametrize("shape,nslices,kxy,kz,mu,kappa", [
+    ((8, 16, 16), [2, 2, 2, 2], 3, 5, 0.0, 0.0),
+    ((9, 21, 70), [1, 3, 2, 3], 5, 7, 0.5, 0.0),
+    ((12, 33, 65), [4, 1, 1, 6], 7, 3, 0.2, 0.0),
+    ((10, 19, 37), [3, 2, 1, 4], 9, 9, 0.3, 0.05),
+    ((1, 30, 50), [1], 5, 1, 0.0, 0.0),
+    ((5, 7, 9), [1, 1, 1, 1, 1], 3, 3, 0.1, 0.02),
 ])
-def test_round_trajectory_fp64(orc, shape, nslices, kxy, kz, mu):
-    g, o, y = setup(shape, 5, binding.FP64, kxy, kz, nslices, binding.SCHED_ROUND, mu)
+def test_round_trajectory_fp64(orc, shape, nslices, kxy, kz, mu, kappa):
+    g, o, y = setup(shape, 5, binding.FP64, kxy, kz, nslices, binding.SCHED_ROUND, mu, kappa=kappa)
     nc, order, color = g.get_schedule()
     assert nc == 1 and list(color) == [0] * len(nslices)
     x, d = y.copy(), np.zeros(shape)
@@ -49,7 +52,10 @@ def test_round_trajectory_fp64(orc, shape, nslices, kxy, kz, mu):
         o.run_round(x, d, nslices, cp - done, history=False)
         done = cp
         assert rel(g.get_x(), x) <= 1e-9, cp
-        assert rel(g.get_dprev(), d) <= 1e-9, cp
+        # near convergence the last step is tiny: bound its error by the
+        # iterate's scale as well
+        dd = np.linalg.norm(g.get_dprev() - d)
+        assert dd <= 1e-9 * np.linalg.norm(d) + 1e-13 * np.linalg.norm(x), cp
         assert abs(res["f"] - o.f(x)) <= 1e-12 * abs(o.f(x))
 
 
