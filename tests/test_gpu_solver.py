@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from paper_2002_02328_amd import binding, inputs
-from gpu_common import pair, rel, maxrel
+from gpu_common import pair, rel, maxrel, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -241,3 +241,31 @@ def test_tile_heights_agree_and_autotune_keeps_state(orc):
     g64 = binding.Problem(8, 8, 4, binding.FP64)
     with pytest.raises(binding.Bd3mgError):
         g64.set_option(binding.OPT_TILE_ROWS_UPDATE, 32)
+
+
+def test_large_volume_two_sweeps_against_oracle(orc):
+    """The 512x512x128 workload (PSF 9x9x9, 32 uneven blocks) in FP32: two
+    sweeps from x0 = y against the FP64 oracle's two sweeps on the same
+    rounded inputs."""
+    w = inputs.large_fp32()
+    gxy = rounded(orc.gauss_table(w.sigma_xy, w.kxy), binding.FP32)
+    gz = rounded(orc.gauss_table(w.sigma_z, w.kz), binding.FP32)
+    y = rounded(orc.Problem(np.zeros(w.shape), gxy, gxy, gz).H(w.xbar) + w.noise, binding.FP32)
+    o = orc.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
+    nz, ny, nx = w.shape
+    g = binding.Problem(nx, ny, nz, binding.FP32)
+    g.set_psf_separable(gxy, gxy, gz)
+    g.set_params(w.lam, w.delta, w.eta, w.kappa)
+    g.set_data(y)
+    g.set_blocks(w.nslices)
+    g.set_x0(None)
+    nc, order, _ = g.get_schedule()
+    res = g.run(2)
+    x = y.copy()
+    d = np.zeros(w.shape)
+    o.run(x, d, w.nslices, order, 2, history=False)
+    e = rel(g.get_x(), x)
+    print("512x512x128, 2 sweeps: rel |x_gpu - x_oracle| = %.3e" % e)
+    assert e <= 2e-5
+    assert abs(res["f"] - o.f(x)) <= 1e-6 * abs(o.f(x))
+    g.close()
