@@ -100,7 +100,8 @@ const char *bd3mg_last_error(void);
 bd3mg_status bd3mg_psf_gaussian(int nz, int k, const double *sigma, double *table);
 
 /* Create a problem of nx*ny*nz voxels in the given precision (bd3mg_precision)
- * on the current HIP device.  ERR_ARG: a dimension < 1 or precision unknown. */
+ * on the current HIP device.  ERR_ARG: a dimension < 1, precision unknown, or
+ * one slice (nx*ny elements) of 2 GiB or more. */
 bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *out);
 
 /* Release the handle and all its device memory.  NULL is accepted. */

@@ -587,6 +587,9 @@ bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *
     if (nx < 1 || ny < 1 || nz < 1) return fail(BD3MG_ERR_ARG, "dimensions must be >= 1");
     if (precision != BD3MG_FP64 && precision != BD3MG_FP32)
         return fail(BD3MG_ERR_ARG, "unknown precision %d", precision);
+    // in-slice byte offsets are formed in 32 bits by the kernels
+    if ((size_t)nx * ny * (precision == BD3MG_FP64 ? 8 : 4) >= ((size_t)1 << 31))
+        return fail(BD3MG_ERR_ARG, "a slice of %d x %d exceeds 2 GiB", nx, ny);
     bd3mg_problem p = new (std::nothrow) bd3mg_problem_s;
     if (!p) return fail(BD3MG_ERR_NOMEM, "handle");
     p->nx = nx;

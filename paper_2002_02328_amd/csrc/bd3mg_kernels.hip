@@ -59,7 +59,7 @@ struct Region {
     static constexpr int N = W * H;
     static constexpr int E = cdiv(N, NT);
     static constexpr int PAD = E * NT;  // LDS elements to allocate
-    int off[E];
+    uint32_t off[E];  // element offset in the slice (non-negative, < 2^30)
     bool inb[E];
     __device__ __forceinline__ Region(const Geom &g, int x0, int y0)
     {
@@ -69,13 +69,22 @@ struct Region {
             const int jj = e / W, ii = e - jj * W;
             const int j = y0 - HY + jj, i = x0 - HX + ii;
             inb[q] = e < N && i >= 0 && i < g.nx && j >= 0 && j < g.ny;
-            off[q] = inb[q] ? j * g.nx + i : 0;
+            off[q] = inb[q] ? (uint32_t)(j * g.nx + i) : 0u;
         }
     }
 };
 
 template <int W, int H>
 constexpr int padded() { return cdiv(W * H, NT) * NT; }
+
+// base[eoff] with the byte offset formed in 32 bits: base is uniform across
+// the workgroup, so the load takes the scalar-base plus 32-bit vector-offset
+// form and needs no 64-bit address arithmetic per element.
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, uint32_t eoff)
+{
+    return *(const T *)((const char *)base + eoff * (uint32_t)sizeof(T));
+}
 
 // x pass from I (rows of width WI, at least ROWS rows) to O (rows of width WO,
 // padded to a multiple of NT), WO output columns over ROWS rows:
@@ -196,7 +205,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         const T *xs = x + (size_t)k * S;
 #pragma unroll
         for (int qq = 0; qq < rx.E; ++qq) {
-            const T v = xs[rx.off[qq]];
+            const T v = ldo(xs, rx.off[qq]);
             xr[qq] = rx.inb[qq] ? v : T(0);
         }
     }
@@ -206,7 +215,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         const T *ds = s.dp[0] + (size_t)k * S;
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
-            const T v = ds[rg.off[qq]];
+            const T v = ldo(ds, rg.off[qq]);
             dv[qq] = rg.inb[qq] ? v : T(0);
         }
     }
@@ -217,7 +226,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         const T w = s.gz[(size_t)m * KZ + (c + RZ)];
         const T *qm = q + (size_t)m * S;
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * qm[rg.off[qq]];
+        for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldo(qm, rg.off[qq]);
     }
     if (mode == GM_ZCOMB) {
 #pragma unroll
@@ -479,8 +488,8 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
         const T *gs = gg + (size_t)sl * S, *ds = dpv + (size_t)sl * S;
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
-            v1[qq] -= wv * gs[rg.off[qq]];
-            v2[qq] += wv * ds[rg.off[qq]];
+            v1[qq] -= wv * ldo(gs, rg.off[qq]);
+            v2[qq] += wv * ldo(ds, rg.off[qq]);
         }
     }
 #pragma unroll
@@ -595,19 +604,19 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
                 const T *gs = gg + (size_t)sl * S, *ds = dpi + (size_t)sl * S;
 #pragma unroll
                 for (int qq = 0; qq < rg.E; ++qq)
-                    v[qq] += wv * (u2 * ds[rg.off[qq]] - u1 * gs[rg.off[qq]]);
+                    v[qq] += wv * (u2 * ldo(ds, rg.off[qq]) - u1 * ldo(gs, rg.off[qq]));
             } else if (rnd) {
                 if (sl < 0 || sl >= g.nz) continue;
                 const int b = s.sblk[sl];
                 const T c1 = wv * (T)u[2 * b], c2 = wv * (T)u[2 * b + 1];
                 const T *gs = gg + (size_t)sl * S, *ds = dpi + (size_t)sl * S;
 #pragma unroll
-                for (int qq = 0; qq < rg.E; ++qq) v[qq] += c2 * ds[rg.off[qq]] - c1 * gs[rg.off[qq]];
+                for (int qq = 0; qq < rg.E; ++qq) v[qq] += c2 * ldo(ds, rg.off[qq]) - c1 * ldo(gs, rg.off[qq]);
             } else {
                 if (sl < 0 || sl >= g.nz) continue;
                 const T *ss = src + (size_t)sl * S;
 #pragma unroll
-                for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ss[rg.off[qq]];
+                for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ldo(ss, rg.off[qq]);
             }
         }
 #pragma unroll
@@ -619,7 +628,7 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     if (refresh) {
         const T *ys = s.y + (size_t)m * S;
 #pragma unroll
-        for (int qq = 0; qq < r2.E; ++qq) yv[qq] = ys[r2.off[qq]];
+        for (int qq = 0; qq < r2.E; ++qq) yv[qq] = ldo(ys, r2.off[qq]);
     }
     __syncthreads();
     // 2. forward x pass: all H1 rows, the W2 columns of the R-halo tile
@@ -700,7 +709,7 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
             const T wv = wz[c + RZ];
             const T *ss = in + (size_t)sl * S;
 #pragma unroll
-            for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ss[rg.off[qq]];
+            for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ldo(ss, rg.off[qq]);
         }
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
@@ -749,7 +758,7 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
         const T *im = in + (size_t)m * g.nx * g.ny;
         T v[rg.E];
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) v[qq] = im[rg.off[qq]];
+        for (int qq = 0; qq < rg.E; ++qq) v[qq] = ldo(im, rg.off[qq]);
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
     }
