@@ -196,11 +196,13 @@ struct WgArgs {
 // channels) and the haloed input are staged in LDS channel-major, so the
 // eight consecutive voxels of a k-group are contiguous.  The contraction
 // index is the tile-linear voxel v = 32 ks + 8 q + i (rows of 16 along x);
-// for tap (dz, dy, dx) the input row is read at x offset dx from a 16-byte
-// aligned base and shifted by dx elements in registers.  Wave w owns taps
-// w, w + 4, ...
+// nine wavefronts, wave w owning the three taps (dz, dy) = (w / 3, w % 3),
+// dx = 0, 1, 2: the input row is read once from a 16-byte aligned base and
+// shifted by dx elements in registers for each of the three taps.
+constexpr int WG_THREADS = 9 * 64;
+
 template <int CIN, int COUT, int SRC>
-__global__ void __launch_bounds__(NTH) k_wgrad(WgArgs a)
+__global__ void __launch_bounds__(WG_THREADS) k_wgrad(WgArgs a)
 {
     constexpr int MT = COUT / 16;
     constexpr int NV = CTZ * CTY * CTX;  // 256
@@ -215,20 +217,20 @@ __global__ void __launch_bounds__(NTH) k_wgrad(WgArgs a)
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 15, q = lane >> 4;
-    for (int i = tid; i < 16 * IP / 8; i += NTH) *(u32x4 *)(inT + 8 * i) = u32x4{0u, 0u, 0u, 0u};
+    for (int i = tid; i < 16 * IP / 8; i += WG_THREADS) *(u32x4 *)(inT + 8 * i) = u32x4{0u, 0u, 0u, 0u};
     float bsum = 0.f;
 
     for (int ch = 0; ch < NCH; ++ch) {
-        f32x4 acc[7][MT];
+        f32x4 acc[3][MT];
 #pragma unroll
-        for (int ti = 0; ti < 7; ++ti)
+        for (int ti = 0; ti < 3; ++ti)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) acc[ti][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
 
         for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
             const Tile T = tile_of(t, a.ntx, a.nty, a.ntz);
             __syncthreads();
-            for (int u = tid; u < NV * GU; u += NTH) {
+            for (int u = tid; u < NV * GU; u += WG_THREADS) {
                 const int vl = u / GU, part = u - vl * GU;
                 const int zl = vl / (CTY * CTX), yl = (vl / CTX) % CTY, xl = vl % CTX;
                 const int z = T.z0 + zl, y = T.y0 + yl, x = T.x0 + xl;
@@ -239,7 +241,7 @@ __global__ void __launch_bounds__(NTH) k_wgrad(WgArgs a)
                 for (int j = 0; j < 8; ++j)
                     gT[(part * 8 + j) * GP + vl] = (bf16_t)(val[j >> 1] >> (16 * (j & 1)));
             }
-            for (int u = tid; u < (CTZ + 2) * HY * (CTX + 2) * 2; u += NTH) {
+            for (int u = tid; u < (CTZ + 2) * HY * (CTX + 2) * 2; u += WG_THREADS) {
                 const int hv = u >> 1, part = u & 1;
                 const int hz = hv / (HY * (CTX + 2)), rem = hv - hz * (HY * (CTX + 2));
                 const int hy = rem / (CTX + 2), hx = rem - hy * (CTX + 2);
@@ -267,38 +269,26 @@ __global__ void __launch_bounds__(NTH) k_wgrad(WgArgs a)
                     A[mt] = as_bf8(*(const u32x4 *)(gT + (mt * 16 + n) * GP + ks * 32 + 8 * q));
                 const int row = 2 * ks + (q >> 1);
                 const int zr = row / CTY, yr = row - zr * CTY, xs = 8 * (q & 1);
+                const int dz = wave / 3, dy = wave - 3 * dz;
+                const bf16_t *p = inT + n * IP + ((zr + dz) * HY + (yr + dy)) * HXP + xs;
+                const u32x4 w0 = *(const u32x4 *)p, w1 = *(const u32x4 *)(p + 8);
+                const bf16x8 B[3] = {
+                    as_bf8(w0),
+                    as_bf8(u32x4{__builtin_amdgcn_alignbyte(w0[1], w0[0], 2),
+                                 __builtin_amdgcn_alignbyte(w0[2], w0[1], 2),
+                                 __builtin_amdgcn_alignbyte(w0[3], w0[2], 2),
+                                 __builtin_amdgcn_alignbyte(w1[0], w0[3], 2)}),
+                    as_bf8(u32x4{w0[1], w0[2], w0[3], w1[0]})};
 #pragma unroll
-                for (int ti = 0; ti < 7; ++ti) {
-                    const int tap = wave + 4 * ti;
-                    if (tap >= 27) continue;
-                    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-                    const bf16_t *p = inT + n * IP + ((zr + dz) * HY + (yr + dy)) * HXP + xs;
-                    const u32x4 w0 = *(const u32x4 *)p;
-                    u32x4 Bw;
-                    if (dx == 0) {
-                        Bw = w0;
-                    } else {
-                        const u32x4 w1 = *(const u32x4 *)(p + 8);
-                        if (dx == 2) {
-                            Bw = u32x4{w0[1], w0[2], w0[3], w1[0]};
-                        } else {
-                            Bw = u32x4{__builtin_amdgcn_alignbyte(w0[1], w0[0], 2),
-                                       __builtin_amdgcn_alignbyte(w0[2], w0[1], 2),
-                                       __builtin_amdgcn_alignbyte(w0[3], w0[2], 2),
-                                       __builtin_amdgcn_alignbyte(w1[0], w0[3], 2)};
-                        }
-                    }
-                    const bf16x8 B = as_bf8(Bw);
+                for (int ti = 0; ti < 3; ++ti)
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
-                        acc[ti][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B, acc[ti][mt], 0, 0, 0);
-                }
+                        acc[ti][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[ti], acc[ti][mt], 0, 0, 0);
             }
         }
 #pragma unroll
-        for (int ti = 0; ti < 7; ++ti) {
-            const int tap = wave + 4 * ti;
-            if (tap >= 27) continue;
+        for (int ti = 0; ti < 3; ++ti) {
+            const int tap = 3 * wave + ti;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -697,7 +687,7 @@ hipError_t wgrad3(int cin, int cout, int src, Vol v, const bf16_t *g, ConvIn in,
     if (nwg <= 0) return hipErrorInvalidValue;
 #define X(CI, CO, S)                                                                           \
     if (cin == CI && cout == CO && src == S) {                                                 \
-        hipLaunchKernelGGL((k_wgrad<CI, CO, S>), dim3(nwg), dim3(NTH), 0, st, a);              \
+        hipLaunchKernelGGL((k_wgrad<CI, CO, S>), dim3(nwg), dim3(WG_THREADS), 0, st, a);       \
         return hipGetLastError();                                                              \
     }
     BD3NET_WGRAD_CASES(X)
