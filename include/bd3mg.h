@@ -143,7 +143,13 @@ bd3mg_status bd3mg_set_data(bd3mg_problem p, const void *y, int on_device);
 /* Block partition along z: nblocks blocks of nslices[b] consecutive slices,
  * in z order (Sec. 3.1; the sets are pairwise disjoint, Sec. 2.3 eq. "disj").
  * schedule is a bd3mg_schedule.  ERR_ARG: nblocks < 1, a count < 1, or the
- * counts not summing to nz.  Resets every block's previous step to 0. */
+ * counts not summing to nz.  Resets every block's previous step to 0.
+ * The first run afterwards also allocates, besides the problem's volumes,
+ * room for H d1 and H d2 on S +- r_z of every block updated together (the
+ * direction pass stores them, the update pass combines them): at most 2 (n_c + 2 r_z
+ * b_c) slices for the largest group of b_c blocks with n_c slices in all; for
+ * BD3MG_SCHED_ROUND, 2 (nz + 2 r_z nblocks) slices.  ERR_NOMEM there if that
+ * does not fit. */
 bd3mg_status bd3mg_set_blocks(bd3mg_problem p, int nblocks, const int *nslices, int schedule);
 
 /* The sweep order in use: *ncolors, order[nblocks] (block indices in update

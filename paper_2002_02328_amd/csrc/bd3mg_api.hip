@@ -76,6 +76,10 @@ struct bd3mg_problem_s {
     size_t br_alloc = 0;
     Item *d_vol = nullptr;  // every slice of the volume, for whole-volume passes
     int *d_sblk = nullptr;  // block of every slice
+    int2 *d_pairs = nullptr;  // (direction slot, block) sources of the update items
+    size_t pairs_alloc = 0;
+    void *d_hd = nullptr;     // H d1 then H d2 of a launch group's direction items
+    size_t hd_alloc = 0, hd_slots = 0;
 
     // reductions
     double *d_pg = nullptr, *d_pd = nullptr, *d_pe = nullptr, *d_pr = nullptr;
@@ -126,6 +130,8 @@ DevState<T> dev_state(bd3mg_problem p)
     s.gy = (const T *)p->d_gy;
     s.gz = (const T *)p->d_gz;
     s.sblk = p->d_sblk;
+    s.hd[0] = (T *)p->d_hd;
+    s.hd[1] = s.hd[0] ? s.hd[0] + p->hd_slots * p->nx * p->ny : nullptr;
     s.stop = nullptr;
     return s;
 }
@@ -268,11 +274,13 @@ void color_blocks(bd3mg_problem p)
 // Work items of a launch group (a set of blocks updated together):
 //   gradient pass: the blocks' own slices S;
 //   direction pass: S +- r_z (and slice z0 - 1 when kappa > 0, for VZ);
-//   update pass: S +- r_z,
-// all clipped to the volume, block by block in z order.
+//   update pass: S +- r_z (a round: every slice of the volume once),
+// all clipped to the volume, block by block in z order.  Each update item
+// lists its sources: the (direction slot, block) pairs whose stored H d1,
+// H d2 on the item's slice make up H d' there.
 void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<Item> &gi,
-                 std::vector<Item> &di, std::vector<Item> &ui, std::vector<BlockRange> &br,
-                 bd3mg_problem_s::Group &grp, bool round = false)
+                 std::vector<Item> &di, std::vector<Item> &ui, std::vector<int2> &pairs,
+                 std::vector<BlockRange> &br, bd3mg_problem_s::Group &grp, bool round = false)
 {
     const int rz = p->kz / 2;
     const int rd = std::max(rz, p->prm.kappa > 0.0 ? 1 : 0);
@@ -281,17 +289,20 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     grp.u_off = (int)ui.size();
     grp.br_off = (int)br.size();
     std::vector<char> halo(p->nz, 0);
-    double sl = 0.0;
+    std::vector<int> dfirst, dlo;  // per block of the group: first direction slot, its slice
+    double sl = 0.0, np = 0.0;
     for (int b : blocks) {
         const int z0 = p->z0[b], n = p->nsl[b];
-        const int bri = (int)br.size() - grp.br_off;
         BlockRange r{b, (int)gi.size() - grp.g_off, 0, (int)di.size() - grp.d_off, 0};
-        for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n, bri, 0});
-        for (int k = std::max(0, z0 - rd); k < std::min(p->nz, z0 + n + rz); ++k)
-            di.push_back(Item{k, b, z0, n, bri, 0});
+        for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n, 0, 0});
+        const int lo = std::max(0, z0 - rd);
+        dfirst.push_back(r.d0);
+        dlo.push_back(lo);
+        for (int k = lo; k < std::min(p->nz, z0 + n + rz); ++k) di.push_back(Item{k, b, z0, n, 0, 0});
         if (!round)
             for (int k = std::max(0, z0 - rz); k < std::min(p->nz, z0 + n + rz); ++k) {
-                ui.push_back(Item{k, b, z0, n, bri, 0});
+                ui.push_back(Item{k, b, z0, n, (int)pairs.size(), 1});
+                pairs.push_back(int2{r.d0 + k - lo, b});
                 halo[k] = 1;
             }
         r.gn = (int)gi.size() - grp.g_off - r.g0;
@@ -300,15 +311,22 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
         sl += n;
     }
     if (round) {
-        // one update item per slice of the volume; each source slice of the
-        // z-combine takes the coefficients of its own block
+        // one update item per slice of the volume, with a source pair for
+        // every block whose S +- r_z holds the slice; x and dp are updated
+        // with the coefficients of the slice's own block
         for (int k = 0; k < p->nz; ++k) {
             int b = 0;
             while (p->z0[b] + p->nsl[b] <= k) ++b;
-            ui.push_back(Item{k, b, p->z0[b], p->nsl[b], -1, 0});
+            const int h0 = (int)pairs.size();
+            for (size_t t = 0; t < blocks.size(); ++t) {
+                const int c = blocks[t], z0 = p->z0[c], z1 = z0 + p->nsl[c];
+                if (k >= z0 - rz && k < z1 + rz) pairs.push_back(int2{dfirst[t] + k - dlo[t], c});
+            }
+            ui.push_back(Item{k, b, p->z0[b], p->nsl[b], h0, (int)pairs.size() - h0});
             halo[k] = 1;
         }
     }
+    for (int t = grp.u_off; t < (int)ui.size(); ++t) np += ui[t].hn;
     grp.round = round;
     grp.g_cnt = (int)gi.size() - grp.g_off;
     grp.d_cnt = (int)di.size() - grp.d_off;
@@ -318,14 +336,14 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     for (char c : halo) h += c;
     // Algorithmic bytes (every element a pass must read or write counted once):
     // gradient pass reads q on S +- r_z and x, dp on S and writes g on S;
-    // direction pass reads g and dp on S; solve reads the partial sums;
-    // update pass reads g, dp, x on S and q on S +- r_z, writes x, dp on S and
-    // q on S +- r_z.
+    // direction pass reads g and dp on S and writes H d1, H d2 of its items;
+    // solve reads the partial sums; update pass reads H d1, H d2 of its source
+    // pairs, g, dp, x on S and q on S +- r_z, writes x, dp on S and q on S +- r_z.
     const double A = (double)p->nx * p->ny * p->esz;
     grp.bytes[0] = A * (h + 3.0 * sl);
-    grp.bytes[1] = A * 2.0 * sl;
+    grp.bytes[1] = A * (2.0 * sl + 2.0 * grp.d_cnt);
     grp.bytes[2] = (double)(grp.g_cnt * NQG + grp.d_cnt * NQD) * p->ntiles * sizeof(double);
-    grp.bytes[3] = A * (5.0 * sl + 2.0 * h);
+    grp.bytes[3] = A * (2.0 * np + 5.0 * sl + 2.0 * h);
 }
 
 bd3mg_status build_schedule(bd3mg_problem p)
@@ -336,15 +354,16 @@ bd3mg_status build_schedule(bd3mg_problem p)
     color_blocks(p);
     const int nb = (int)p->nsl.size();
     std::vector<Item> gi, di, ui;
+    std::vector<int2> pairs;
     std::vector<BlockRange> br;
     p->groups.assign(p->ncolors + nb, bd3mg_problem_s::Group{});
     for (int c = 0; c < p->ncolors; ++c) {
         std::vector<int> blocks;
         for (int b : p->order)
             if (p->color[b] == c) blocks.push_back(b);
-        group_items(p, blocks, gi, di, ui, br, p->groups[c], p->schedule == BD3MG_SCHED_ROUND);
+        group_items(p, blocks, gi, di, ui, pairs, br, p->groups[c], p->schedule == BD3MG_SCHED_ROUND);
     }
-    for (int b = 0; b < nb; ++b) group_items(p, {b}, gi, di, ui, br, p->groups[p->ncolors + b]);
+    for (int b = 0; b < nb; ++b) group_items(p, {b}, gi, di, ui, pairs, br, p->groups[p->ncolors + b]);
     // one device array: gradient items, then direction items, then update items
     const int ng = (int)gi.size(), nd = (int)di.size();
     for (auto &grp : p->groups) {
@@ -359,6 +378,9 @@ bd3mg_status build_schedule(bd3mg_problem p)
     HIP_TRY(hipMemcpyAsync(p->d_items, all.data(), all.size() * sizeof(Item), hipMemcpyHostToDevice,
                            p->stream));
     HIP_TRY(hipMemcpyAsync(p->d_br, br.data(), br.size() * sizeof(BlockRange), hipMemcpyHostToDevice,
+                           p->stream));
+    ST_TRY(realloc_dev((void **)&p->d_pairs, &p->pairs_alloc, pairs.size() * sizeof(int2), "update sources"));
+    HIP_TRY(hipMemcpyAsync(p->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice,
                            p->stream));
     {
         std::vector<int> sblk(p->nz);
@@ -387,6 +409,10 @@ bd3mg_status build_schedule(bd3mg_problem p)
     ST_TRY(realloc_dev((void **)&p->d_pd, &p->pd_cap,
                        (size_t)maxd * tiles_of(p->geom, 16) * NQD * sizeof(double),
                        "direction partial sums"));
+    // H d1 and H d2 of the largest group's direction items
+    ST_TRY(realloc_dev(&p->d_hd, &p->hd_alloc, 2 * (size_t)maxd * p->nx * p->ny * p->esz,
+                       "stored directions H d1, H d2"));
+    p->hd_slots = (size_t)maxd;
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->sched_dirty = false;
     return BD3MG_OK;
@@ -398,7 +424,7 @@ bd3mg_status refresh_t(bd3mg_problem p, const T *src, T *qout, const int *stop)
 {
     DevState<T> s = dev_state<T>(p);
     s.stop = stop;
-    HIP_TRY(launch_update<T>(p->geom, s, src, qout, p->d_vol, p->nz, nullptr, UM_REFRESH, p->stream));
+    HIP_TRY(launch_refresh<T>(p->geom, s, src, qout, p->d_vol, p->nz, p->stream));
     return BD3MG_OK;
 }
 
@@ -506,8 +532,7 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
                          p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
-    HIP_TRY(launch_update<T>(p->geom, s, nullptr, s.q, it + gr.u_off, gr.u_cnt, p->d_u,
-                             gr.round ? UM_ROUND : UM_UPDATE, p->stream));
+    HIP_TRY(launch_update<T>(p->geom, s, it + gr.u_off, gr.u_cnt, p->d_pairs, p->d_u, p->stream));
     if (prof) ST_TRY(prof_end(p));
     return BD3MG_OK;
 }
@@ -533,7 +558,7 @@ bd3mg_status apply_t(bd3mg_problem p, int op, T *ti, T *to, T *tr)
         HIP_TRY(launch_grad<T>(p->geom, p->prm, s, tr, ti, to, p->d_vol, p->nz, GM_ZCOMB, nullptr,
                                p->stream));
     } else {
-        HIP_TRY(launch_update<T>(p->geom, s, ti, tr, p->d_vol, p->nz, nullptr, UM_REFRESH, p->stream));
+        HIP_TRY(launch_refresh<T>(p->geom, s, ti, tr, p->d_vol, p->nz, p->stream));
         HIP_TRY(launch_grad<T>(p->geom, p->prm, s, tr, ti, to, p->d_vol, p->nz, GM_GRAD, nullptr,
                                p->stream));
     }
@@ -622,7 +647,7 @@ bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *
         if (hipMalloc(v, p->N * p->esz) != hipSuccess) return bail(BD3MG_ERR_NOMEM, "volume allocation failed");
     // every slice of the volume as a work item, and the evaluation sums
     std::vector<Item> vol;
-    for (int k = 0; k < nz; ++k) vol.push_back(Item{k, -1, 0, nz, -1, 0});
+    for (int k = 0; k < nz; ++k) vol.push_back(Item{k, -1, 0, nz, 0, 0});
     const size_t nslot = (size_t)p->ntiles * nz;
     if (hipMalloc(&p->d_vol, vol.size() * sizeof(Item)) != hipSuccess ||
         hipMalloc(&p->d_pe, nslot * NQE * sizeof(double)) != hipSuccess ||
@@ -643,7 +668,7 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2],
                     p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_sblk, p->d_pg, p->d_pd,
-                    p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl};
+                    p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_pairs, p->d_hd};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &q : p->pending) {

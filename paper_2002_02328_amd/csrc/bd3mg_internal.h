@@ -62,8 +62,10 @@ struct Item {
     int block;
     int z0;
     int n;
-    int bri;  // index of the block's BlockRange in its launch group (-1: none)
-    int pad;
+    // update items: the source pairs [h0, h0 + hn) of the launch group's pair
+    // list, each (direction slot, block) whose stored H d1, H d2 on slice k
+    // enter H d' on slice k
+    int h0, hn;
 };
 
 // Work items of one block inside the item lists of a launch group.
@@ -100,7 +102,8 @@ struct DevState {
     const int *stop;           // when non-null and set, every pass returns at entry
     const T *gx, *gy;          // in-slice PSF tables [nz][2R + 1], centred, zero-padded
     const T *gz;               // z PSF table [nz][kz]
-    const int *sblk;           // block of every slice (round updates), else null
+    const int *sblk;           // block of every slice
+    T *hd[2];                  // H d1, H d2 of the launch group's direction items [slot][ny][nx]
 };
 
 enum GradMode : int {
@@ -110,25 +113,25 @@ enum GradMode : int {
     GM_GRAD = 3    // out = grad f
 };
 
-enum UpdateMode : int {
-    UM_UPDATE = 0,   // d' = -u1 g + u2 dp on the block: q += XY^T H d', x += d', dp[1] = d'
-    UM_REFRESH = 1,  // q = XY^T (H src - y) on the items' slices
-    UM_ROUND = 2     // every slice once, d' = -u1 g + u2 dp with the coefficients of
-                     // each slice's own block (s.sblk): q += XY^T H d', x += d', dp[1] = d'
-};
-
 template <typename T>
 hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *q,
                        const T *x, T *out, const Item *items, int nitems, int mode,
                        double *partials, hipStream_t st);
 
+// Direction pass; also stores H d1, H d2 of item i at slot i of s.hd.
 template <typename T>
 hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
                        int nitems, double *partials, hipStream_t st);
 
+// Update pass from the stored H d1, H d2 (pairs: (slot, block) per source).
 template <typename T>
-hipError_t launch_update(const Geom &g, const DevState<T> &s, const T *src, T *qout,
-                         const Item *items, int nitems, const double *u, int mode, hipStream_t st);
+hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
+                         const int2 *pairs, const double *u, hipStream_t st);
+
+// qout = XY^T (H src - y) on the items' slices.
+template <typename T>
+hipError_t launch_refresh(const Geom &g, const DevState<T> &s, const T *src, T *qout,
+                          const Item *items, int nitems, hipStream_t st);
 
 // out = H(in) - sub (sub may be null) on the items' slices; with partials,
 // each slot also receives its sum of out^2.

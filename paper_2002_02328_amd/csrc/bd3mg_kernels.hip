@@ -457,10 +457,13 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W = TX + 2 * R, H = TYK + 2 * R;
+    // the x pass of d2 is written over the z-combine of d1 (three tiles, not
+    // four: more workgroups fit a compute unit's LDS)
     __shared__ T A1[padded<W, H>()];
     __shared__ T A2[padded<W, H>()];
     __shared__ T B1[padded<TX, H>()];
-    __shared__ T B2[padded<TX, H>()];
+    T *const B2 = A1;
+    static_assert(padded<TX, H>() <= padded<W, H>(), "x pass of d2 must fit the d1 tile");
     __shared__ double red[(NT / 64) * NQD];
 
     const Item it = items[blockIdx.z];
@@ -499,11 +502,25 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     }
     __syncthreads();
     xpass<T, R, W, TX, H, R, false>(A1, B1, wx);
+    __syncthreads();
     xpass<T, R, W, TX, H, R, false>(A2, B2, wx);
     __syncthreads();
     T h1[NRK], h2[NRK];
     ypass_out<T, R, TX, R, false, NRK>(B1, h1, wy);
     ypass_out<T, R, TX, R, false, NRK>(B2, h2, wy);
+    {
+        // stored for the update pass, which combines them with the step
+        // coefficients instead of blurring the new step again
+        T *o1 = s.hd[0] + (size_t)blockIdx.z * S, *o2 = s.hd[1] + (size_t)blockIdx.z * S;
+#pragma unroll
+        for (int e = 0; e < NRK; ++e) {
+            const int j = y0 + out_row(e), i = x0 + tx;
+            if (i >= g.nx || j >= g.ny) continue;
+            const size_t o = (size_t)j * g.nx + i;
+            o1[o] = h1[e];
+            o2[o] = h2[e];
+        }
+    }
 
     double qs[NQD];
 #pragma unroll
@@ -539,36 +556,115 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
 }
 
 // ---------------------------------------------------------------------------
-// Update pass, one slice m per item.
-// UM_UPDATE (block S = [z0, z0+n), step coefficients u of the block):
-//   d' = -u1 g + u2 dp on S;  q_m += XY^T_m (H d')_m  (m in S +- r_z);
-//   and for m in S: x_m += d'_m, dp[1]_m = d'_m.
-// UM_REFRESH: q_m = XY^T_m (H src - y)_m.
-// UM_ROUND (items: every slice once): as UM_UPDATE with the blocks of a round
-//   all at once, each source slice j scaled by the coefficients of its own
-//   block s.sblk[j] (the steps have disjoint supports, so H of their sum is
-//   the sum of their H).
-// (H v)_m is formed on the tile plus an R halo (z-combine on a 2R halo, x and
-// y passes), zeroed outside the slice (the adjoint blur sees zero padding),
-// then blurred back by the adjoint x and y passes of slice m.  Previous steps
-// are read from dp[0] and written to dp[1], so a workgroup reading its
-// neighbours' halo never sees a half-updated step.
+// Update pass, one slice m per item, from the direction pass's stored
+// H d1, H d2 (d1 = -g, d2 = dp on the block S, zero elsewhere):
+//   (H d')_m = sum over the item's pairs (slot, b) of u1_b (H d1)_slot + u2_b (H d2)_slot,
+//   q_m += XY^T_m (H d')_m,
+//   and for m in the item's own block: d'_m = -u1 g_m + u2 dp_m, x_m += d'_m,
+//   dp[1]_m = d'_m.
+// A coloured group has one pair per item (the blocks of a colour have
+// disjoint S +- r_z); a round has every block whose S +- r_z holds m (the
+// steps have disjoint supports, so H of their sum is the sum of their H).
+// H d' is read on the tile plus an R halo (zero outside the slice: the
+// adjoint blur sees zero padding), then blurred back by the adjoint x and y
+// passes of slice m.  Previous steps are read from dp[0] and written to
+// dp[1], so a workgroup never sees a half-updated step.
+// ---------------------------------------------------------------------------
+template <typename T, int R, int TYK>
+__global__ void __launch_bounds__(NT)
+k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ pairs,
+         const double *__restrict__ u)
+{
+    constexpr int NRK = TYK / (NT / TX);
+    if (s.stop && *s.stop) return;
+    constexpr int K = 2 * R + 1;
+    constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R;
+    __shared__ T A[padded<W2, H2>()];
+    __shared__ T B[padded<TX, H2>()];
+
+    const Item it = items[blockIdx.z];
+    const int m = it.k;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
+    const int tx = threadIdx.x & (TX - 1);
+    const size_t S = (size_t)g.nx * g.ny;
+    T wx[K], wy[K];
+    load_taps<T, R>(wx, s.gx + (size_t)m * K);
+    load_taps<T, R>(wy, s.gy + (size_t)m * K);
+    // the outputs' q, and on the block x, dp and g, are loaded first so that
+    // their latency overlaps the loads of H d'
+    const bool ins = (m >= it.z0 && m < it.z0 + it.n);
+    const T *qs = s.q + (size_t)m * S, *xs = s.x + (size_t)m * S;
+    const T *ds = s.dp[0] + (size_t)m * S, *gs = s.g + (size_t)m * S;
+    T qv[NRK], xv[NRK], dv[NRK], gv[NRK];
+#pragma unroll
+    for (int e = 0; e < NRK; ++e) {
+        const int j = y0 + out_row(e), i = x0 + tx;
+        const uint32_t o = (i < g.nx && j < g.ny) ? (uint32_t)(j * g.nx + i) : 0u;
+        qv[e] = ldo(qs, o);
+        xv[e] = dv[e] = gv[e] = 0;
+        if (ins) {
+            xv[e] = ldo(xs, o);
+            dv[e] = ldo(ds, o);
+            gv[e] = ldo(gs, o);
+        }
+    }
+    {
+        Region<W2, H2, R, R> rg(g, x0, y0);
+        T v[rg.E];
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) v[qq] = 0;
+        for (int p = 0; p < it.hn; ++p) {
+            const int2 pr = pairs[it.h0 + p];
+            const T c1 = (T)u[2 * pr.y], c2 = (T)u[2 * pr.y + 1];
+            const T *h1 = s.hd[0] + (size_t)pr.x * S, *h2 = s.hd[1] + (size_t)pr.x * S;
+#pragma unroll
+            for (int qq = 0; qq < rg.E; ++qq) v[qq] += c1 * ldo(h1, rg.off[qq]) + c2 * ldo(h2, rg.off[qq]);
+        }
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
+    }
+    __syncthreads();
+    xpass<T, R, W2, TX, H2, R, true>(A, B, wx);
+    __syncthreads();
+    T v[NRK];
+    ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
+    const T u1 = ins ? (T)u[2 * it.block] : T(0), u2 = ins ? (T)u[2 * it.block + 1] : T(0);
+#pragma unroll
+    for (int e = 0; e < NRK; ++e) {
+        const int j = y0 + out_row(e), i = x0 + tx;
+        if (i >= g.nx || j >= g.ny) continue;
+        const size_t o = vidx(g, m, j, i);
+        s.q[o] = qv[e] + v[e];
+        if (ins) {
+            const T d = u2 * dv[e] - u1 * gv[e];
+            s.x[o] = xv[e] + d;
+            s.dp[1][o] = d;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Refresh of the blurred residual, one slice m per item:
+//   q_m = XY^T_m (H src - y)_m.
+// (H src)_m is formed on the tile plus an R halo (z-combine on a 2R halo, x
+// and y passes), zeroed outside the slice, then blurred back by the adjoint
+// x and y passes of slice m.
 // ---------------------------------------------------------------------------
 template <typename T, int KZ, int R, int TYK>
 __global__ void __launch_bounds__(NT)
-k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
-         const Item *__restrict__ items, const double *__restrict__ u, int mode)
+k_refresh(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
+          const Item *__restrict__ items)
 {
     constexpr int NRK = TYK / (NT / TX);
     if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W1 = TX + 4 * R, H1 = TYK + 4 * R;  // z-combined source, 2R halo
-    constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R;  // H v, R halo
-    __shared__ T A[padded<W1, H1>()];                // z-combined source, later H v
+    constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R;  // H src - y, R halo
+    __shared__ T A[padded<W1, H1>()];                // z-combined source, later H src - y
     __shared__ T B[padded<W2, H1>()];                // forward x pass, later adjoint x pass
 
     const Item it = items[blockIdx.z];
-    const int m = it.k, z0 = it.z0, z1 = it.z0 + it.n;
+    const int m = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
@@ -576,18 +672,6 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     T wx[K], wy[K];
     load_taps<T, R>(wx, s.gx + (size_t)m * K);
     load_taps<T, R>(wy, s.gy + (size_t)m * K);
-    const bool upd = (mode == UM_UPDATE), rnd = (mode == UM_ROUND), refresh = (mode == UM_REFRESH);
-    T u1 = 0, u2 = 0;
-    if (upd) {
-        u1 = (T)u[2 * it.block];
-        u2 = (T)u[2 * it.block + 1];
-    } else if (rnd) {
-        const int b = s.sblk[m];
-        u1 = (T)u[2 * b];
-        u2 = (T)u[2 * b + 1];
-    }
-    const T *__restrict__ gg = s.g;
-    const T *__restrict__ dpi = s.dp[0];
 
     // 1. z-combine of the source on the tile plus a 2R halo
     {
@@ -598,34 +682,19 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
 #pragma unroll
         for (int c = -RZ; c <= RZ; ++c) {
             const int sl = m - c;
+            if (sl < 0 || sl >= g.nz) continue;
             const T wv = wz[c + RZ];
-            if (upd) {
-                if (sl < z0 || sl >= z1) continue;
-                const T *gs = gg + (size_t)sl * S, *ds = dpi + (size_t)sl * S;
+            const T *ss = src + (size_t)sl * S;
 #pragma unroll
-                for (int qq = 0; qq < rg.E; ++qq)
-                    v[qq] += wv * (u2 * ldo(ds, rg.off[qq]) - u1 * ldo(gs, rg.off[qq]));
-            } else if (rnd) {
-                if (sl < 0 || sl >= g.nz) continue;
-                const int b = s.sblk[sl];
-                const T c1 = wv * (T)u[2 * b], c2 = wv * (T)u[2 * b + 1];
-                const T *gs = gg + (size_t)sl * S, *ds = dpi + (size_t)sl * S;
-#pragma unroll
-                for (int qq = 0; qq < rg.E; ++qq) v[qq] += c2 * ldo(ds, rg.off[qq]) - c1 * ldo(gs, rg.off[qq]);
-            } else {
-                if (sl < 0 || sl >= g.nz) continue;
-                const T *ss = src + (size_t)sl * S;
-#pragma unroll
-                for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ldo(ss, rg.off[qq]);
-            }
+            for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ldo(ss, rg.off[qq]);
         }
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
     }
-    // the data term of a refresh is needed on the R halo; load it early
+    // the data term is needed on the R halo; load it early
     Region<W2, H2, R, R> r2(g, x0, y0);
     T yv[r2.E];
-    if (refresh) {
+    {
         const T *ys = s.y + (size_t)m * S;
 #pragma unroll
         for (int qq = 0; qq < r2.E; ++qq) yv[qq] = ldo(ys, r2.off[qq]);
@@ -634,7 +703,7 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     // 2. forward x pass: all H1 rows, the W2 columns of the R-halo tile
     xpass<T, R, W1, W2, H1, R, false>(A, B, wx);
     __syncthreads();
-    // 3. forward y pass on the R-halo tile into A (H v), zero outside the slice
+    // 3. forward y pass on the R-halo tile into A (H src - y), zero outside the slice
 #pragma unroll
     for (int qq = 0; qq < r2.E; ++qq) {
         const int e = threadIdx.x + qq * NT;
@@ -645,8 +714,7 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
         T acc = 0;
 #pragma unroll
         for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[-b * W2];
-        if (refresh) acc -= yv[qq];
-        A[e] = r2.inb[qq] ? acc : T(0);
+        A[e] = r2.inb[qq] ? acc - yv[qq] : T(0);
     }
     __syncthreads();
     // 4. adjoint x pass over the R-halo rows into B
@@ -659,17 +727,7 @@ k_update(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout,
     for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
-        const size_t o = vidx(g, m, j, i);
-        if (!refresh) {
-            qout[o] += v[e];
-            if (rnd || (m >= z0 && m < z1)) {
-                const T d = u2 * dpi[o] - u1 * gg[o];
-                s.x[o] += d;
-                s.dp[1][o] = d;
-            }
-        } else {
-            qout[o] = v[e];
-        }
+        qout[vidx(g, m, j, i)] = v[e];
     }
 }
 
@@ -892,13 +950,24 @@ hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, c
 }
 
 template <typename T>
-hipError_t launch_update(const Geom &g, const DevState<T> &s, const T *src, T *qout, const Item *items,
-                         int nitems, const double *u, int mode, hipStream_t st)
+hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
+                         const int2 *pairs, const double *u, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
-                    hipLaunchKernelGGL((k_update<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0,
-                                       st, g, s, src, qout, items, u, mode))));
+    BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
+                   hipLaunchKernelGGL((k_update<T, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
+                                      g, s, items, pairs, u)));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_refresh(const Geom &g, const DevState<T> &s, const T *src, T *qout, const Item *items,
+                          int nitems, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_aux,
+                    hipLaunchKernelGGL((k_refresh<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                                       st, g, s, src, qout, items))));
     return hipGetLastError();
 }
 
@@ -961,8 +1030,10 @@ hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
                                        double *, hipStream_t);                                    \
     template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
                                        const Item *, int, double *, hipStream_t);                 \
-    template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const T *, T *,        \
-                                         const Item *, int, const double *, int, hipStream_t);    \
+    template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Item *, int,      \
+                                         const int2 *, const double *, hipStream_t);              \
+    template hipError_t launch_refresh<T>(const Geom &, const DevState<T> &, const T *, T *,       \
+                                          const Item *, int, hipStream_t);                        \
     template hipError_t launch_H<T>(const Geom &, const DevState<T> &, const T *, const T *, T *,  \
                                     const Item *, int, double *, hipStream_t);                    \
     template hipError_t launch_blurT<T>(const Geom &, const DevState<T> &, const T *, T *,         \

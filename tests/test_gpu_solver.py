@@ -141,9 +141,13 @@ def test_profile_counts_launches(orc):
         n, ms, by = prof[k]
         assert n == 3 * nc and ms > 0 and by > 0
     assert prof["eval"][0] == 0
-    # direction pass of one sweep reads g and dp once on every block slice
+    # per sweep, the direction pass reads g and dp on every block slice and
+    # writes H d1, H d2 on S +- r_z of every block (6 + 8 + 8 + 6 slices);
+    # the update pass reads H d1, H d2 there, reads g, dp, x and writes x, dp
+    # on the block slices, and reads and writes q on S +- r_z
     A = 64 * 64 * 8
-    assert prof["dirs"][2] == 3 * 2 * 16 * A
+    assert prof["dirs"][2] == 3 * (2 * 16 + 2 * 28) * A
+    assert prof["update"][2] == 3 * (2 * 28 + 5 * 16 + 2 * 28) * A
     assert g.get_profile()["grad"][0] == 0
 
 
