@@ -45,7 +45,10 @@ __device__ __forceinline__ T clampv(T v, T lo, T hi) { return v < lo ? lo : (v >
 __device__ __forceinline__ float inv_sqrt(float v) { return rsqrtf(v); }
 __device__ __forceinline__ double inv_sqrt(double v) { return 1.0 / sqrt(v); }
 
-__device__ __forceinline__ int out_row(int e) { return (int)(threadIdx.x / TX) + (NT / TX) * e; }
+// Tile row of a thread's e-th output when each thread owns NR consecutive
+// rows of one column (wavefront w holds rows [w NR, (w + 1) NR)).
+template <int NR>
+__device__ __forceinline__ int out_row(int e) { return (int)(threadIdx.x / TX) * NR + e; }
 
 constexpr int cdiv(int a, int b) { return (a + b - 1) / b; }
 
@@ -109,18 +112,82 @@ __device__ __forceinline__ void xpass(const T *I, T *O, const T (&wx)[2 * R + 1]
     }
 }
 
-// y pass into registers: v[e] at tile row out_row(e), column threadIdx.x % TX,
-// reading rows (out_row + OFF -/+ b) of B (rows of width WB); NR rows per thread.
+// Row stride of an LDS tile W elements wide whose rows are read 16 bytes at
+// a time: W rounded up to a whole number of 16-byte words.
+template <typename T, int W>
+constexpr int vstride() { return cdiv(W * (int)sizeof(T), 16) * 16 / (int)sizeof(T); }
+
+// LDS index of region element e (row e / W, column e % W) in a tile of row
+// stride WS.
+template <int W, int WS>
+__device__ __forceinline__ int lds_at(int e)
+{
+    const int r = e / W;
+    return r * WS + (e - r * W);
+}
+
+// x pass to TX output columns, four consecutive outputs per thread: from I
+// (rows of stride WS = vstride<T, TX + 2R>(), 16-byte aligned; column c of
+// the output tile reads columns c .. c + 2R) to O (rows of width TX), over
+// ROWS rows:
+//   forward O[r][c] = sum_a wx[a] I[r][c + R - a],
+//   adjoint O[r][c] = sum_a wx[a] I[r][c + R + a].
+// The 4 + 2R inputs of a thread are read as whole 16-byte words.
+template <typename T, int R, int ROWS, bool ADJ>
+__device__ __forceinline__ void xpass4(const T *I, T *O, const T (&wx)[2 * R + 1])
+{
+    constexpr int WS = vstride<T, TX + 2 * R>();
+    constexpr int VW = 16 / (int)sizeof(T);  // elements per 16-byte word
+    constexpr int NI = 4 + 2 * R, NL = cdiv(NI, VW);
+    static_assert(TX % 4 == 0 && WS % VW == 0 && (TX - 4) + NL * VW <= WS, "x pass reads stay in the row");
+    constexpr int G = TX / 4, N = G * ROWS, E = cdiv(N, NT);
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int e = threadIdx.x + q * NT;
+        if (N % NT != 0 && e >= N) break;
+        const int r = e / G, c = 4 * (e - r * G);
+        T in[NL * VW];
+        const uint4 *src = reinterpret_cast<const uint4 *>(I + r * WS + c);
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const uint4 w = src[l];
+            __builtin_memcpy(in + l * VW, &w, 16);
+        }
+        T out[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            T acc = 0;
+#pragma unroll
+            for (int a = -R; a <= R; ++a) acc += wx[a + R] * in[v + R + (ADJ ? a : -a)];
+            out[v] = acc;
+        }
+        uint4 *dst = reinterpret_cast<uint4 *>(O + r * TX + c);
+#pragma unroll
+        for (int l = 0; l < 4 / VW; ++l) {
+            uint4 w;
+            __builtin_memcpy(&w, out + l * VW, 16);
+            dst[l] = w;
+        }
+    }
+}
+
+// y pass into registers: v[e] at tile row out_row<NR>(e), column
+// threadIdx.x % TX, reading rows (out_row + OFF -/+ b) of B (rows of width
+// WB).  A thread's NR rows are consecutive, so it reads the NR + 2R values of
+// its column once and slides the stencil over them.
 template <typename T, int R, int WB, int OFF, bool ADJ, int NR>
 __device__ __forceinline__ void ypass_out(const T *B, T (&v)[NR], const T (&wy)[2 * R + 1])
 {
     const int i = threadIdx.x & (TX - 1);
+    const T *col = B + (out_row<NR>(0) + OFF - R) * WB + i;
+    T c[NR + 2 * R];
+#pragma unroll
+    for (int t = 0; t < NR + 2 * R; ++t) c[t] = col[t * WB];
 #pragma unroll
     for (int e = 0; e < NR; ++e) {
-        const T *col = B + (out_row(e) + OFF) * WB + i;
         T acc = 0;
 #pragma unroll
-        for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[(ADJ ? b : -b) * WB];
+        for (int b = -R; b <= R; ++b) acc += wy[b + R] * c[e + R + (ADJ ? b : -b)];
         v[e] = acc;
     }
 }
@@ -328,7 +395,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         const int tx = threadIdx.x & (TX - 1);
 #pragma unroll
         for (int e = 0; e < RPT; ++e) {
-            const int lj = out_row(e), li = tx;
+            const int lj = out_row<RPT>(e), li = tx;
             const int j = y0 + lj, i = x0 + li;
             if (i >= g.nx || j >= g.ny) continue;
             const double w = (double)WW[(lj + 1) * PW + (li + 1)];
@@ -457,14 +524,17 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W = TX + 2 * R, H = TYK + 2 * R;
-    // the x pass of d2 is written over the z-combine of d1 (three tiles, not
-    // four: more workgroups fit a compute unit's LDS)
-    __shared__ T A1[padded<W, H>()];
-    __shared__ T A2[padded<W, H>()];
-    __shared__ T B1[padded<TX, H>()];
+    // the x pass of d2 is written over the z-combine of d1, and the
+    // reduction of the inner products over the z-combine of d2 (three tiles,
+    // not four: more workgroups fit a compute unit's LDS)
+    constexpr int WS = vstride<T, W>();
+    __shared__ __align__(16) T A1[padded<WS, H>()];
+    __shared__ __align__(16) T A2[padded<WS, H>()];
+    __shared__ __align__(16) T B1[padded<TX, H>()];
     T *const B2 = A1;
-    static_assert(padded<TX, H>() <= padded<W, H>(), "x pass of d2 must fit the d1 tile");
-    __shared__ double red[(NT / 64) * NQD];
+    double *const red = reinterpret_cast<double *>(A2);
+    static_assert(padded<TX, H>() <= padded<WS, H>(), "x pass of d2 must fit the d1 tile");
+    static_assert((NT / 64) * NQD * sizeof(double) <= padded<WS, H>() * sizeof(T), "reduction must fit");
 
     const Item it = items[blockIdx.z];
     const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
@@ -497,13 +567,15 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     }
 #pragma unroll
     for (int qq = 0; qq < rg.E; ++qq) {
-        A1[threadIdx.x + qq * NT] = rg.inb[qq] ? v1[qq] : T(0);
-        A2[threadIdx.x + qq * NT] = rg.inb[qq] ? v2[qq] : T(0);
+        const int e = threadIdx.x + qq * NT;
+        if (rg.N % NT != 0 && e >= rg.N) break;
+        A1[lds_at<W, WS>(e)] = rg.inb[qq] ? v1[qq] : T(0);
+        A2[lds_at<W, WS>(e)] = rg.inb[qq] ? v2[qq] : T(0);
     }
     __syncthreads();
-    xpass<T, R, W, TX, H, R, false>(A1, B1, wx);
+    xpass4<T, R, H, false>(A1, B1, wx);
     __syncthreads();
-    xpass<T, R, W, TX, H, R, false>(A2, B2, wx);
+    xpass4<T, R, H, false>(A2, B2, wx);
     __syncthreads();
     T h1[NRK], h2[NRK];
     ypass_out<T, R, TX, R, false, NRK>(B1, h1, wy);
@@ -514,7 +586,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
         T *o1 = s.hd[0] + (size_t)blockIdx.z * S, *o2 = s.hd[1] + (size_t)blockIdx.z * S;
 #pragma unroll
         for (int e = 0; e < NRK; ++e) {
-            const int j = y0 + out_row(e), i = x0 + tx;
+            const int j = y0 + out_row<NRK>(e), i = x0 + tx;
             if (i >= g.nx || j >= g.ny) continue;
             const size_t o = (size_t)j * g.nx + i;
             o1[o] = h1[e];
@@ -529,7 +601,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
-        const int j = y0 + out_row(e), i = x0 + tx;
+        const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
         const double a = (double)h1[e], b = (double)h2[e];
         qs[0] += a * a;
@@ -578,9 +650,9 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     constexpr int NRK = TYK / (NT / TX);
     if (s.stop && *s.stop) return;
     constexpr int K = 2 * R + 1;
-    constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R;
-    __shared__ T A[padded<W2, H2>()];
-    __shared__ T B[padded<TX, H2>()];
+    constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R, WS2 = vstride<T, W2>();
+    __shared__ __align__(16) T A[padded<WS2, H2>()];
+    __shared__ __align__(16) T B[padded<TX, H2>()];
 
     const Item it = items[blockIdx.z];
     const int m = it.k;
@@ -591,14 +663,15 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     load_taps<T, R>(wx, s.gx + (size_t)m * K);
     load_taps<T, R>(wy, s.gy + (size_t)m * K);
     // the outputs' q, and on the block x, dp and g, are loaded first so that
-    // their latency overlaps the loads of H d'
+    // their latency overlaps the loads of H d' (no pass of this launch writes
+    // H d1 or H d2)
     const bool ins = (m >= it.z0 && m < it.z0 + it.n);
     const T *qs = s.q + (size_t)m * S, *xs = s.x + (size_t)m * S;
     const T *ds = s.dp[0] + (size_t)m * S, *gs = s.g + (size_t)m * S;
     T qv[NRK], xv[NRK], dv[NRK], gv[NRK];
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
-        const int j = y0 + out_row(e), i = x0 + tx;
+        const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         const uint32_t o = (i < g.nx && j < g.ny) ? (uint32_t)(j * g.nx + i) : 0u;
         qv[e] = ldo(qs, o);
         xv[e] = dv[e] = gv[e] = 0;
@@ -621,25 +694,36 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
             for (int qq = 0; qq < rg.E; ++qq) v[qq] += c1 * ldo(h1, rg.off[qq]) + c2 * ldo(h2, rg.off[qq]);
         }
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            if (rg.N % NT != 0 && e >= rg.N) break;
+            A[lds_at<W2, WS2>(e)] = rg.inb[qq] ? v[qq] : T(0);
+        }
     }
-    __syncthreads();
-    xpass<T, R, W2, TX, H2, R, true>(A, B, wx);
-    __syncthreads();
-    T v[NRK];
-    ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
-    const T u1 = ins ? (T)u[2 * it.block] : T(0), u2 = ins ? (T)u[2 * it.block + 1] : T(0);
+    // x and dp of this slice are read by no other workgroup: written now,
+    // which frees their registers for the blur passes
+    if (ins) {
+        const T u1 = (T)u[2 * it.block], u2 = (T)u[2 * it.block + 1];
 #pragma unroll
-    for (int e = 0; e < NRK; ++e) {
-        const int j = y0 + out_row(e), i = x0 + tx;
-        if (i >= g.nx || j >= g.ny) continue;
-        const size_t o = vidx(g, m, j, i);
-        s.q[o] = qv[e] + v[e];
-        if (ins) {
+        for (int e = 0; e < NRK; ++e) {
+            const int j = y0 + out_row<NRK>(e), i = x0 + tx;
+            if (i >= g.nx || j >= g.ny) continue;
+            const size_t o = vidx(g, m, j, i);
             const T d = u2 * dv[e] - u1 * gv[e];
             s.x[o] = xv[e] + d;
             s.dp[1][o] = d;
         }
+    }
+    __syncthreads();
+    xpass4<T, R, H2, true>(A, B, wx);
+    __syncthreads();
+    T v[NRK];
+    ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
+#pragma unroll
+    for (int e = 0; e < NRK; ++e) {
+        const int j = y0 + out_row<NRK>(e), i = x0 + tx;
+        if (i >= g.nx || j >= g.ny) continue;
+        s.q[vidx(g, m, j, i)] = qv[e] + v[e];
     }
 }
 
@@ -660,8 +744,10 @@ k_refresh(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W1 = TX + 4 * R, H1 = TYK + 4 * R;  // z-combined source, 2R halo
     constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R;  // H src - y, R halo
-    __shared__ T A[padded<W1, H1>()];                // z-combined source, later H src - y
-    __shared__ T B[padded<W2, H1>()];                // forward x pass, later adjoint x pass
+    constexpr int WS2 = vstride<T, W2>();
+    static_assert(padded<W1, H1>() >= WS2 * H2, "H src - y must fit the source tile");
+    __shared__ __align__(16) T A[padded<W1, H1>()];  // z-combined source, later H src - y
+    __shared__ __align__(16) T B[padded<W2, H1>()];  // forward x pass, later adjoint x pass
 
     const Item it = items[blockIdx.z];
     const int m = it.k;
@@ -707,25 +793,25 @@ k_refresh(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout
 #pragma unroll
     for (int qq = 0; qq < r2.E; ++qq) {
         const int e = threadIdx.x + qq * NT;
-        int r = e / W2;
+        if (r2.N % NT != 0 && e >= r2.N) break;
+        const int r = e / W2;
         const int c = e - r * W2;
-        if (qq == r2.E - 1) r = r < H2 ? r : H2 - 1;
         const T *col = B + (r + R) * W2 + c;
         T acc = 0;
 #pragma unroll
         for (int b = -R; b <= R; ++b) acc += wy[b + R] * col[-b * W2];
-        A[e] = r2.inb[qq] ? acc - yv[qq] : T(0);
+        A[r * WS2 + c] = r2.inb[qq] ? acc - yv[qq] : T(0);
     }
     __syncthreads();
     // 4. adjoint x pass over the R-halo rows into B
-    xpass<T, R, W2, TX, H2, R, true>(A, B, wx);
+    xpass4<T, R, H2, true>(A, B, wx);
     __syncthreads();
     // 5. adjoint y pass into registers
     T v[NRK];
     ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
-        const int j = y0 + out_row(e), i = x0 + tx;
+        const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
         qout[vidx(g, m, j, i)] = v[e];
     }
@@ -742,9 +828,9 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
     constexpr int NRK = TYK / (NT / TX);
     if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
-    constexpr int W = TX + 2 * R, H = TYK + 2 * R;
-    __shared__ T A[padded<W, H>()];
-    __shared__ T B[padded<TX, H>()];
+    constexpr int W = TX + 2 * R, H = TYK + 2 * R, WS = vstride<T, W>();
+    __shared__ __align__(16) T A[padded<WS, H>()];
+    __shared__ __align__(16) T B[padded<TX, H>()];
     __shared__ double red[NT / 64];
     const Item it = items[blockIdx.z];
     const int k = it.k;
@@ -770,17 +856,21 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
             for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ldo(ss, rg.off[qq]);
         }
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            if (rg.N % NT != 0 && e >= rg.N) break;
+            A[lds_at<W, WS>(e)] = rg.inb[qq] ? v[qq] : T(0);
+        }
     }
     __syncthreads();
-    xpass<T, R, W, TX, H, R, false>(A, B, wx);
+    xpass4<T, R, H, false>(A, B, wx);
     __syncthreads();
     T h[NRK];
     ypass_out<T, R, TX, R, false, NRK>(B, h, wy);
     double ss[1] = {0.0};
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
-        const int j = y0 + out_row(e), i = x0 + tx;
+        const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         if (i < g.nx && j < g.ny) {
             const size_t o = vidx(g, k, j, i);
             const T v = sub ? h[e] - sub[o] : h[e];
@@ -801,9 +891,9 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
 {
     constexpr int NRK = TYK / (NT / TX);
     constexpr int K = 2 * R + 1;
-    constexpr int W = TX + 2 * R, H = TYK + 2 * R;
-    __shared__ T A[padded<W, H>()];
-    __shared__ T B[padded<TX, H>()];
+    constexpr int W = TX + 2 * R, H = TYK + 2 * R, WS = vstride<T, W>();
+    __shared__ __align__(16) T A[padded<WS, H>()];
+    __shared__ __align__(16) T B[padded<TX, H>()];
     const Item it = items[blockIdx.z];
     const int m = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
@@ -818,16 +908,20 @@ k_blurT(Geom g, DevState<T> s, const T *__restrict__ in, T *__restrict__ out,
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) v[qq] = ldo(im, rg.off[qq]);
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) A[threadIdx.x + qq * NT] = rg.inb[qq] ? v[qq] : T(0);
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            if (rg.N % NT != 0 && e >= rg.N) break;
+            A[lds_at<W, WS>(e)] = rg.inb[qq] ? v[qq] : T(0);
+        }
     }
     __syncthreads();
-    xpass<T, R, W, TX, H, R, true>(A, B, wx);
+    xpass4<T, R, H, true>(A, B, wx);
     __syncthreads();
     T v[NRK];
     ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
-        const int j = y0 + out_row(e), i = x0 + tx;
+        const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         if (i < g.nx && j < g.ny) out[vidx(g, m, j, i)] = v[e];
     }
 }
