@@ -56,22 +56,33 @@ def make_problem(binding, w):
     return g
 
 
-def measured_traffic(workload, kernel, tile_rows):
-    """HBM bytes per launch of the dominant kernel from the committed PMC record
-    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when the kernel sources or the tile variant differ from those measured."""
-    path = os.path.join(ROOT, "profiles", "traffic_update.json")
+def kernel_variant(w, kernel, tile_rows):
+    """Name of the sweep kernel instance a pass runs, as the profiler prints it."""
+    t = "double" if w.fp64 else "float"
+    kz, r = w.kz, max(w.kxy // 2, 1)
+    return {"grad": "k_grad<%s, %d>" % (t, kz),
+            "dirs": "k_dirs<%s, %d, %d, %d>" % (t, kz, r, tile_rows["dirs"]),
+            "solve": "k_solve",
+            "update": "k_update<%s, %d, %d>" % (t, r, tile_rows["update"])}[kernel]
+
+
+def measured_traffic(workload, variant):
+    """HBM bytes per launch of a sweep kernel instance from the committed PMC
+    record (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration),
+    or None when the kernel sources differ from those measured or the instance
+    was not measured."""
+    path = os.path.join(ROOT, "profiles", "traffic_sweep.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(workload)
-    if not rec or rec["kernel"] != kernel or rec["tile_rows_update"] != tile_rows:
+    if not rec:
         return None
     h = hashlib.sha256()
     for f in ("bd3mg_kernels.hip", "bd3mg_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2002_02328_amd", "csrc", f), "rb").read())
     if h.hexdigest() != rec["kernel_source_sha256"]:
         return None
-    return rec["bytes_per_launch"]
+    return rec["bytes_per_launch"].get(variant)
 
 
 def cpu_baseline(w, budget_s):
@@ -193,6 +204,7 @@ def main():
     g.set_option(binding.OPT_PROFILE, 0)
     hot = {k: v for k, v in prof.items() if k != "eval" and v[0] > 0}
     dom = max(hot, key=lambda k: hot[k][1])
+    variant = kernel_variant(w, dom, {"dirs": td, "update": tu})
     n, ms, by = hot[dom]
     achieved = by / (ms * 1e-3) / 1e9
     kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
@@ -220,9 +232,9 @@ def main():
                    "blocks": int(len(w.nslices)), "colors": int(nc),
                    "reductions": "f64", "step": "one sweep (every block updated once)",
                    "tile_rows": {"dirs": td, "update": tu}},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(w.name, dom, tu),
+        "roofline": {"bound": "hbm", "kernel": dom, "variant": variant, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(w.name, variant),
                      "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n},
         "kernels": kernels,
         "sweep_algorithmic_GBps": all_bytes / (total_ms * 1e-3) / 1e9,
