@@ -874,7 +874,7 @@ bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int ch
     ST_TRY(ensure_ready(p));
     const double vol = (double)p->N * p->esz;
     // The stop test runs on the device: a check that meets the tolerance
-    // raises a flag and every later pass returns at entry, so the host only
+    // raises a flag and every later pass returns without writing, so the host only
     // waits once per chunk of sweeps.
     constexpr int CHUNK = 16;
     const bool stopping = grad_rtol > 0.0;

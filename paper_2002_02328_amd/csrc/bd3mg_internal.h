@@ -99,7 +99,7 @@ inline int tiles_of(const Geom &g, int ty) { return g.ntx * ((g.ny + ty - 1) / t
 template <typename T>
 struct DevState {
     T *x, *y, *q, *g, *dp[2];  // dp[0]: previous steps read, dp[1]: written
-    const int *stop;           // when non-null and set, every pass returns at entry
+    const int *stop;           // when non-null and set, every pass returns without writing
     const T *gx, *gy;          // in-slice PSF tables [nz][2R + 1], centred, zero-padded
     const T *gz;               // z PSF table [nz][kz]
     const int *sblk;           // block of every slice

@@ -245,7 +245,6 @@ __global__ void __launch_bounds__(NT)
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials)
 {
-    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2;
     constexpr int XW = TX + 3, XH = TY + 3;  // x at (y0-1+jj, x0-1+ii)
     constexpr int PW = TX + 2, PH = TY + 2;  // w VX x, w VY x, w at (y0-1+jj, x0-1+ii)
@@ -259,6 +258,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
     __shared__ double red[(NT / 64) * NQG];
 
     const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
     const int k = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const size_t S = (size_t)g.nx * g.ny;
@@ -428,28 +428,41 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
 // threads of the workgroup take part.
 __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange &br, int ntg, int ntd,
                                             const double *__restrict__ pg, const double *__restrict__ pd,
-                                            double *__restrict__ u, double *__restrict__ info)
+                                            double *__restrict__ u, double *__restrict__ info,
+                                            const int *__restrict__ stop)
 {
     constexpr int NV = NQG + NQD;
     __shared__ double red[NT / 64][NV];
     __shared__ double tot[NV];
-    // each thread sums its slots in order, then one tree over the threads
+    // each thread sums its slots in order, then one tree over the threads;
+    // the slots are read CH per thread at a time, gradient and direction
+    // slots together, so their loads are in flight at once
+    constexpr int CH = 2;
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     {
-        const double *p = pg + (size_t)br.g0 * ntg * NQG;
-        const int n = br.gn * ntg;
-        for (int t = threadIdx.x; t < n; t += NT)
+        const double *p1 = pg + (size_t)br.g0 * ntg * NQG;
+        const double *p2 = pd + (size_t)br.d0 * ntd * NQD;
+        const int n1 = br.gn * ntg, n2 = br.dn * ntd;
+        for (int t0 = threadIdx.x; t0 < n1 || t0 < n2; t0 += CH * NT) {
+            double a[CH][NQG], b[CH][NQD];
 #pragma unroll
-            for (int v = 0; v < NQG; ++v) acc[v] += p[(size_t)t * NQG + v];
-    }
-    {
-        const double *p = pd + (size_t)br.d0 * ntd * NQD;
-        const int n = br.dn * ntd;
-        for (int t = threadIdx.x; t < n; t += NT)
+            for (int c = 0; c < CH; ++c) {
+                const int t = t0 + c * NT;
 #pragma unroll
-            for (int v = 0; v < NQD; ++v) acc[NQG + v] += p[(size_t)t * NQD + v];
+                for (int v = 0; v < NQG; ++v) a[c][v] = t < n1 ? p1[(size_t)t * NQG + v] : 0.0;
+#pragma unroll
+                for (int v = 0; v < NQD; ++v) b[c][v] = t < n2 ? p2[(size_t)t * NQD + v] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+#pragma unroll
+                for (int v = 0; v < NQG; ++v) acc[v] += a[c][v];
+#pragma unroll
+                for (int v = 0; v < NQD; ++v) acc[NQG + v] += b[c][v];
+            }
+        }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -466,7 +479,9 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
         tot[threadIdx.x] = sv;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    // once the run has stopped nothing is written (the flag is read here,
+    // not at entry, so that its load overlaps those of the slots)
+    if (threadIdx.x == 0 && !(stop && *stop)) {
         // gradient pass: <g,g>, <g,dp>, <dp,dp>, then the TV curvature sums;
         // direction pass: <Hd_a,Hd_b>, then <VZ d_a, VZ d_b>
         const double gg = tot[0], gd = tot[1], dd = tot[2];
@@ -506,8 +521,7 @@ k_solve(Params prm, const BlockRange *__restrict__ brs, int ntg, int ntd, const 
         const double *__restrict__ pd, double *__restrict__ u, double *__restrict__ info,
         const int *__restrict__ stop)
 {
-    if (stop && *stop) return;
-    solve_block(prm, brs[blockIdx.x], ntg, ntd, pg, pd, u, info);
+    solve_block(prm, brs[blockIdx.x], ntg, ntd, pg, pd, u, info, stop);
 }
 
 // ---------------------------------------------------------------------------
@@ -521,7 +535,6 @@ __global__ void __launch_bounds__(NT)
 k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double *__restrict__ partials)
 {
     constexpr int NRK = TYK / (NT / TX);
-    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W = TX + 2 * R, H = TYK + 2 * R;
     // the x pass of d2 is written over the z-combine of d1, and the
@@ -537,6 +550,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     static_assert((NT / 64) * NQD * sizeof(double) <= padded<WS, H>() * sizeof(T), "reduction must fit");
 
     const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
     const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
@@ -648,13 +662,13 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
          const double *__restrict__ u)
 {
     constexpr int NRK = TYK / (NT / TX);
-    if (s.stop && *s.stop) return;
     constexpr int K = 2 * R + 1;
     constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R, WS2 = vstride<T, W2>();
     __shared__ __align__(16) T A[padded<WS2, H2>()];
     __shared__ __align__(16) T B[padded<TX, H2>()];
 
     const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
     const int m = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
@@ -740,7 +754,6 @@ k_refresh(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout
           const Item *__restrict__ items)
 {
     constexpr int NRK = TYK / (NT / TX);
-    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W1 = TX + 4 * R, H1 = TYK + 4 * R;  // z-combined source, 2R halo
     constexpr int W2 = TX + 2 * R, H2 = TYK + 2 * R;  // H src - y, R halo
@@ -750,6 +763,7 @@ k_refresh(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout
     __shared__ __align__(16) T B[padded<W2, H1>()];  // forward x pass, later adjoint x pass
 
     const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
     const int m = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
@@ -826,13 +840,13 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
     const Item *__restrict__ items, double *__restrict__ partials)
 {
     constexpr int NRK = TYK / (NT / TX);
-    if (s.stop && *s.stop) return;
     constexpr int RZ = KZ / 2, K = 2 * R + 1;
     constexpr int W = TX + 2 * R, H = TYK + 2 * R, WS = vstride<T, W>();
     __shared__ __align__(16) T A[padded<WS, H>()];
     __shared__ __align__(16) T B[padded<TX, H>()];
     __shared__ double red[NT / 64];
     const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
     const int k = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
@@ -946,7 +960,8 @@ k_sum(const double *__restrict__ partials, int nslot, int nq, double *__restrict
 
 // Stop test on the device: ||grad f|| from the evaluation slots (fixed-order
 // sum), recorded in *gnorm; when it is at most thr, *stop is raised and the
-// sweep number recorded, and every later pass of the run returns at entry.
+// sweep number recorded, and every later pass of the run returns without
+// writing.
 __global__ void __launch_bounds__(NT)
 k_check(const double *__restrict__ partials, int nslot, double thr, int sweep, int *stop,
         int *stop_sweep, double *gnorm)
