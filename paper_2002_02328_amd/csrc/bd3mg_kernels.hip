@@ -781,9 +781,8 @@ k_refresh(Geom g, DevState<T> s, const T *__restrict__ src, T *__restrict__ qout
         for (int qq = 0; qq < rg.E; ++qq) v[qq] = 0;
 #pragma unroll
         for (int c = -RZ; c <= RZ; ++c) {
-            const int sl = m - c;
-            if (sl < 0 || sl >= g.nz) continue;
-            const T wv = wz[c + RZ];
+            const int sl = min(max(m - c, 0), g.nz - 1);  // weight 0 past the volume
+            const T wv = (m - c == sl) ? wz[c + RZ] : T(0);
             const T *ss = src + (size_t)sl * S;
 #pragma unroll
             for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ldo(ss, rg.off[qq]);
@@ -862,9 +861,8 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
         for (int qq = 0; qq < rg.E; ++qq) v[qq] = 0;
 #pragma unroll
         for (int c = -RZ; c <= RZ; ++c) {
-            const int sl = k - c;
-            if (sl < 0 || sl >= g.nz) continue;
-            const T wv = wz[c + RZ];
+            const int sl = min(max(k - c, 0), g.nz - 1);  // weight 0 past the volume
+            const T wv = (k - c == sl) ? wz[c + RZ] : T(0);
             const T *ss = in + (size_t)sl * S;
 #pragma unroll
             for (int qq = 0; qq < rg.E; ++qq) v[qq] += wv * ldo(ss, rg.off[qq]);
