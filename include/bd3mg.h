@@ -224,7 +224,12 @@ typedef enum {
      * of the partial sums (rounding only). */
     BD3MG_OPT_TILE_ROWS_DIRS = 2,
     BD3MG_OPT_TILE_ROWS_UPDATE = 3,
-    BD3MG_OPT_TILE_ROWS_AUX = 4
+    BD3MG_OPT_TILE_ROWS_AUX = 4,
+    /* Output slices per workgroup of the direction pass: 1, 2 (consecutive
+     * slices of a block share the reads of their common source slices), or 0
+     * (the default: 2 for a launch group with at least 2^23 direction output
+     * voxels, else 1).  Results are bitwise the same for every setting. */
+    BD3MG_OPT_DIRS_SLICES = 5
 } bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
 

@@ -66,6 +66,7 @@ struct bd3mg_problem_s {
     int ncolors = 0;
     struct Group {
         int g_off, g_cnt, d_off, d_cnt, u_off, u_cnt, br_off, br_cnt;
+        int du_off, du_cnt;  // direction units: one or two consecutive slices of a block
         double bytes[4];  // algorithmic bytes of the gradient, direction, solve and update passes
         bool round;       // update pass over every slice with per-slice block coefficients
     };
@@ -78,6 +79,9 @@ struct bd3mg_problem_s {
     int *d_sblk = nullptr;  // block of every slice
     int2 *d_pairs = nullptr;  // (direction slot, block) sources of the update items
     size_t pairs_alloc = 0;
+    int2 *d_units = nullptr;  // (first direction item, slice count) of the direction workgroups
+    size_t units_alloc = 0;
+    int dirs_slices = 0;      // slices per direction workgroup (0: by group size)
     void *d_hd = nullptr;     // H d1 then H d2 of a launch group's direction items
     size_t hd_alloc = 0, hd_slots = 0;
 
@@ -280,7 +284,8 @@ void color_blocks(bd3mg_problem p)
 // H d2 on the item's slice make up H d' there.
 void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<Item> &gi,
                  std::vector<Item> &di, std::vector<Item> &ui, std::vector<int2> &pairs,
-                 std::vector<BlockRange> &br, bd3mg_problem_s::Group &grp, bool round = false)
+                 std::vector<int2> &units, std::vector<BlockRange> &br, bd3mg_problem_s::Group &grp,
+                 bool round = false)
 {
     const int rz = p->kz / 2;
     const int rd = std::max(rz, p->prm.kappa > 0.0 ? 1 : 0);
@@ -288,8 +293,9 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     grp.d_off = (int)di.size();
     grp.u_off = (int)ui.size();
     grp.br_off = (int)br.size();
+    grp.du_off = (int)units.size();
     std::vector<char> halo(p->nz, 0);
-    std::vector<int> dfirst, dlo;  // per block of the group: first direction slot, its slice
+    std::vector<int> dfirst, dlo, dend;  // per block of the group: direction slots, first slice
     double sl = 0.0, np = 0.0;
     for (int b : blocks) {
         const int z0 = p->z0[b], n = p->nsl[b];
@@ -299,6 +305,7 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
         dfirst.push_back(r.d0);
         dlo.push_back(lo);
         for (int k = lo; k < std::min(p->nz, z0 + n + rz); ++k) di.push_back(Item{k, b, z0, n, 0, 0});
+        dend.push_back((int)di.size() - grp.d_off);
         if (!round)
             for (int k = std::max(0, z0 - rz); k < std::min(p->nz, z0 + n + rz); ++k) {
                 ui.push_back(Item{k, b, z0, n, (int)pairs.size(), 1});
@@ -327,7 +334,17 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
         }
     }
     for (int t = grp.u_off; t < (int)ui.size(); ++t) np += ui[t].hn;
+    // A direction workgroup takes two consecutive slices of a block (sharing
+    // the reads of their common source slices) when the group has enough
+    // direction outputs to keep every compute unit busy with half as many
+    // workgroups (at least 2^23 voxels), else one.
+    const int ndir = (int)di.size() - grp.d_off;
+    const int per = p->dirs_slices > 0 ? p->dirs_slices
+                                       : ((double)ndir * p->nx * p->ny >= (double)(1 << 23) ? 2 : 1);
+    for (size_t t = 0; t < dfirst.size(); ++t)
+        for (int i = dfirst[t]; i < dend[t]; i += per) units.push_back(int2{i, std::min(per, dend[t] - i)});
     grp.round = round;
+    grp.du_cnt = (int)units.size() - grp.du_off;
     grp.g_cnt = (int)gi.size() - grp.g_off;
     grp.d_cnt = (int)di.size() - grp.d_off;
     grp.u_cnt = (int)ui.size() - grp.u_off;
@@ -354,16 +371,16 @@ bd3mg_status build_schedule(bd3mg_problem p)
     color_blocks(p);
     const int nb = (int)p->nsl.size();
     std::vector<Item> gi, di, ui;
-    std::vector<int2> pairs;
+    std::vector<int2> pairs, units;
     std::vector<BlockRange> br;
     p->groups.assign(p->ncolors + nb, bd3mg_problem_s::Group{});
     for (int c = 0; c < p->ncolors; ++c) {
         std::vector<int> blocks;
         for (int b : p->order)
             if (p->color[b] == c) blocks.push_back(b);
-        group_items(p, blocks, gi, di, ui, pairs, br, p->groups[c], p->schedule == BD3MG_SCHED_ROUND);
+        group_items(p, blocks, gi, di, ui, pairs, units, br, p->groups[c], p->schedule == BD3MG_SCHED_ROUND);
     }
-    for (int b = 0; b < nb; ++b) group_items(p, {b}, gi, di, ui, pairs, br, p->groups[p->ncolors + b]);
+    for (int b = 0; b < nb; ++b) group_items(p, {b}, gi, di, ui, pairs, units, br, p->groups[p->ncolors + b]);
     // one device array: gradient items, then direction items, then update items
     const int ng = (int)gi.size(), nd = (int)di.size();
     for (auto &grp : p->groups) {
@@ -381,6 +398,9 @@ bd3mg_status build_schedule(bd3mg_problem p)
                            p->stream));
     ST_TRY(realloc_dev((void **)&p->d_pairs, &p->pairs_alloc, pairs.size() * sizeof(int2), "update sources"));
     HIP_TRY(hipMemcpyAsync(p->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice,
+                           p->stream));
+    ST_TRY(realloc_dev((void **)&p->d_units, &p->units_alloc, units.size() * sizeof(int2), "direction units"));
+    HIP_TRY(hipMemcpyAsync(p->d_units, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice,
                            p->stream));
     {
         std::vector<int> sblk(p->nz);
@@ -524,7 +544,8 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
                            p->d_pg, p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
-    HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, it + gr.d_off, gr.d_cnt, p->d_pd, p->stream));
+    HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, it + gr.d_off, p->d_units + gr.du_off, gr.du_cnt, p->d_pd,
+                           p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
     HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,
@@ -668,7 +689,8 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2],
                     p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_sblk, p->d_pg, p->d_pd,
-                    p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_pairs, p->d_hd};
+                    p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_pairs, p->d_hd,
+                    p->d_units};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (auto &q : p->pending) {
@@ -1008,6 +1030,11 @@ bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value)
         *t = (int)value;
         return BD3MG_OK;
     }
+    case BD3MG_OPT_DIRS_SLICES:
+        if (value < 0 || value > 2) return fail(BD3MG_ERR_ARG, "direction slices must be 0, 1 or 2");
+        p->dirs_slices = (int)value;
+        p->sched_dirty = true;
+        return BD3MG_OK;
     default:
         return fail(BD3MG_ERR_ARG, "unknown option %d", option);
     }

@@ -118,10 +118,11 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
                        const T *x, T *out, const Item *items, int nitems, int mode,
                        double *partials, hipStream_t st);
 
-// Direction pass; also stores H d1, H d2 of item i at slot i of s.hd.
+// Direction pass over nunits units (first item, 1 or 2 consecutive slices of
+// a block); stores H d1, H d2 of item i at slot i of s.hd.
 template <typename T>
 hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
-                       int nitems, double *partials, hipStream_t st);
+                       const int2 *units, int nunits, double *partials, hipStream_t st);
 
 // Update pass from the stored H d1, H d2 (pairs: (slot, block) per source).
 template <typename T>

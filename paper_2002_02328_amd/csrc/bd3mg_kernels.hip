@@ -525,66 +525,41 @@ k_solve(Params prm, const BlockRange *__restrict__ brs, int ntg, int ntd, const 
 }
 
 // ---------------------------------------------------------------------------
-// Direction pass, one output slice k per item, for the block S = [z0, z0+n):
-// with d1 = -g and d2 = dp (zero outside S),
+// Direction pass for the block S = [z0, z0+n): with d1 = -g and d2 = dp (zero
+// outside S), on output slice k
 //   (H d)_k = XY_k( sum_c gz_k[c] d_{k-c} ),
-// the sums <Hd_a, Hd_b> and <VZ d_a, VZ d_b> (a, b in {1, 2}).
+// stored for the update pass, and the sums <Hd_a, Hd_b> and
+// <VZ d_a, VZ d_b> (a, b in {1, 2}) of the slice, per tile.
+// A workgroup takes one or two consecutive output slices k, k+1 of a block
+// (a unit): their z-combines share KZ - 1 source slices, which are read once.
 // ---------------------------------------------------------------------------
-template <typename T, int KZ, int R, int TYK>
-__global__ void __launch_bounds__(NT)
-k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double *__restrict__ partials)
+
+// LDS passes, stores and sums of one output slice kk (direction item i) from
+// its z-combined d1, d2 on the tile plus an R halo.
+template <typename T, int R, int TYK, int E>
+__device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, const DevState<T> &s,
+                                            const Item &it, int kk, size_t i, const T (&v1)[E],
+                                            const T (&v2)[E], const uint32_t (&off)[E], const bool (&inb)[E],
+                                            T *A1, T *A2, T *B1, double *partials)
 {
     constexpr int NRK = TYK / (NT / TX);
-    constexpr int RZ = KZ / 2, K = 2 * R + 1;
-    constexpr int W = TX + 2 * R, H = TYK + 2 * R;
-    // the x pass of d2 is written over the z-combine of d1, and the
-    // reduction of the inner products over the z-combine of d2 (three tiles,
-    // not four: more workgroups fit a compute unit's LDS)
+    constexpr int K = 2 * R + 1, W = TX + 2 * R, H = TYK + 2 * R, N = W * H;
     constexpr int WS = vstride<T, W>();
-    __shared__ __align__(16) T A1[padded<WS, H>()];
-    __shared__ __align__(16) T A2[padded<WS, H>()];
-    __shared__ __align__(16) T B1[padded<TX, H>()];
     T *const B2 = A1;
     double *const red = reinterpret_cast<double *>(A2);
-    static_assert(padded<TX, H>() <= padded<WS, H>(), "x pass of d2 must fit the d1 tile");
-    static_assert((NT / 64) * NQD * sizeof(double) <= padded<WS, H>() * sizeof(T), "reduction must fit");
-
-    const Item it = items[blockIdx.z];
-    if (s.stop && *s.stop) return;  // read with the item, not before it
-    const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
+    const int z0 = it.z0, z1 = it.z0 + it.n;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
-    const T *__restrict__ gg = s.g;
-    const T *__restrict__ dpv = s.dp[0];
-    const T *wz = s.gz + (size_t)k * KZ;
     T wx[K], wy[K];
-    load_taps<T, R>(wx, s.gx + (size_t)k * K);
-    load_taps<T, R>(wy, s.gy + (size_t)k * K);
-
-    // z-combine of d1 and d2 on the tile plus an R halo
-    Region<W, H, R, R> rg(g, x0, y0);
-    T v1[rg.E], v2[rg.E];
+    load_taps<T, R>(wx, s.gx + (size_t)kk * K);
+    load_taps<T, R>(wy, s.gy + (size_t)kk * K);
 #pragma unroll
-    for (int qq = 0; qq < rg.E; ++qq) v1[qq] = v2[qq] = 0;
-#pragma unroll
-    for (int c = -RZ; c <= RZ; ++c) {
-        const int sl = k - c;
-        if (sl < z0 || sl >= z1) continue;
-        const T wv = wz[c + RZ];
-        const T *gs = gg + (size_t)sl * S, *ds = dpv + (size_t)sl * S;
-#pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) {
-            v1[qq] -= wv * ldo(gs, rg.off[qq]);
-            v2[qq] += wv * ldo(ds, rg.off[qq]);
-        }
-    }
-#pragma unroll
-    for (int qq = 0; qq < rg.E; ++qq) {
+    for (int qq = 0; qq < E; ++qq) {
         const int e = threadIdx.x + qq * NT;
-        if (rg.N % NT != 0 && e >= rg.N) break;
-        A1[lds_at<W, WS>(e)] = rg.inb[qq] ? v1[qq] : T(0);
-        A2[lds_at<W, WS>(e)] = rg.inb[qq] ? v2[qq] : T(0);
+        if (N % NT != 0 && e >= N) break;
+        A1[lds_at<W, WS>(e)] = inb[qq] ? v1[qq] : T(0);
+        A2[lds_at<W, WS>(e)] = inb[qq] ? v2[qq] : T(0);
     }
     __syncthreads();
     xpass4<T, R, H, false>(A1, B1, wx);
@@ -597,35 +572,36 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
     {
         // stored for the update pass, which combines them with the step
         // coefficients instead of blurring the new step again
-        T *o1 = s.hd[0] + (size_t)blockIdx.z * S, *o2 = s.hd[1] + (size_t)blockIdx.z * S;
+        T *o1 = s.hd[0] + i * S, *o2 = s.hd[1] + i * S;
 #pragma unroll
         for (int e = 0; e < NRK; ++e) {
-            const int j = y0 + out_row<NRK>(e), i = x0 + tx;
-            if (i >= g.nx || j >= g.ny) continue;
-            const size_t o = (size_t)j * g.nx + i;
+            const int j = y0 + out_row<NRK>(e), ii = x0 + tx;
+            if (ii >= g.nx || j >= g.ny) continue;
+            const size_t o = (size_t)j * g.nx + ii;
             o1[o] = h1[e];
             o2[o] = h2[e];
         }
     }
-
     double qs[NQD];
 #pragma unroll
     for (int v = 0; v < NQD; ++v) qs[v] = 0.0;
-    const bool ink = (k >= z0 && k < z1);
-    const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
+    const bool ink = (kk >= z0 && kk < z1);
+    const bool zterm = (prm.kappa != 0.0) && kk >= z0 - 1 && kk < z1 && kk < g.nz - 1;
+    const T *__restrict__ gg = s.g;
+    const T *__restrict__ dpv = s.dp[0];
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
-        const int j = y0 + out_row<NRK>(e), i = x0 + tx;
-        if (i >= g.nx || j >= g.ny) continue;
+        const int j = y0 + out_row<NRK>(e), ii = x0 + tx;
+        if (ii >= g.nx || j >= g.ny) continue;
         const double a = (double)h1[e], b = (double)h2[e];
         qs[0] += a * a;
         qs[1] += a * b;
         qs[2] += b * b;
         if (zterm) {
-            // VZ d at slice k: d_{k+1} - d_k with d zero outside S
-            const size_t o = vidx(g, k, j, i);
+            // VZ d at slice kk: d_{kk+1} - d_kk with d zero outside S
+            const size_t o = vidx(g, kk, j, ii);
             double z1v = 0.0, z2v = 0.0;
-            if (k + 1 >= z0 && k + 1 < z1) {
+            if (kk + 1 >= z0 && kk + 1 < z1) {
                 z1v -= (double)gg[o + S];
                 z2v += (double)dpv[o + S];
             }
@@ -638,7 +614,72 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, double
             qs[5] += z2v * z2v;
         }
     }
-    wg_reduce_store<NQD>(qs, red, partials + slot_of() * NQD);
+    wg_reduce_store<NQD>(qs, red, partials + ((i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * NQD);
+}
+
+template <typename T, int KZ, int R, int TYK>
+__global__ void __launch_bounds__(NT)
+k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ units,
+       double *__restrict__ partials)
+{
+    constexpr int RZ = KZ / 2;
+    constexpr int W = TX + 2 * R, H = TYK + 2 * R;
+    // the x pass of d2 is written over the z-combine of d1, and the
+    // reduction of the inner products over the z-combine of d2 (three tiles,
+    // not four: more workgroups fit a compute unit's LDS)
+    constexpr int WS = vstride<T, W>();
+    __shared__ __align__(16) T A1[padded<WS, H>()];
+    __shared__ __align__(16) T A2[padded<WS, H>()];
+    __shared__ __align__(16) T B1[padded<TX, H>()];
+    static_assert(padded<TX, H>() <= padded<WS, H>(), "x pass of d2 must fit the d1 tile");
+    static_assert((NT / 64) * NQD * sizeof(double) <= padded<WS, H>() * sizeof(T), "reduction must fit");
+
+    const int2 un = units[blockIdx.z];  // first direction item, 1 or 2 slices
+    const Item it = items[un.x];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
+    const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
+    const bool two = un.y > 1;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
+    const size_t S = (size_t)g.nx * g.ny;
+    const T *__restrict__ gg = s.g;
+    const T *__restrict__ dpv = s.dp[0];
+    const T *wz0 = s.gz + (size_t)k * KZ;
+    const T *wz1 = s.gz + (size_t)(two ? k + 1 : k) * KZ;
+
+    // z-combines of d1 and d2 for slices k (a) and k + 1 (b) on the tile plus
+    // an R halo: source slice sl = k - RZ + t, tap k - sl of slice k and
+    // tap k + 1 - sl of slice k + 1 (sources in decreasing z, the order of a
+    // single slice's sum)
+    Region<W, H, R, R> rg(g, x0, y0);
+    T a1[rg.E], a2[rg.E], b1[rg.E], b2[rg.E];
+#pragma unroll
+    for (int qq = 0; qq < rg.E; ++qq) a1[qq] = a2[qq] = b1[qq] = b2[qq] = 0;
+#pragma unroll
+    for (int t = KZ; t >= 0; --t) {
+        const int sl = k - RZ + t;
+        if (sl < z0 || sl >= z1 || (t == KZ && !two)) continue;
+        const T wa = t < KZ ? wz0[KZ - 1 - t] : T(0);
+        const T wb = t > 0 && two ? wz1[KZ - t] : T(0);
+        const T *gs = gg + (size_t)sl * S, *ds = dpv + (size_t)sl * S;
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const T gv = ldo(gs, rg.off[qq]), dv = ldo(ds, rg.off[qq]);
+            if (t < KZ) {
+                a1[qq] -= wa * gv;
+                a2[qq] += wa * dv;
+            }
+            if (t > 0) {
+                b1[qq] -= wb * gv;
+                b2[qq] += wb * dv;
+            }
+        }
+    }
+    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)un.x, a1, a2, rg.off, rg.inb, A1, A2, B1, partials);
+    if (two) {
+        __syncthreads();  // the reduction of slice k read A2
+        dirs_finish<T, R, TYK>(g, prm, s, it, k + 1, (size_t)un.x + 1, b1, b2, rg.off, rg.inb, A1, A2, B1,
+                               partials);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1047,12 +1088,12 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
 
 template <typename T>
 hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
-                       int nitems, double *partials, hipStream_t st)
+                       const int2 *units, int nunits, double *partials, hipStream_t st)
 {
-    if (nitems <= 0) return hipSuccess;
+    if (nunits <= 0) return hipSuccess;
     BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
-                    hipLaunchKernelGGL((k_dirs<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0,
-                                       st, g, prm, s, items, partials))));
+                    hipLaunchKernelGGL((k_dirs<T, KZ, R, TYK>), grid_of(g, nunits, TYK), dim3(NT), 0,
+                                       st, g, prm, s, items, units, partials))));
     return hipGetLastError();
 }
 
@@ -1136,7 +1177,7 @@ hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
                                        const T *, const T *, T *, const Item *, int, int,         \
                                        double *, hipStream_t);                                    \
     template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
-                                       const Item *, int, double *, hipStream_t);                 \
+                                       const Item *, const int2 *, int, double *, hipStream_t);   \
     template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Item *, int,      \
                                          const int2 *, const double *, hipStream_t);              \
     template hipError_t launch_refresh<T>(const Geom &, const DevState<T> &, const T *, T *,       \

@@ -126,3 +126,29 @@ def test_round_batch_equals_single_runs(orc):
     b.run(7)
     for g, xs in zip(probs, single):
         assert np.array_equal(g.get_x(), xs)
+
+
+@pytest.mark.parametrize("schedule", [binding.SCHED_COLORED, binding.SCHED_ROUND])
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
+@pytest.mark.parametrize("kz", [7, 1])
+def test_direction_slices_per_workgroup_bitwise(orc, schedule, prec, kz):
+    """Two output slices per direction workgroup (their common source slices
+    read once) give bitwise the result of one slice per workgroup; blocks with
+    odd and even numbers of direction slices, kappa > 0 (the VZ sums), and the
+    FP64 trajectory of the paired pass against the oracle."""
+    nslices = [3, 1, 4, 2, 5]
+    runs = []
+    for per in (1, 2):
+        g, o, y = setup((15, 20, 70), 11, prec, 5, kz, nslices, schedule, mu=0.2, kappa=0.03)
+        g.set_option(binding.OPT_DIRS_SLICES, per)
+        g.run(6)
+        runs.append((g.get_x(), g.get_dprev()))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    if prec == binding.FP64:
+        x, d = y.copy(), np.zeros(y.shape)
+        if schedule == binding.SCHED_ROUND:
+            o.run_round(x, d, nslices, 6, history=False)
+        else:
+            nc, order, color = g.get_schedule()
+            o.run(x, d, nslices, order, 6, history=False)
+        assert rel(runs[1][0], x) <= 1e-9
