@@ -553,7 +553,7 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
                          p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
-    HIP_TRY(launch_update<T>(p->geom, s, it + gr.u_off, gr.u_cnt, p->d_pairs, p->d_u, p->stream));
+    HIP_TRY(launch_update<T>(p->geom, s, it + gr.u_off, gr.u_cnt, p->d_pairs, p->d_u, gr.round, p->stream));
     if (prof) ST_TRY(prof_end(p));
     return BD3MG_OK;
 }

@@ -124,10 +124,11 @@ template <typename T>
 hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
                        const int2 *units, int nunits, double *partials, hipStream_t st);
 
-// Update pass from the stored H d1, H d2 (pairs: (slot, block) per source).
+// Update pass from the stored H d1, H d2 (pairs: (slot, block) per source;
+// multi: items may have more than one source, as in a round).
 template <typename T>
 hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
-                         const int2 *pairs, const double *u, hipStream_t st);
+                         const int2 *pairs, const double *u, bool multi, hipStream_t st);
 
 // qout = XY^T (H src - y) on the items' slices.
 template <typename T>

@@ -697,7 +697,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, const 
 // passes of slice m.  Previous steps are read from dp[0] and written to
 // dp[1], so a workgroup never sees a half-updated step.
 // ---------------------------------------------------------------------------
-template <typename T, int R, int TYK>
+template <typename T, int R, int TYK, bool MULTI>
 __global__ void __launch_bounds__(NT)
 k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ pairs,
          const double *__restrict__ u)
@@ -741,7 +741,25 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
         T v[rg.E];
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) v[qq] = 0;
-        for (int p = 0; p < it.hn; ++p) {
+        // sources two at a time, so that the loads of both are in flight
+        // together (a round has several per slice; a colour has one, and
+        // its instance carries no code for more)
+        int p = 0;
+        for (; MULTI && p + 1 < it.hn; p += 2) {
+            const int2 pa = pairs[it.h0 + p], pb = pairs[it.h0 + p + 1];
+            const T a1 = (T)u[2 * pa.y], a2 = (T)u[2 * pa.y + 1];
+            const T b1 = (T)u[2 * pb.y], b2 = (T)u[2 * pb.y + 1];
+            const T *ha1 = s.hd[0] + (size_t)pa.x * S, *ha2 = s.hd[1] + (size_t)pa.x * S;
+            const T *hb1 = s.hd[0] + (size_t)pb.x * S, *hb2 = s.hd[1] + (size_t)pb.x * S;
+#pragma unroll
+            for (int qq = 0; qq < rg.E; ++qq) {
+                const T xa1 = ldo(ha1, rg.off[qq]), xa2 = ldo(ha2, rg.off[qq]);
+                const T xb1 = ldo(hb1, rg.off[qq]), xb2 = ldo(hb2, rg.off[qq]);
+                v[qq] += a1 * xa1 + a2 * xa2;
+                v[qq] += b1 * xb1 + b2 * xb2;
+            }
+        }
+        if (p < it.hn) {
             const int2 pr = pairs[it.h0 + p];
             const T c1 = (T)u[2 * pr.y], c2 = (T)u[2 * pr.y + 1];
             const T *h1 = s.hd[0] + (size_t)pr.x * S, *h2 = s.hd[1] + (size_t)pr.x * S;
@@ -1099,12 +1117,18 @@ hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, c
 
 template <typename T>
 hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
-                         const int2 *pairs, const double *u, hipStream_t st)
+                         const int2 *pairs, const double *u, bool multi, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
-                   hipLaunchKernelGGL((k_update<T, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
-                                      g, s, items, pairs, u)));
+    if (multi) {
+        BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
+                       hipLaunchKernelGGL((k_update<T, R, TYK, true>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                                          st, g, s, items, pairs, u)));
+    } else {
+        BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
+                       hipLaunchKernelGGL((k_update<T, R, TYK, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                                          st, g, s, items, pairs, u)));
+    }
     return hipGetLastError();
 }
 
@@ -1179,7 +1203,7 @@ hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
     template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
                                        const Item *, const int2 *, int, double *, hipStream_t);   \
     template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Item *, int,      \
-                                         const int2 *, const double *, hipStream_t);              \
+                                         const int2 *, const double *, bool, hipStream_t);        \
     template hipError_t launch_refresh<T>(const Geom &, const DevState<T> &, const T *, T *,       \
                                           const Item *, int, hipStream_t);                        \
     template hipError_t launch_H<T>(const Geom &, const DevState<T> &, const T *, const T *, T *,  \
