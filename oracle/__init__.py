@@ -30,6 +30,7 @@ class _Problem(C.Structure):
         ("kappa", C.c_double), ("xmin", C.c_double), ("xmax", C.c_double),
         ("dense", C.c_int),
         ("mu", C.c_double),
+        ("pk", C.c_void_p),
     ]
 
 
@@ -43,6 +44,7 @@ def lib():
         P = C.POINTER(_Problem)
         dp = C.c_void_p
         L.orc_gauss_table.argtypes = [C.c_int, C.c_int, dp, dp]
+        L.orc_rotated_gauss.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp]
         L.orc_H.argtypes = [P, dp, dp, C.c_int, C.c_int]
         L.orc_HT.argtypes = [P, dp, dp, C.c_int, C.c_int]
         L.orc_V.argtypes = [P, C.c_int, C.c_int, dp, dp]
@@ -100,13 +102,39 @@ def gauss_table(sigma, k: int) -> np.ndarray:
     return out
 
 
-class Problem:
-    """The criterion of Sec. 3.1 on one volume, with a separable depth-variant PSF.
+def rotated_gauss_kernels(sx, sy, theta, sz, kxy: int, kz: int) -> np.ndarray:
+    """[nz][kz][kxy][kxy] per-depth rotated anisotropic Gaussians, each summing
+    to 1 (the blur of the paper's experiments, Sec. 3.1: variance and rotation
+    drawn per depth)."""
+    a = [_f64(v) for v in (sx, sy, theta, sz)]
+    nz = a[0].size
+    assert all(v.size == nz for v in a)
+    out = np.empty((nz, kz, kxy, kxy), dtype=np.float64)
+    lib().orc_rotated_gauss(int(nz), int(kxy), int(kz), *[_ptr(v) for v in a], _ptr(out))
+    return out
 
-    gx, gy, gz: [nz][K] factor tables; y: [nz][ny][nx] observation.
-    dense=True evaluates H by its triple-sum definition, otherwise by the
-    separable twin.
+
+class Problem:
+    """The criterion of Sec. 3.1 on one volume, with a depth-variant PSF.
+
+    gx, gy, gz: [nz][K] factor tables of a separable PSF; y: [nz][ny][nx]
+    observation.  dense=True evaluates H by its triple-sum definition,
+    otherwise by the separable twin.  Problem.with_kernels takes general
+    per-slice kernels instead.
     """
+
+    @classmethod
+    def with_kernels(cls, y, pk, **kw):
+        """General per-slice kernels pk[nz][kz][ky][kx] (odd sizes), applied
+        by the triple sum (Hx)_k = sum_{c,b,a} pk[k][c][b][a] x_{k-c,j-b,i-a}."""
+        pk = _f64(pk)
+        nz = np.asarray(y).shape[0]
+        assert pk.ndim == 4 and pk.shape[0] == nz and all(n % 2 == 1 for n in pk.shape[1:])
+        kz, ky, kx = pk.shape[1:]
+        o = cls(y, np.zeros((nz, kx)), np.zeros((nz, ky)), np.zeros((nz, kz)), **kw)
+        o.pk = pk
+        o._s.pk = pk.ctypes.data
+        return o
 
     def __init__(self, y, gx, gy, gz, lam=0.0, delta=1.0, eta=0.0, kappa=0.0,
                  xmin=0.0, xmax=1.0, dense=False, mu=0.0):
@@ -124,7 +152,8 @@ class Problem:
                            self.gx.shape[1], self.gy.shape[1], self.gz.shape[1],
                            self.gx.ctypes.data, self.gy.ctypes.data, self.gz.ctypes.data,
                            self.y.ctypes.data, self.lam, self.delta, self.eta, self.kappa,
-                           self.xmin, self.xmax, int(self.dense), self.mu)
+                           self.xmin, self.xmax, int(self.dense), self.mu, None)
+        self.pk = None
 
     @property
     def shape(self):

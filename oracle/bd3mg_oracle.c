@@ -12,10 +12,13 @@
  * Conventions (readings of the paper where it is silent; each is listed with
  * its reason in the design notes of the repository):
  *   - Volumes are [nz][ny][nx], x fastest.  Index (k, j, i).
- *   - H is output-slice indexed (Sec. 3.1, "for each depth z the blur
- *     kernel..."): (Hx)_{k,j,i} = sum_{c,b,a} gz_k[c] gy_k[b] gx_k[a]
- *     x_{k-c, j-b, i-a}, zero padding, same size.  Tables are stored as
- *     g[k][a + r], a in [-r, r].
+ *   - H is output-slice indexed (Sec. 3.1: each depth has its own blur
+ *     kernel): (Hx)_{k,j,i} = sum_{c,b,a} P_k[c][b][a] x_{k-c, j-b, i-a},
+ *     zero padding, same size.  P_k is either separable, P_k[c][b][a] =
+ *     gz_k[c] gy_k[b] gx_k[a] with tables stored as g[k][a + r], a in
+ *     [-r, r], or a general kernel (the rotated Gaussians of random
+ *     variance and rotation that the paper draws per depth) stored as
+ *     pk[k][c + rz][b + ry][a + rx].
  *   - V^X, V^Y, V^Z are forward differences whose last difference is 0.
  *   - f is the criterion of Sec. 3.1 (eq. "eq_crit"):
  *       f(x) = 1/2 ||Hx - y||^2 + eta d^2(x, [xmin,xmax]^N)
@@ -53,6 +56,7 @@ typedef struct {
     double lambda, delta, eta, kappa, xmin, xmax;
     int dense;                   /* 1: triple-sum definition of H; 0: separable twin */
     double mu;                   /* curvature inflation of every block majorant (Assumption C); 0: none */
+    const double *pk;            /* general kernels [nz][kz][ky][kx] (triple sum), or NULL */
 } orc_problem;
 
 #define VOX(p, k, j, i) (((size_t)(k) * (size_t)(p)->ny + (size_t)(j)) * (size_t)(p)->nx + (size_t)(i))
@@ -111,8 +115,47 @@ void orc_gauss_table(int nz, int k, const double *sigma, double *out)
     }
 }
 
+/* General per-depth kernels of the paper's experiments (Sec. 3.1: each depth
+ * has a Gaussian blur of its own variance and rotation): for slice k, an
+ * anisotropic Gaussian with in-slice widths sx[k] along the axis rotated by
+ * theta[k] from x and sy[k] across it, and width sz[k] along z,
+ *   P_k[c][b][a] = exp(-u^2 / (2 sx^2) - v^2 / (2 sy^2) - c^2 / (2 sz^2)) / Z_k,
+ *   u = a cos(theta) + b sin(theta),  v = -a sin(theta) + b cos(theta),
+ * normalised so that every P_k sums to 1.  out is [nz][kz][kxy][kxy].      */
+void orc_rotated_gauss(int nz, int kxy, int kz, const double *sx, const double *sy,
+                       const double *theta, const double *sz, double *out)
+{
+    int r = kxy / 2, rz = kz / 2;
+    size_t per = (size_t)kz * kxy * kxy;
+    for (int k = 0; k < nz; ++k) {
+        double *o = out + (size_t)k * per;
+        double ct = cos(theta[k]), st = sin(theta[k]), tot = 0.0;
+        for (int c = -rz; c <= rz; ++c)
+            for (int b = -r; b <= r; ++b)
+                for (int a = -r; a <= r; ++a) {
+                    double u = a * ct + b * st, v = -a * st + b * ct;
+                    double e = u * u / (2.0 * sx[k] * sx[k]) + v * v / (2.0 * sy[k] * sy[k]) +
+                               (double)(c * c) / (2.0 * sz[k] * sz[k]);
+                    double w = exp(-e);
+                    o[((size_t)(c + rz) * kxy + (b + r)) * kxy + (a + r)] = w;
+                    tot += w;
+                }
+        for (size_t q = 0; q < per; ++q) o[q] /= tot;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* H and its adjoint, restricted to output slices [k0, k1).                  */
+
+/* Kernel weight P_k[c][b][a] (c, b, a centred). */
+static double psf_w(const orc_problem *p, int k, int c, int b, int a)
+{
+    int rx = p->kx / 2, ry = p->ky / 2, rz = p->kz / 2;
+    if (p->pk)
+        return p->pk[(((size_t)k * p->kz + (c + rz)) * p->ky + (b + ry)) * p->kx + (a + rx)];
+    return p->gz[(size_t)k * p->kz + c + rz] * p->gy[(size_t)k * p->ky + b + ry] *
+           p->gx[(size_t)k * p->kx + a + rx];
+}
 
 /* Triple-sum definition. */
 static void H_dense(const orc_problem *p, const double *x, double *out, int k0, int k1)
@@ -120,9 +163,6 @@ static void H_dense(const orc_problem *p, const double *x, double *out, int k0, 
     int rx = p->kx / 2, ry = p->ky / 2, rz = p->kz / 2;
 #pragma omp parallel for schedule(static)
     for (int k = k0; k < k1; ++k) {
-        const double *gz = p->gz + (size_t)k * p->kz;
-        const double *gy = p->gy + (size_t)k * p->ky;
-        const double *gx = p->gx + (size_t)k * p->kx;
         for (int j = 0; j < p->ny; ++j)
             for (int i = 0; i < p->nx; ++i) {
                 double s = 0.0;
@@ -135,7 +175,7 @@ static void H_dense(const orc_problem *p, const double *x, double *out, int k0, 
                         for (int a = -rx; a <= rx; ++a) {
                             int ii = i - a;
                             if (ii < 0 || ii >= p->nx) continue;
-                            double w = gz[c + rz] * gy[b + ry] * gx[a + rx];
+                            double w = psf_w(p, k, c, b, a);
                             s += w * x[VOX(p, kk, jj, ii)];
                         }
                     }
@@ -145,7 +185,7 @@ static void H_dense(const orc_problem *p, const double *x, double *out, int k0, 
     }
 }
 
-/* (H^T r)_{k,j,i} = sum_{c,b,a} gz_{k+c}[c] gy_{k+c}[b] gx_{k+c}[a] r_{k+c, j+b, i+a}. */
+/* (H^T r)_{k,j,i} = sum_{c,b,a} P_{k+c}[c][b][a] r_{k+c, j+b, i+a}. */
 static void HT_dense(const orc_problem *p, const double *r, double *out, int k0, int k1)
 {
     int rx = p->kx / 2, ry = p->ky / 2, rz = p->kz / 2;
@@ -157,16 +197,13 @@ static void HT_dense(const orc_problem *p, const double *r, double *out, int k0,
                 for (int c = -rz; c <= rz; ++c) {
                     int kk = k + c;
                     if (kk < 0 || kk >= p->nz) continue;
-                    const double *gz = p->gz + (size_t)kk * p->kz;
-                    const double *gy = p->gy + (size_t)kk * p->ky;
-                    const double *gx = p->gx + (size_t)kk * p->kx;
                     for (int b = -ry; b <= ry; ++b) {
                         int jj = j + b;
                         if (jj < 0 || jj >= p->ny) continue;
                         for (int a = -rx; a <= rx; ++a) {
                             int ii = i + a;
                             if (ii < 0 || ii >= p->nx) continue;
-                            double w = gz[c + rz] * gy[b + ry] * gx[a + rx];
+                            double w = psf_w(p, kk, c, b, a);
                             s += w * r[VOX(p, kk, jj, ii)];
                         }
                     }
@@ -277,7 +314,7 @@ void orc_H(const orc_problem *p, const double *x, double *out, int k0, int k1)
     if (k0 < 0) k0 = 0;
     if (k1 > p->nz) k1 = p->nz;
     if (k0 >= k1) return;
-    if (p->dense) H_dense(p, x, out, k0, k1); else H_sep(p, x, out, k0, k1);
+    if (p->dense || p->pk) H_dense(p, x, out, k0, k1); else H_sep(p, x, out, k0, k1);
 }
 
 void orc_HT(const orc_problem *p, const double *r, double *out, int k0, int k1)
@@ -285,7 +322,7 @@ void orc_HT(const orc_problem *p, const double *r, double *out, int k0, int k1)
     if (k0 < 0) k0 = 0;
     if (k1 > p->nz) k1 = p->nz;
     if (k0 >= k1) return;
-    if (p->dense) HT_dense(p, r, out, k0, k1); else HT_sep(p, r, out, k0, k1);
+    if (p->dense || p->pk) HT_dense(p, r, out, k0, k1); else HT_sep(p, r, out, k0, k1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -675,6 +712,23 @@ double orc_lipschitz_bound(const orc_problem *p)
 {
     int rz = p->kz / 2;
     double rmax = 0.0, cmax = 0.0;
+    if (p->pk) {
+        /* general kernels: row sums of |H| are bounded by sum |P_k| of the
+         * output slice, column sums by what an input slice s gathers from the
+         * slices s + c it reaches, sum_c sum_{b,a} |P_{s+c}[c][b][a]| */
+        size_t kk = (size_t)p->ky * p->kx;
+        for (int k = 0; k < p->nz; ++k) {
+            double r = 0.0, c = 0.0;
+            for (int t = -rz; t <= rz; ++t)
+                for (size_t q = 0; q < kk; ++q) {
+                    r += fabs(p->pk[((size_t)k * p->kz + t + rz) * kk + q]);
+                    if (k + t >= 0 && k + t < p->nz) c += fabs(p->pk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);
+                }
+            if (r > rmax) rmax = r;
+            if (c > cmax) cmax = c;
+        }
+        return rmax * cmax + 2.0 * p->eta + 8.0 * p->lambda / p->delta + 8.0 * p->kappa;
+    }
     for (int k = 0; k < p->nz; ++k) {
         double r = 0.0, c = 0.0;
         for (int t = -rz; t <= rz; ++t) {

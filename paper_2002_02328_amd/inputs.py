@@ -182,6 +182,54 @@ def tiny(shape, seed, kxy=3, kz=3, nblocks=None, lam=0.01, delta=0.05, eta=0.01,
                     lam, delta, eta, kappa, nsl, sweeps=10, fp64=True)
 
 
+def rotated_psf_draws(nz, rng, sxy=(0.5, 2.5), sz=(1.0, 4.0)):
+    """Per-depth parameters of a rotated anisotropic Gaussian blur (the paper
+    draws variance and rotation per depth from uniform laws): in-slice widths
+    sx, sy ~ U[sxy], rotation theta ~ U[0, pi), z width sz ~ U[sz]."""
+    return {"sx": rng.uniform(*sxy, nz), "sy": rng.uniform(*sxy, nz),
+            "theta": rng.uniform(0.0, np.pi, nz), "sz": rng.uniform(*sz, nz)}
+
+
+def dense_fp32_256x256x24(seed=7000):
+    """256x256x24 FP32 volume (the size of the paper's FlyBrain test), 60
+    ellipsoids, per-depth rotated Gaussian kernels 11x11x21 (in-slice widths
+    U[0.5, 2.5], rotation U[0, pi), z width U[1, 4]), noise 0.04, lambda 0.01,
+    delta 0.02, eta 0.01, 8 uneven blocks of 2..4 slices."""
+    shape = (24, 256, 256)
+    rp, rn, rb = _seeds(seed)
+    xbar = ellipsoid_phantom(shape, 60, rp)
+    noise = 0.04 * rn.standard_normal(shape)
+    psf = rotated_psf_draws(24, np.random.default_rng(seed + 3))
+    return Workload("dense-fp32-256x256x24", shape, xbar, noise, np.zeros(24), np.zeros(24), 11, 21,
+                    0.01, 0.02, 0.01, 0.0, uneven_partition(24, 8, 2, 4, rb), grad_rtol=1e-4,
+                    extra={"psf": psf})
+
+
+def dense_fp32_155x154x79(seed=7100):
+    """155x154x79 FP32 volume (the size of the paper's Aneurysm test), 80
+    ellipsoids, per-depth rotated Gaussian kernels 5x5x11 (in-slice widths
+    U[0.5, 1.5], rotation U[0, pi), z width U[0.5, 2.5]), noise 0.04, 16
+    uneven blocks of 3..7 slices."""
+    shape = (79, 154, 155)
+    rp, rn, rb = _seeds(seed)
+    xbar = ellipsoid_phantom(shape, 80, rp)
+    noise = 0.04 * rn.standard_normal(shape)
+    psf = rotated_psf_draws(79, np.random.default_rng(seed + 3), sxy=(0.5, 1.5), sz=(0.5, 2.5))
+    return Workload("dense-fp32-155x154x79", shape, xbar, noise, np.zeros(79), np.zeros(79), 5, 11,
+                    0.01, 0.02, 0.01, 0.0, uneven_partition(79, 16, 3, 7, rb), grad_rtol=1e-4,
+                    extra={"psf": psf})
+
+
+def tiny_dense(shape, seed, kxy=5, kz=5, nblocks=None, lam=0.01, delta=0.05, eta=0.01, kappa=0.0,
+               sxy=(0.5, 1.5), sz=(0.6, 2.0), noise=0.02):
+    """Small random problem with rotated per-depth kernels, for tests."""
+    w = tiny(shape, seed, kxy=kxy, kz=kz, nblocks=nblocks, lam=lam, delta=delta, eta=eta,
+             kappa=kappa, noise=noise)
+    w.name = "tiny-dense-%dx%dx%d" % (shape[2], shape[1], shape[0])
+    w.extra = {"psf": rotated_psf_draws(shape[0], np.random.default_rng(seed + 3), sxy, sz)}
+    return w
+
+
 def warmstart_train_member(t, seed_base=5_000_000):
     """Training pair t of the learned warm start: a 128x128x32 volume with 25
     ellipsoids (the ellipsoid density of the 256x256x64 volume), the 256x256x64
@@ -230,4 +278,6 @@ WORKLOADS = {
     "plain-fp64-64x64x16": small_plain_fp64,
     "plain-fp32-256x256x64": mid_fp32,
     "plain-fp32-512x512x128": large_fp32,
+    "dense-fp32-256x256x24": dense_fp32_256x256x24,
+    "dense-fp32-155x154x79": dense_fp32_155x154x79,
 }

@@ -40,6 +40,14 @@ MUTATIONS = {
                                   "            for (size_t q = (size_t)z0 * nslice(p); q < (size_t)(z0 + nslices[b]) * nslice(p); ++q)"
                                   " { x[q] += dn[q]; dprev[q] = dn[q]; dn[q] = 0.0; }\n"),
     "lipschitz-tv-term": ("8.0 * p->lambda / p->delta", "p->lambda / p->delta"),
+    "dense-kernel-of-input-slice": ("double w = psf_w(p, k, c, b, a);", "double w = psf_w(p, kk, c, b, a);"),
+    "dense-adjoint-kernel-of-output-slice": ("double w = psf_w(p, kk, c, b, a);", "double w = psf_w(p, k, c, b, a);"),
+    "dense-tap-flipped-in-z": ("p->pk[(((size_t)k * p->kz + (c + rz)) * p->ky",
+                               "p->pk[(((size_t)k * p->kz + (rz - c)) * p->ky"),
+    "rotation-direction": ("double u = a * ct + b * st, v = -a * st + b * ct;",
+                           "double u = a * ct - b * st, v = a * st + b * ct;"),
+    "dense-lipschitz-column-sums": ("if (k + t >= 0 && k + t < p->nz) c += fabs(p->pk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);",
+                                    "if (k + t >= 0 && k + t < p->nz) c += 0.5 * fabs(p->pk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);"),
 }
 
 NET_MUTATIONS = {
@@ -59,7 +67,8 @@ NET_MUTATIONS = {
     "net-bf16-ties-away": ("u += 0x7fffu + lsb;", "u += 0x8000u; (void)lsb;"),
 }
 
-PIN_FILES = {SRC: ["test_oracle_pins.py", "test_oracle_round.py"], NET_SRC: ["test_oracle_convnet.py"]}
+PIN_FILES = {SRC: ["test_oracle_pins.py", "test_oracle_round.py", "test_oracle_dense.py"],
+             NET_SRC: ["test_oracle_convnet.py"]}
 
 
 def _cases():
