@@ -118,6 +118,27 @@ bd3mg_status bd3mg_set_psf_separable(bd3mg_problem p, int kx, int ky, int kz,
 bd3mg_status bd3mg_set_psf_gaussian(bd3mg_problem p, int kxy, int kz,
                                     const double *sigma_xy, const double *sigma_z);
 
+/* Per-depth rotated anisotropic Gaussian kernels (Sec. 3.1: the blur of each
+ * depth has its own variance and rotation, drawn at random): for slice z,
+ *   P_z[t][b][a] = exp(-u^2 / (2 sx^2) - v^2 / (2 sy^2) - t^2 / (2 sz^2)) / Z_z,
+ *   u = a cos(theta) + b sin(theta),  v = b cos(theta) - a sin(theta),
+ * t, b, a centred (|t| <= kz/2, |b|, |a| <= kxy/2), each kernel summing to 1.
+ * Host arrays sx, sy, theta, sz [nz]; out [nz][kz][kxy][kxy] (host, caller
+ * owned).  ERR_ARG: even sizes, nz < 1, a width <= 0 or a non-finite
+ * value. */
+bd3mg_status bd3mg_psf_rotated_gaussian(int nz, int kxy, int kz, const double *sx, const double *sy,
+                                        const double *theta, const double *sz, double *out);
+
+/* General depth-variant PSF (Sec. 3.1, eq. "model"): the kernel of output
+ * slice k is P[k] (host, [nz][kz][ky][kx], c, b, a centred) and
+ *   (Hx)_k[j][i] = sum_{c,b,a} P_k[c][b][a] x_{k-c}[j-b][i-a]
+ * with zero padding.  Replaces a separable PSF (and a separable PSF set later
+ * replaces this one).  The passes then use the general kernels: the
+ * maintained residual vector (the q of bd3mg_get_state / bd3mg_set_state) is
+ * r = Hx - y itself.  ERR_ARG: even sizes, kx or ky > 11, kz > 21, or a
+ * non-finite entry.  Marks the residual stale. */
+bd3mg_status bd3mg_set_psf_dense(bd3mg_problem p, int kx, int ky, int kz, const double *P);
+
 /* Parameters of f (Sec. 3.1, eq. "eq_crit").  ERR_ARG: delta <= 0, lambda,
  * eta or kappa < 0, xmin > xmax, or a non-finite value.  Defaults before the
  * first call: lambda = eta = kappa = 0, delta = 1, [xmin, xmax] = [0, 1]. */
@@ -164,7 +185,8 @@ bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device);
 /* Run BD3MG sweeps from the current state (x, each block's previous step and
  * the maintained blurred residual q, q_m = XY^T_m (H x - y)_m: the residual of
  * slice m blurred by the adjoint of slice m's in-slice factors, from which
- * H^T (H x - y) is a z-stencil), so calls can be chained: run(a) then run(b)
+ * H^T (H x - y) is a z-stencil; with a general PSF, q = H x - y), so calls
+ * can be chained: run(a) then run(b)
  * gives bitwise the same state as run(a + b).  Stops after max_sweeps
  * sweeps, or, when grad_rtol > 0, at the first check with ||grad f(x)|| <=
  * grad_rtol * ||grad f(y)||; a check happens every check_every sweeps and

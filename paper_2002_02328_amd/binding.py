@@ -34,6 +34,8 @@ SIGNATURES = {
     "bd3mg_destroy": ([_dp], C.c_int),
     "bd3mg_set_psf_separable": ([_dp, _i, _i, _i, _dp, _dp, _dp], C.c_int),
     "bd3mg_set_psf_gaussian": ([_dp, _i, _i, _dp, _dp], C.c_int),
+    "bd3mg_psf_rotated_gaussian": ([_i, _i, _i, _dp, _dp, _dp, _dp, _dp], C.c_int),
+    "bd3mg_set_psf_dense": ([_dp, _i, _i, _i, _dp], C.c_int),
     "bd3mg_set_params": ([_dp, _d, _d, _d, _d, _d, _d], C.c_int),
     "bd3mg_set_data": ([_dp, _dp, _i], C.c_int),
     "bd3mg_set_blocks": ([_dp, _i, _dp, _i], C.c_int),
@@ -117,6 +119,17 @@ def psf_gaussian(sigma, k):
     return out
 
 
+def psf_rotated_gaussian(sx, sy, theta, sz, kxy, kz):
+    """[nz][kz][kxy][kxy] per-depth rotated Gaussian kernels (host)."""
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (sx, sy, theta, sz)]
+    nz = a[0].size
+    if any(v.size != nz for v in a):
+        raise ValueError("need one value of each parameter per slice")
+    out = np.empty((nz, kz, kxy, kxy), dtype=np.float64)
+    _check(load().bd3mg_psf_rotated_gaussian(nz, kxy, kz, *[v.ctypes.data for v in a], out.ctypes.data))
+    return out
+
+
 def probe_copy(nbytes, iters=5):
     """(GB/s, ms) of the best of iters streaming copies of nbytes."""
     gb, ms = C.c_double(), C.c_double()
@@ -180,6 +193,13 @@ class Problem:
         if sxy.size != self.shape[0] or sz.size != self.shape[0]:
             raise ValueError("need one sigma per slice")
         _check(load().bd3mg_set_psf_gaussian(self._h, kxy, kz, sxy.ctypes.data, sz.ctypes.data))
+
+    def set_psf_dense(self, P):
+        """General per-depth kernels P[nz][kz][ky][kx]."""
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        if P.ndim != 4 or P.shape[0] != self.shape[0]:
+            raise ValueError("kernels must be [nz][kz][ky][kx]")
+        _check(load().bd3mg_set_psf_dense(self._h, P.shape[3], P.shape[2], P.shape[1], P.ctypes.data))
 
     def set_params(self, lam, delta, eta, kappa=0.0, xmin=0.0, xmax=1.0):
         _check(load().bd3mg_set_params(self._h, lam, delta, eta, kappa, xmin, xmax))

@@ -52,10 +52,15 @@ struct bd3mg_problem_s {
     int kx = 0, ky = 0, kz = 0;
     void *d_gx = nullptr, *d_gy = nullptr, *d_gz = nullptr;
     std::vector<double> hgx, hgy, hgz;  // the tables as given (for the Lipschitz bound)
+    // general per-depth kernels: then the maintained vector q holds r = Hx - y
+    bool dense = false;
+    void *d_pk = nullptr;    // [nz][kz][2R+1][2R+1], storage type
+    void *d_ones = nullptr;  // [nz] ones: the z table of the gradient pass in the dense mode
+    std::vector<double> hpk;  // [nz][kz][ky][kx] as given
 
     // volumes (storage type); q is the in-slice adjoint-blurred residual
     void *x = nullptr, *y = nullptr, *q = nullptr, *g = nullptr, *dpb[2] = {nullptr, nullptr};
-    void *tmp[3] = {nullptr, nullptr, nullptr};
+    void *tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // tmp[3]: H^T r of the dense mode
     int cur = 0;  // dpb[cur] holds every block's last step
     bool data_set = false, x_set = false, q_stale = true;
 
@@ -138,6 +143,25 @@ DevState<T> dev_state(bd3mg_problem p)
     s.hd[1] = s.hd[0] ? s.hd[0] + p->hd_slots * p->nx * p->ny : nullptr;
     s.stop = nullptr;
     return s;
+}
+
+// Gradient pass of the dense mode: H^T r on the items' slices into tmp[3] by
+// the general-kernel adjoint, then the gradient kernel with a one-tap z table
+// reading it (the rest of grad f and the partial sums as in the separable
+// mode).
+template <typename T>
+hipError_t dense_grad(bd3mg_problem p, const DevState<T> &s, const T *r, const T *x, T *out,
+                      const Item *items, int n, int mode, double *partials)
+{
+    T *ht = (T *)p->tmp[3];
+    hipError_t e = launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, r, nullptr, ht, items, n, DM_HT,
+                                   nullptr, p->stream);
+    if (e != hipSuccess) return e;
+    Geom g1 = p->geom;
+    g1.rz = 0;
+    DevState<T> s1 = s;
+    s1.gz = (const T *)p->d_ones;
+    return launch_grad<T>(g1, p->prm, s1, ht, x, out, items, n, mode, partials, p->stream);
 }
 
 bd3mg_status check_finite(const double *v, size_t n, const char *what)
@@ -357,7 +381,8 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     // solve reads the partial sums; update pass reads H d1, H d2 of its source
     // pairs, g, dp, x on S and q on S +- r_z, writes x, dp on S and q on S +- r_z.
     const double A = (double)p->nx * p->ny * p->esz;
-    grp.bytes[0] = A * (h + 3.0 * sl);
+    // (dense mode: the gradient pass also writes and reads H^T r on S)
+    grp.bytes[0] = A * (h + (p->dense ? 5.0 : 3.0) * sl);
     grp.bytes[1] = A * (2.0 * sl + 2.0 * grp.d_cnt);
     grp.bytes[2] = (double)(grp.g_cnt * NQG + grp.d_cnt * NQD) * p->ntiles * sizeof(double);
     grp.bytes[3] = A * (2.0 * np + 5.0 * sl + 2.0 * h);
@@ -433,6 +458,7 @@ bd3mg_status build_schedule(bd3mg_problem p)
     ST_TRY(realloc_dev(&p->d_hd, &p->hd_alloc, 2 * (size_t)maxd * p->nx * p->ny * p->esz,
                        "stored directions H d1, H d2"));
     p->hd_slots = (size_t)maxd;
+    if (p->dense) ST_TRY(ensure_tmp(p, 4));  // H^T r of the gradient pass
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->sched_dirty = false;
     return BD3MG_OK;
@@ -444,6 +470,11 @@ bd3mg_status refresh_t(bd3mg_problem p, const T *src, T *qout, const int *stop)
 {
     DevState<T> s = dev_state<T>(p);
     s.stop = stop;
+    if (p->dense) {
+        HIP_TRY(launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, src, s.y, qout, p->d_vol, p->nz, DM_H,
+                                nullptr, p->stream));
+        return BD3MG_OK;
+    }
     HIP_TRY(launch_refresh<T>(p->geom, s, src, qout, p->d_vol, p->nz, p->stream));
     return BD3MG_OK;
 }
@@ -461,8 +492,12 @@ bd3mg_status check_t(bd3mg_problem p, double thr, int sweep, int *stop)
 {
     DevState<T> s = dev_state<T>(p);
     s.stop = stop;
-    HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.q, s.x, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe,
-                           p->stream));
+    if (p->dense) {
+        HIP_TRY(dense_grad<T>(p, s, s.q, s.x, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe));
+    } else {
+        HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.q, s.x, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe,
+                               p->stream));
+    }
     HIP_TRY(launch_check(p->d_pe, p->ntiles * p->nz, thr, sweep, &p->d_ctl->stop, &p->d_ctl->stop_sweep,
                          &p->d_ctl->gnorm, p->stream));
     return BD3MG_OK;
@@ -481,15 +516,27 @@ bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, doub
 {
     DevState<T> s = dev_state<T>(p);
     const int nslot = p->ntiles * p->nz;
-    HIP_TRY(launch_grad<T>(p->geom, p->prm, s, qin, xin, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe,
-                           p->stream));
+    if (p->dense) {
+        ST_TRY(ensure_tmp(p, 4));
+        HIP_TRY(dense_grad<T>(p, s, qin, xin, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe));
+    } else {
+        HIP_TRY(launch_grad<T>(p->geom, p->prm, s, qin, xin, nullptr, p->d_vol, p->nz, GM_EVAL, p->d_pe,
+                               p->stream));
+    }
     HIP_TRY(launch_sum(p->d_pe, nslot, NQE, p->d_sum, p->stream));
     if (f) {
         ST_TRY(ensure_tmp(p, 1));
-        HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, (T *)p->tmp[0], p->d_vol, p->nz, p->d_pr,
-                            p->stream));
-        HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, p->geom.ty_aux) * p->nz, 1, p->d_sum + NQE,
-                           p->stream));
+        if (p->dense) {
+            HIP_TRY(launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, xin, (const T *)p->y, (T *)p->tmp[0],
+                                    p->d_vol, p->nz, DM_H, p->d_pr, p->stream));
+            HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, DENSE_TILE_ROWS) * p->nz, 1, p->d_sum + NQE,
+                               p->stream));
+        } else {
+            HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, (T *)p->tmp[0], p->d_vol, p->nz, p->d_pr,
+                                p->stream));
+            HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, p->geom.ty_aux) * p->nz, 1, p->d_sum + NQE,
+                               p->stream));
+        }
     }
     double q[NQE + 1] = {0, 0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(q, p->d_sum, (f ? NQE + 1 : NQE) * sizeof(double), hipMemcpyDeviceToHost,
@@ -539,6 +586,26 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
     DevState<T> s = dev_state<T>(p);
     s.stop = stop;
     const Item *it = p->d_items;
+    if (p->dense) {
+        // general kernels: H^T r and grad f on S, H d1 and H d2 on S +- r_z by
+        // the dense kernels, r += u1 H d1 + u2 H d2 elementwise
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_GRAD, gr.bytes[0]));
+        HIP_TRY(dense_grad<T>(p, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK, p->d_pg));
+        if (prof) ST_TRY(prof_end(p));
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
+        HIP_TRY(launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, nullptr, nullptr, nullptr, it + gr.d_off,
+                                gr.d_cnt, DM_DIRS, p->d_pd, p->stream));
+        if (prof) ST_TRY(prof_end(p));
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
+        HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,
+                             tiles_of(p->geom, DENSE_TILE_ROWS), p->d_pg, p->d_pd, p->d_u, p->d_info, stop,
+                             p->stream));
+        if (prof) ST_TRY(prof_end(p));
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
+        HIP_TRY(launch_dense_update<T>(p->geom, s, it + gr.u_off, gr.u_cnt, p->d_pairs, p->d_u, p->stream));
+        if (prof) ST_TRY(prof_end(p));
+        return BD3MG_OK;
+    }
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_GRAD, gr.bytes[0]));
     HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK,
                            p->d_pg, p->stream));
@@ -572,6 +639,22 @@ template <typename T>
 bd3mg_status apply_t(bd3mg_problem p, int op, T *ti, T *to, T *tr)
 {
     DevState<T> s = dev_state<T>(p);
+    if (p->dense) {
+        const T *pk = (const T *)p->d_pk;
+        if (op == BD3MG_OP_H) {
+            HIP_TRY(launch_dense<T>(p->geom, p->prm, s, pk, ti, nullptr, to, p->d_vol, p->nz, DM_H, nullptr,
+                                    p->stream));
+        } else if (op == BD3MG_OP_HT) {
+            HIP_TRY(launch_dense<T>(p->geom, p->prm, s, pk, ti, nullptr, to, p->d_vol, p->nz, DM_HT, nullptr,
+                                    p->stream));
+        } else {
+            ST_TRY(ensure_tmp(p, 4));
+            HIP_TRY(launch_dense<T>(p->geom, p->prm, s, pk, ti, s.y, tr, p->d_vol, p->nz, DM_H, nullptr,
+                                    p->stream));
+            HIP_TRY(dense_grad<T>(p, s, tr, ti, to, p->d_vol, p->nz, GM_GRAD, nullptr));
+        }
+        return BD3MG_OK;
+    }
     if (op == BD3MG_OP_H) {
         HIP_TRY(launch_H<T>(p->geom, s, ti, nullptr, to, p->d_vol, p->nz, nullptr, p->stream));
     } else if (op == BD3MG_OP_HT) {
@@ -687,7 +770,8 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
 {
     if (!p) return BD3MG_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
-    void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2],
+    void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2], p->tmp[3],
+                    p->d_pk, p->d_ones,
                     p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_sblk, p->d_pg, p->d_pd,
                     p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_pairs, p->d_hd,
                     p->d_units};
@@ -749,6 +833,7 @@ bd3mg_status bd3mg_set_psf_separable(bd3mg_problem p, int kx, int ky, int kz, co
     p->geom.rx = kx / 2;
     p->geom.ry = ky / 2;
     p->geom.rz = kz / 2;
+    p->dense = false;
     p->psf_set = true;
     p->q_stale = true;
     p->gnorm_ref_valid = false;
@@ -791,6 +876,88 @@ bd3mg_status bd3mg_set_inflation(bd3mg_problem p, double mu)
     return BD3MG_OK;
 }
 
+bd3mg_status bd3mg_psf_rotated_gaussian(int nz, int kxy, int kz, const double *sx, const double *sy,
+                                        const double *theta, const double *sz, double *out)
+{
+    if (nz < 1 || kxy < 1 || kz < 1 || (kxy % 2) == 0 || (kz % 2) == 0)
+        return fail(BD3MG_ERR_ARG, "need nz >= 1 and odd kernel sizes");
+    if (!sx || !sy || !theta || !sz || !out) return fail(BD3MG_ERR_ARG, "null pointer");
+    for (int z = 0; z < nz; ++z)
+        if (!(sx[z] > 0.0) || !(sy[z] > 0.0) || !(sz[z] > 0.0) || !std::isfinite(sx[z]) ||
+            !std::isfinite(sy[z]) || !std::isfinite(sz[z]) || !std::isfinite(theta[z]))
+            return fail(BD3MG_ERR_ARG, "widths must be positive and finite, the angle finite (slice %d)", z);
+    const int r = kxy / 2, rz = kz / 2;
+    const size_t per = (size_t)kz * kxy * kxy;
+    for (int z = 0; z < nz; ++z) {
+        double *o = out + (size_t)z * per;
+        const double c = std::cos(theta[z]), sn = std::sin(theta[z]);
+        const double ax = 0.5 / (sx[z] * sx[z]), ay = 0.5 / (sy[z] * sy[z]), az = 0.5 / (sz[z] * sz[z]);
+        double tot = 0.0;
+        size_t q = 0;
+        for (int t = -rz; t <= rz; ++t)
+            for (int b = -r; b <= r; ++b)
+                for (int a = -r; a <= r; ++a, ++q) {
+                    // coordinates along and across the rotated axis
+                    const double u = c * a + sn * b, v = c * b - sn * a;
+                    o[q] = std::exp(-(ax * u * u + ay * v * v + az * t * t));
+                    tot += o[q];
+                }
+        for (q = 0; q < per; ++q) o[q] /= tot;
+    }
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_set_psf_dense(bd3mg_problem p, int kx, int ky, int kz, const double *P)
+{
+    ST_TRY(validate_handle(p));
+    for (int k : {kx, ky})
+        if (k < 1 || (k % 2) == 0 || k > 2 * RDMAX + 1)
+            return fail(BD3MG_ERR_ARG, "in-slice kernel sizes must be odd, 1..%d (got %d)", 2 * RDMAX + 1, k);
+    if (kz < 1 || (kz % 2) == 0 || kz > KZDMAX)
+        return fail(BD3MG_ERR_ARG, "kz must be odd, 1..%d (got %d)", KZDMAX, kz);
+    if (!P) return fail(BD3MG_ERR_ARG, "null kernel table");
+    const size_t per = (size_t)kz * ky * kx;
+    ST_TRY(check_finite(P, (size_t)p->nz * per, "P"));
+    // stored centred in (2R + 1) x (2R + 1) per tap plane, R = max(rx, ry, 1)
+    const int R = std::max(1, std::max(kx / 2, ky / 2)), KR = 2 * R + 1;
+    const size_t n = (size_t)p->nz * kz * KR * KR;
+    std::vector<double> t(n, 0.0);
+    for (int z = 0; z < p->nz; ++z)
+        for (int c = 0; c < kz; ++c)
+            for (int b = 0; b < ky; ++b)
+                for (int a = 0; a < kx; ++a)
+                    t[(((size_t)z * kz + c) * KR + (R - ky / 2 + b)) * KR + (R - kx / 2 + a)] =
+                        P[(((size_t)z * kz + c) * ky + b) * kx + a];
+    if (p->d_pk) HIP_TRY(hipFree(p->d_pk));
+    if (p->d_ones) HIP_TRY(hipFree(p->d_ones));
+    p->d_pk = p->d_ones = nullptr;
+    if (hipMalloc(&p->d_pk, n * p->esz) != hipSuccess || hipMalloc(&p->d_ones, (size_t)p->nz * p->esz) != hipSuccess)
+        return fail(BD3MG_ERR_NOMEM, "kernel table");
+    std::vector<double> ones((size_t)p->nz, 1.0);
+    if (p->prec == BD3MG_FP64) {
+        HIP_TRY(hipMemcpy(p->d_pk, t.data(), n * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_ones, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(t.begin(), t.end()), o(ones.begin(), ones.end());
+        HIP_TRY(hipMemcpy(p->d_pk, f.data(), n * sizeof(float), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(p->d_ones, o.data(), o.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    p->hpk.assign(P, P + (size_t)p->nz * per);
+    p->geom.R = R;
+    p->kx = kx;
+    p->ky = ky;
+    p->kz = kz;
+    p->geom.rx = kx / 2;
+    p->geom.ry = ky / 2;
+    p->geom.rz = kz / 2;
+    p->dense = true;
+    p->psf_set = true;
+    p->q_stale = true;
+    p->gnorm_ref_valid = false;
+    p->sched_dirty = true;
+    return BD3MG_OK;
+}
+
 bd3mg_status bd3mg_lipschitz_bound(bd3mg_problem p, double *L)
 {
     ST_TRY(validate_handle(p));
@@ -799,6 +966,25 @@ bd3mg_status bd3mg_lipschitz_bound(bd3mg_problem p, double *L)
     // the tables in the storage precision, as the operator uses them
     auto st = [&](double v) { return std::fabs(p->prec == BD3MG_FP64 ? v : (double)(float)v); };
     const int rz = p->kz / 2, nz = p->nz;
+    if (p->dense) {
+        // row sums of |H| bounded by sum |P_k| of an output slice, column sums
+        // by what an input slice s gathers, sum_c sum_{b,a} |P_{s+c}[c][b][a]|
+        const size_t kk = (size_t)p->ky * p->kx;
+        double rmax = 0.0, cmax = 0.0;
+        for (int k = 0; k < nz; ++k) {
+            double r = 0.0, c = 0.0;
+            for (int t = -rz; t <= rz; ++t)
+                for (size_t q = 0; q < kk; ++q) {
+                    r += st(p->hpk[((size_t)k * p->kz + t + rz) * kk + q]);
+                    if (k + t >= 0 && k + t < nz) c += st(p->hpk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);
+                }
+            rmax = std::max(rmax, r);
+            cmax = std::max(cmax, c);
+        }
+        const Params &q = p->prm;
+        *L = rmax * cmax + 2.0 * q.eta + 8.0 * q.lambda / q.delta + 8.0 * q.kappa;
+        return BD3MG_OK;
+    }
     double rmax = 0.0, cmax = 0.0, sx = 0.0, sy = 0.0;
     for (int k = 0; k < nz; ++k) {
         double r = 0.0, c = 0.0, ax = 0.0, ay = 0.0;
@@ -1057,6 +1243,7 @@ bd3mg_status bd3mg_autotune(bd3mg_problem p, int sweeps, int *chosen, double *ms
     p->profile = false;
     std::vector<int> cand = {16};
     if (p->prec == BD3MG_FP32) cand.push_back(32);
+    if (p->dense) cand = {p->geom.ty_dirs};  // the dense kernels have one tile shape
     double best = -1.0;
     int bd = p->geom.ty_dirs, bu = p->geom.ty_update;
     for (int td : cand)

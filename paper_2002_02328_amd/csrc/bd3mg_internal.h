@@ -146,6 +146,27 @@ template <typename T>
 hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out,
                         const Item *items, int nitems, hipStream_t st);
 
+// General per-depth kernels (dense PSF), pk = [nz][kz][2R+1][2R+1]:
+// DM_H    out = H in (- sub, may be null), partials (optional): per (item,
+//         tile) sum of out^2;
+// DM_DIRS H d1, H d2 of the items' blocks (d1 = -g, d2 = dp) -> s.hd at the
+//         item's slot, partials NQD per (item, tile);
+// DM_HT   out = H^T in.
+// Tiles are TX x DENSE_TILE_ROWS.
+constexpr int DENSE_TILE_ROWS = 32;
+constexpr int RDMAX = 5;    // largest in-slice radius of a dense kernel (11 wide)
+constexpr int KZDMAX = 21;  // largest z extent of a dense kernel
+enum : int { DM_H = 0, DM_DIRS = 1, DM_HT = 2 };
+template <typename T>
+hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, const T *pk,
+                        const T *in, const T *sub, T *out, const Item *items, int nitems, int mode,
+                        double *partials, hipStream_t st);
+
+// Update pass of the dense mode (the maintained vector is r = Hx - y).
+template <typename T>
+hipError_t launch_dense_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
+                               const int2 *pairs, const double *u, hipStream_t st);
+
 // Per block range: fixed-order reduction of the block's slots, the 2x2
 // majorant system, its pseudo-inverse and the step coefficients u.
 hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int ntiles_g,

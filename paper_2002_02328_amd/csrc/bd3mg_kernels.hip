@@ -1043,6 +1043,193 @@ k_check(const double *__restrict__ partials, int nslot, double thr, int sweep, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// General per-depth kernels (dense PSF).  The kernel of output slice k is a
+// (2 rz + 1) x (2R + 1) x (2R + 1) table P_k[c][b][a] (zero-padded in-slice
+// to the radius R of the kernel instance; pk is [nz][kz][2R+1][2R+1]):
+//   forward  (H x)_k[j][i]   = sum_{c,b,a} P_k[c][b][a]     x_{k-c}[j-b][i-a],
+//   adjoint  (H^T r)_s[j][i] = sum_{c,b,a} P_{s+c}[c][b][a] r_{s+c}[j+b][i+a].
+// A workgroup computes a TX x TYD output tile of one slice: for each source
+// slice in turn, the source tile plus an R halo is staged in LDS (the next
+// source's loads are in flight while the current one is consumed), and each
+// thread slides the 2D stencil over NRD consecutive rows of its column: for
+// each tap column it reads the NRD + 2R values of the column once.
+// ---------------------------------------------------------------------------
+constexpr int TYD = DENSE_TILE_ROWS;  // rows of a dense-kernel tile
+constexpr int NRD = TYD / (NT / TX);   // rows per thread: 8
+
+template <typename T, int R, int NCH, bool ADJ>
+__device__ __forceinline__ void dense_accumulate(const T *L, int ldw, const T *__restrict__ w,
+                                                 T (&acc)[NCH][NRD], int nch_stride)
+{
+    constexpr int K = 2 * R + 1, NV = NRD + 2 * R;
+    const int tx = threadIdx.x & (TX - 1);
+    const int r0 = (int)(threadIdx.x / TX) * NRD;
+    // one tap column at a time (unrolling this loop as well would hold the
+    // columns of several taps in registers)
+#pragma unroll 1
+    for (int a = -R; a <= R; ++a) {
+        // forward: column tx + R - a, rows r0 + e + R - b; adjoint: + a, + b
+        const int col = tx + R + (ADJ ? a : -a);
+        T v[NCH][NV];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int t = 0; t < NV; ++t) v[ch][t] = L[ch * nch_stride + (r0 + t) * ldw + col];
+#pragma unroll
+        for (int b = -R; b <= R; ++b) {
+            const T wv = w[(b + R) * K + (a + R)];
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+                for (int e = 0; e < NRD; ++e) acc[ch][e] += wv * v[ch][e + R + (ADJ ? b : -b)];
+        }
+    }
+}
+
+template <typename T, int R, int NCH, bool ADJ>
+__global__ void __launch_bounds__(NT)
+k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__restrict__ in,
+        const T *__restrict__ sub, T *__restrict__ out, const Item *__restrict__ items, int mode,
+        double *__restrict__ partials)
+{
+    constexpr int K = 2 * R + 1, W = TX + 2 * R, H = TYD + 2 * R;
+    constexpr int LT = padded<W, H>();
+    __shared__ T L[NCH * LT];
+    __shared__ double red[(NT / 64) * NQD];
+    const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
+    const int k = it.k;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYD;
+    const int tx = threadIdx.x & (TX - 1);
+    const int rz = g.rz, kz = 2 * g.rz + 1;
+    const size_t S = (size_t)g.nx * g.ny;
+    const bool dirs = (mode == DM_DIRS);
+    // source slices: forward sl = k - c, adjoint sl = k + c, c in [-rz, rz],
+    // inside the volume, and for the direction pass inside the item's block
+    const int lo = dirs ? it.z0 : 0, hi = dirs ? it.z0 + it.n : g.nz;
+    const int s0 = max(k - rz, lo), s1 = min(k + rz + 1, hi);  // [s0, s1)
+    Region<W, H, R, R> rg(g, x0, y0);
+    T st[NCH][rg.E];
+    auto fetch = [&](int sl) {
+        const T *p0 = dirs ? s.g + (size_t)sl * S : in + (size_t)sl * S;
+        const T *p1 = s.dp[0] + (size_t)sl * S;
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const T v0 = ldo(p0, rg.off[qq]);
+            st[0][qq] = rg.inb[qq] ? (dirs ? -v0 : v0) : T(0);
+            if constexpr (NCH > 1) {
+                const T v1 = ldo(p1, rg.off[qq]);
+                st[1][qq] = rg.inb[qq] ? v1 : T(0);
+            }
+        }
+    };
+    T acc[NCH][NRD];
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+        for (int e = 0; e < NRD; ++e) acc[ch][e] = 0;
+    if (s0 < s1) fetch(s0);
+    for (int sl = s0; sl < s1; ++sl) {
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+            for (int qq = 0; qq < rg.E; ++qq) L[ch * LT + threadIdx.x + qq * NT] = st[ch][qq];
+        __syncthreads();
+        if (sl + 1 < s1) fetch(sl + 1);  // in flight while this slice is consumed
+        // forward: tap c = k - sl of output slice k; adjoint: tap c = sl - k of source slice sl
+        const T *w = ADJ ? pk + ((size_t)sl * kz + (sl - k + rz)) * K * K
+                         : pk + ((size_t)k * kz + (k - sl + rz)) * K * K;
+        dense_accumulate<T, R, NCH, ADJ>(L, W, w, acc, LT);
+        __syncthreads();
+    }
+
+    double qs[NQD];
+#pragma unroll
+    for (int v = 0; v < NQD; ++v) qs[v] = 0.0;
+    const int r0 = (int)(threadIdx.x / TX) * NRD;
+    if (dirs) {
+        T *o1 = s.hd[0] + (size_t)blockIdx.z * S, *o2 = s.hd[1] + (size_t)blockIdx.z * S;
+        const int z0 = it.z0, z1 = it.z0 + it.n;
+        const bool ink = (k >= z0 && k < z1);
+        const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
+#pragma unroll
+        for (int e = 0; e < NRD; ++e) {
+            const int j = y0 + r0 + e, i = x0 + tx;
+            if (i >= g.nx || j >= g.ny) continue;
+            const size_t o = (size_t)j * g.nx + i;
+            o1[o] = acc[0][e];
+            o2[o] = acc[NCH - 1][e];
+            const double a = (double)acc[0][e], b = (double)acc[NCH - 1][e];
+            qs[0] += a * a;
+            qs[1] += a * b;
+            qs[2] += b * b;
+            if (zterm) {
+                // VZ d at slice k: d_{k+1} - d_k with d zero outside S
+                const size_t ov = (size_t)k * S + o;
+                double z1v = 0.0, z2v = 0.0;
+                if (k + 1 >= z0 && k + 1 < z1) {
+                    z1v -= (double)s.g[ov + S];
+                    z2v += (double)s.dp[0][ov + S];
+                }
+                if (ink) {
+                    z1v += (double)s.g[ov];
+                    z2v -= (double)s.dp[0][ov];
+                }
+                qs[3] += z1v * z1v;
+                qs[4] += z1v * z2v;
+                qs[5] += z2v * z2v;
+            }
+        }
+        wg_reduce_store<NQD>(qs, red, partials + slot_of() * NQD);
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < NRD; ++e) {
+        const int j = y0 + r0 + e, i = x0 + tx;
+        if (i >= g.nx || j >= g.ny) continue;
+        const size_t o = (size_t)k * S + (size_t)j * g.nx + i;
+        const T v = sub ? acc[0][e] - sub[o] : acc[0][e];
+        out[o] = v;
+        qs[0] += (double)v * (double)v;
+    }
+    if (partials) {
+        double q1[1] = {qs[0]};
+        wg_reduce_store<1>(q1, red, partials + slot_of());
+    }
+}
+
+// Update pass of the dense mode, where the maintained vector is the residual
+// r = Hx - y itself: per item (slice m),
+//   r_m += sum over the item's pairs (slot, b) of u1_b (H d1)_slot + u2_b (H d2)_slot,
+//   and for m in the item's own block: d' = -u1 g + u2 dp, x += d', dp[1] = d'.
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_dense_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ pairs,
+               const double *__restrict__ u)
+{
+    const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the item, not before it
+    const int m = it.k;
+    const size_t S = (size_t)g.nx * g.ny;
+    const bool ins = (m >= it.z0 && m < it.z0 + it.n);
+    const T u1 = ins ? (T)u[2 * it.block] : T(0), u2 = ins ? (T)u[2 * it.block + 1] : T(0);
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < S; e += (size_t)gridDim.x * NT) {
+        const size_t o = (size_t)m * S + e;
+        T acc = s.q[o];
+        for (int p = 0; p < it.hn; ++p) {
+            const int2 pr = pairs[it.h0 + p];
+            acc += (T)u[2 * pr.y] * s.hd[0][(size_t)pr.x * S + e] + (T)u[2 * pr.y + 1] * s.hd[1][(size_t)pr.x * S + e];
+        }
+        s.q[o] = acc;
+        if (ins) {
+            const T d = u2 * s.dp[0][o] - u1 * s.g[o];
+            s.x[o] += d;
+            s.dp[1][o] = d;
+        }
+    }
+}
+
 // Streaming copy, 16 bytes per lane per iteration, grid-stride.
 __global__ void __launch_bounds__(NT) k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                              size_t n)
@@ -1196,6 +1383,47 @@ hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
     return hipGetLastError();
 }
 
+#define BD3MG_RD_SWITCH(r, CALL)                  \
+    switch (r) {                                  \
+    case 1: { constexpr int R = 1; CALL; } break; \
+    case 2: { constexpr int R = 2; CALL; } break; \
+    case 3: { constexpr int R = 3; CALL; } break; \
+    case 4: { constexpr int R = 4; CALL; } break; \
+    case 5: { constexpr int R = 5; CALL; } break; \
+    default: return hipErrorInvalidValue;         \
+    }
+
+template <typename T>
+hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, const T *pk, const T *in,
+                        const T *sub, T *out, const Item *items, int nitems, int mode, double *partials,
+                        hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems);
+    if (mode == DM_DIRS) {
+        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 2, false>), grid, dim3(NT), 0, st, g, prm, s,
+                                                pk, in, sub, out, items, mode, partials));
+    } else if (mode == DM_HT) {
+        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true>), grid, dim3(NT), 0, st, g, prm, s,
+                                                pk, in, sub, out, items, mode, partials));
+    } else {
+        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, false>), grid, dim3(NT), 0, st, g, prm, s,
+                                                pk, in, sub, out, items, mode, partials));
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dense_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
+                               const int2 *pairs, const double *u, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    const size_t S = (size_t)g.nx * g.ny;
+    const int gx = (int)std::min<size_t>((S + 4 * NT - 1) / (4 * NT), 1024);
+    hipLaunchKernelGGL(k_dense_update<T>, dim3(gx, 1, nitems), dim3(NT), 0, st, g, s, items, pairs, u);
+    return hipGetLastError();
+}
+
 #define BD3MG_INSTANTIATE(T)                                                                      \
     template hipError_t launch_grad<T>(const Geom &, const Params &, const DevState<T> &,          \
                                        const T *, const T *, T *, const Item *, int, int,         \
@@ -1211,6 +1439,15 @@ hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
     template hipError_t launch_blurT<T>(const Geom &, const DevState<T> &, const T *, T *,         \
                                         const Item *, int, hipStream_t);
 
+#define BD3MG_INSTANTIATE_DENSE(T)                                                                \
+    template hipError_t launch_dense<T>(const Geom &, const Params &, const DevState<T> &, const T *,  \
+                                        const T *, const T *, T *, const Item *, int, int, double *,    \
+                                        hipStream_t);                                                   \
+    template hipError_t launch_dense_update<T>(const Geom &, const DevState<T> &, const Item *, int,    \
+                                               const int2 *, const double *, hipStream_t);
+
+BD3MG_INSTANTIATE_DENSE(float)
+BD3MG_INSTANTIATE_DENSE(double)
 BD3MG_INSTANTIATE(float)
 BD3MG_INSTANTIATE(double)
 

@@ -71,3 +71,26 @@ def test_create_rejects_bad_sizes_without_touching_the_device(lib):
     h = C.c_void_p()
     assert lib.bd3mg_create(4, 4, 4, 0, None) == binding.ERR_ARG
     assert lib.bd3mg_destroy(None) == binding.OK
+
+
+def test_rotated_gaussian_matches_oracle_kernels(lib, orc):
+    from paper_2002_02328_amd import binding
+    rng = np.random.default_rng(31)
+    for kxy, kz in [(11, 21), (5, 11), (3, 1), (1, 3)]:
+        nz = 6
+        sx, sy, sz = rng.uniform(0.4, 2.5, nz), rng.uniform(0.4, 2.5, nz), rng.uniform(0.5, 4, nz)
+        th = rng.uniform(0, np.pi, nz)
+        t = binding.psf_rotated_gaussian(sx, sy, th, sz, kxy, kz)
+        o = orc.rotated_gauss_kernels(sx, sy, th, sz, kxy, kz)
+        assert t.shape == o.shape and np.allclose(t, o, rtol=1e-13, atol=1e-300)
+
+
+def test_rotated_gaussian_rejects_bad_arguments(lib):
+    from paper_2002_02328_amd import binding
+    one = np.ones(2)
+    with pytest.raises(binding.Bd3mgError):
+        binding.psf_rotated_gaussian(one, one, one, one, 4, 3)
+    with pytest.raises(binding.Bd3mgError):
+        binding.psf_rotated_gaussian(one, [1.0, 0.0], one, one, 3, 3)
+    with pytest.raises(binding.Bd3mgError):
+        binding.psf_rotated_gaussian(one, one, [0.0, float("inf")], one, 3, 3)
