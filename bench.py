@@ -31,6 +31,8 @@ sys.path.insert(0, ROOT)
 METRIC = "voxel-iterations/s + time-to-f-tolerance (plain vs warm-started), % HBM peak"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (FP64: 78.6)
+FP64_VALU_PEAK_TFLOPS = 78.6
 WEIGHTS = os.path.join(ROOT, "paper_2002_02328_amd", "weights", "warmstart_c16.bin")
 
 
@@ -45,10 +47,18 @@ def net_flops(nvox, c=16):
     return per * nvox
 
 
+def is_dense(w):
+    return "psf" in w.extra
+
+
 def make_problem(binding, w):
     nz, ny, nx = w.shape
     g = binding.Problem(nx, ny, nz, binding.FP64 if w.fp64 else binding.FP32)
-    g.set_psf_gaussian(w.kxy, w.kz, w.sigma_xy, w.sigma_z)
+    if is_dense(w):
+        ps = w.extra["psf"]
+        g.set_psf_dense(binding.psf_rotated_gaussian(ps["sx"], ps["sy"], ps["theta"], ps["sz"], w.kxy, w.kz))
+    else:
+        g.set_psf_gaussian(w.kxy, w.kz, w.sigma_xy, w.sigma_z)
     g.set_params(w.lam, w.delta, w.eta, w.kappa)
     y = g.H(w.xbar) + w.noise.astype(g.dtype)  # degradation model y = H xbar + b
     g.set_data(y.astype(g.dtype))
@@ -56,10 +66,33 @@ def make_problem(binding, w):
     return g
 
 
+def dense_flops(w, ncolors, color):
+    """Arithmetic of the general-kernel passes per sweep (one multiply and one
+    add per kernel tap and output voxel, taps of the (2R+1)^2 in-slice
+    planes): the gradient pass applies H^T on every block slice from the
+    volume's slices within r_z, the direction pass H to d1 and d2 on S +- r_z
+    of every block from the block's own slices within r_z."""
+    nz, ny, nx = w.shape
+    rz, R = w.kz // 2, max(w.kxy // 2, 1)
+    tap = 2.0 * (2 * R + 1) ** 2 * nx * ny
+    z0 = np.concatenate([[0], np.cumsum(w.nslices)[:-1]])
+    grad = dirs = 0.0
+    for b, n in enumerate(w.nslices):
+        s0, s1 = int(z0[b]), int(z0[b] + n)
+        for s in range(s0, s1):
+            grad += (min(nz, s + rz + 1) - max(0, s - rz)) * tap
+        for k in range(max(0, s0 - max(rz, 1 if w.kappa > 0 else 0)), min(nz, s1 + rz)):
+            dirs += 2 * max(0, min(s1, k + rz + 1) - max(s0, k - rz)) * tap
+    return {"grad": grad, "dirs": dirs}
+
+
 def kernel_variant(w, kernel, tile_rows):
     """Name of the sweep kernel instance a pass runs, as the profiler prints it."""
     t = "double" if w.fp64 else "float"
     kz, r = w.kz, max(w.kxy // 2, 1)
+    if is_dense(w):
+        return {"grad": "k_dense<%s, %d, 1, true>" % (t, r), "dirs": "k_dense<%s, %d, 2, false>" % (t, r),
+                "solve": "k_solve", "update": "k_dense_update<%s>" % t}[kernel]
     return {"grad": "k_grad<%s, %d>" % (t, kz),
             "dirs": "k_dirs<%s, %d, %d, %d>" % (t, kz, r, tile_rows["dirs"]),
             "solve": "k_solve",
@@ -88,10 +121,16 @@ def measured_traffic(workload, variant):
 def cpu_baseline(w, budget_s):
     """FP64 oracle on the same workload: as many whole sweeps as fit the budget."""
     import oracle
-    gxy = oracle.gauss_table(w.sigma_xy, w.kxy)
-    gz = oracle.gauss_table(w.sigma_z, w.kz)
-    y = oracle.Problem(np.zeros(w.shape), gxy, gxy, gz).H(w.xbar) + w.noise
-    o = oracle.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
+    if is_dense(w):
+        ps = w.extra["psf"]
+        pk = oracle.rotated_gauss_kernels(ps["sx"], ps["sy"], ps["theta"], ps["sz"], w.kxy, w.kz)
+        y = oracle.Problem.with_kernels(np.zeros(w.shape), pk).H(w.xbar) + w.noise
+        o = oracle.Problem.with_kernels(y, pk, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
+    else:
+        gxy = oracle.gauss_table(w.sigma_xy, w.kxy)
+        gz = oracle.gauss_table(w.sigma_z, w.kz)
+        y = oracle.Problem(np.zeros(w.shape), gxy, gxy, gz).H(w.xbar) + w.noise
+        o = oracle.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
     nc, order, _ = oracle.color_schedule(w.nslices, 2 * (w.kz // 2))
     x = y.copy()
     d = np.zeros(w.shape)
@@ -148,7 +187,7 @@ def round_schedule(binding, w, args):
                     "converged": bool(res["converged"]), "grad_rel": res["grad_norm"] / res["grad_norm_ref"],
                     "f": res["f"], "tol": args.tol}
         tt = {"plain_x0_y": to_tol(None), "warm_started": None}
-        if os.path.exists(WEIGHTS):
+        if os.path.exists(WEIGHTS) and not is_dense(w):
             net = binding.Net()
             net.load(open(WEIGHTS, "rb").read())
             net.infer(r)
@@ -207,6 +246,20 @@ def main():
     variant = kernel_variant(w, dom, {"dirs": td, "update": tu})
     n, ms, by = hot[dom]
     achieved = by / (ms * 1e-3) / 1e9
+    if is_dense(w):
+        # the general-kernel passes are bound by vector arithmetic
+        fl = dense_flops(w, nc, color)
+        peak = FP64_VALU_PEAK_TFLOPS if w.fp64 else FP32_VALU_PEAK_TFLOPS
+        tf = fl[dom] / (ms * 1e-3 / args.steps) / 1e12 if dom in fl else 0.0
+        roof = {"bound": "alu", "kernel": dom, "variant": variant, "achieved": tf, "peak": peak,
+                "unit": "TFLOP/s", "frac": tf / peak, "traffic": measured_traffic(w.name, variant),
+                "avg_launch_us": 1e3 * ms / n, "flop_per_launch": fl.get(dom, 0.0) * args.steps / n,
+                "flop_per_sweep": fl}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "variant": variant, "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(w.name, variant),
+                "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n}
     kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
                    "GB/s": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
                for k, v in prof.items() if v[0] > 0}
@@ -228,14 +281,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if w.fp64 else "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "shape_zyx": list(w.shape), "psf": "%dx%dx%d" % (w.kxy, w.kxy, w.kz),
+        "config": {"workload": w.name, "shape_zyx": list(w.shape),
+                   "psf": ("rotated %dx%dx%d" if is_dense(w) else "%dx%dx%d") % (w.kxy, w.kxy, w.kz),
                    "blocks": int(len(w.nslices)), "colors": int(nc),
                    "reductions": "f64", "step": "one sweep (every block updated once)",
                    "tile_rows": {"dirs": td, "update": tu}},
-        "roofline": {"bound": "hbm", "kernel": dom, "variant": variant, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(w.name, variant),
-                     "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n},
+        "roofline": roof,
         "kernels": kernels,
         "sweep_algorithmic_GBps": all_bytes / (total_ms * 1e-3) / 1e9,
         "copy_probe_GBps": probe_gbs,
@@ -243,7 +294,7 @@ def main():
 
     if not args.no_tol:
         net = None
-        if os.path.exists(WEIGHTS):
+        if os.path.exists(WEIGHTS) and not is_dense(w):  # trained on the separable-blur volumes
             net = binding.Net()
             net.load(open(WEIGHTS, "rb").read())
             net.infer(g)  # sizes the network's buffers for this volume (untimed)

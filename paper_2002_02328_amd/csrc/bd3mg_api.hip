@@ -56,6 +56,8 @@ struct bd3mg_problem_s {
     bool dense = false;
     void *d_pk = nullptr;    // [nz][kz][2R+1][2R+1], storage type
     void *d_ones = nullptr;  // [nz] ones: the z table of the gradient pass in the dense mode
+    void *d_hts = nullptr;   // source shares of H^T r of a launch group (dense mode)
+    size_t hts_alloc = 0;
     std::vector<double> hpk;  // [nz][kz][ky][kx] as given
 
     // volumes (storage type); q is the in-slice adjoint-blurred residual
@@ -149,13 +151,23 @@ DevState<T> dev_state(bd3mg_problem p)
 // the general-kernel adjoint, then the gradient kernel with a one-tap z table
 // reading it (the rest of grad f and the partial sums as in the separable
 // mode).
+// Source shares of the adjoint for n output slices: enough workgroups to
+// fill the GPU when a group has few slices (at least two sources a share).
+int dense_split(bd3mg_problem p, int n)
+{
+    const int wgs = n * tiles_of(p->geom, DENSE_TILE_ROWS);
+    const int ns = (1024 + wgs - 1) / std::max(wgs, 1);
+    return std::max(1, std::min(ns, (p->kz + 1) / 2));
+}
+
 template <typename T>
 hipError_t dense_grad(bd3mg_problem p, const DevState<T> &s, const T *r, const T *x, T *out,
-                      const Item *items, int n, int mode, double *partials)
+                      const Item *items, int n, int mode, double *partials, bool split = false)
 {
     T *ht = (T *)p->tmp[3];
+    const int ns = split ? dense_split(p, n) : 1;
     hipError_t e = launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, r, nullptr, ht, items, n, DM_HT,
-                                   nullptr, p->stream);
+                                   nullptr, p->stream, ns, (T *)p->d_hts);
     if (e != hipSuccess) return e;
     Geom g1 = p->geom;
     g1.rz = 0;
@@ -458,7 +470,12 @@ bd3mg_status build_schedule(bd3mg_problem p)
     ST_TRY(realloc_dev(&p->d_hd, &p->hd_alloc, 2 * (size_t)maxd * p->nx * p->ny * p->esz,
                        "stored directions H d1, H d2"));
     p->hd_slots = (size_t)maxd;
-    if (p->dense) ST_TRY(ensure_tmp(p, 4));  // H^T r of the gradient pass
+    if (p->dense) {
+        ST_TRY(ensure_tmp(p, 4));  // H^T r of the gradient pass
+        size_t sl = 1;
+        for (auto &grp : p->groups) sl = std::max(sl, (size_t)dense_split(p, grp.g_cnt) * grp.g_cnt);
+        ST_TRY(realloc_dev(&p->d_hts, &p->hts_alloc, sl * p->nx * p->ny * p->esz, "adjoint source shares"));
+    }
     HIP_TRY(hipStreamSynchronize(p->stream));
     p->sched_dirty = false;
     return BD3MG_OK;
@@ -590,7 +607,7 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
         // general kernels: H^T r and grad f on S, H d1 and H d2 on S +- r_z by
         // the dense kernels, r += u1 H d1 + u2 H d2 elementwise
         if (prof) ST_TRY(prof_begin(p, BD3MG_K_GRAD, gr.bytes[0]));
-        HIP_TRY(dense_grad<T>(p, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK, p->d_pg));
+        HIP_TRY(dense_grad<T>(p, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK, p->d_pg, true));
         if (prof) ST_TRY(prof_end(p));
         if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
         HIP_TRY(launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, nullptr, nullptr, nullptr, it + gr.d_off,
@@ -771,7 +788,7 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
     if (!p) return BD3MG_OK;
     if (p->stream) (void)hipStreamSynchronize(p->stream);
     void *bufs[] = {p->x, p->y, p->q, p->g, p->dpb[0], p->dpb[1], p->tmp[0], p->tmp[1], p->tmp[2], p->tmp[3],
-                    p->d_pk, p->d_ones,
+                    p->d_pk, p->d_ones, p->d_hts,
                     p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_sblk, p->d_pg, p->d_pd,
                     p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_pairs, p->d_hd,
                     p->d_units};

@@ -1091,13 +1091,18 @@ template <typename T, int R, int NCH, bool ADJ>
 __global__ void __launch_bounds__(NT)
 k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__restrict__ in,
         const T *__restrict__ sub, T *__restrict__ out, const Item *__restrict__ items, int mode,
-        double *__restrict__ partials)
+        double *__restrict__ partials, int nsplit)
 {
     constexpr int K = 2 * R + 1, W = TX + 2 * R, H = TYD + 2 * R;
     constexpr int LT = padded<W, H>();
     __shared__ T L[NCH * LT];
     __shared__ double red[(NT / 64) * NQD];
-    const Item it = items[blockIdx.z];
+    // nsplit > 1 (adjoint only): workgroup z = item nsplit + part, each part
+    // a contiguous share of the item's source slices, written to the plane
+    // out + part (number of items) S + item S for a fixed-order sum later
+    const int ii = nsplit > 1 ? (int)blockIdx.z / nsplit : (int)blockIdx.z;
+    const int part = nsplit > 1 ? (int)blockIdx.z - ii * nsplit : 0;
+    const Item it = items[ii];
     if (s.stop && *s.stop) return;  // read with the item, not before it
     const int k = it.k;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYD;
@@ -1108,7 +1113,9 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
     // source slices: forward sl = k - c, adjoint sl = k + c, c in [-rz, rz],
     // inside the volume, and for the direction pass inside the item's block
     const int lo = dirs ? it.z0 : 0, hi = dirs ? it.z0 + it.n : g.nz;
-    const int s0 = max(k - rz, lo), s1 = min(k + rz + 1, hi);  // [s0, s1)
+    const int a0 = max(k - rz, lo), a1 = min(k + rz + 1, hi);
+    const int len = max(a1 - a0, 0);
+    const int s0 = a0 + (len * part) / nsplit, s1 = a0 + (len * (part + 1)) / nsplit;  // [s0, s1)
     Region<W, H, R, R> rg(g, x0, y0);
     T st[NCH][rg.E];
     auto fetch = [&](int sl) {
@@ -1184,18 +1191,36 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
         wg_reduce_store<NQD>(qs, red, partials + slot_of() * NQD);
         return;
     }
+    const size_t base = nsplit > 1 ? ((size_t)part * (gridDim.z / nsplit) + ii) * S : (size_t)k * S;
 #pragma unroll
     for (int e = 0; e < NRD; ++e) {
         const int j = y0 + r0 + e, i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
-        const size_t o = (size_t)k * S + (size_t)j * g.nx + i;
-        const T v = sub ? acc[0][e] - sub[o] : acc[0][e];
-        out[o] = v;
+        const size_t o = (size_t)j * g.nx + i;
+        const T v = sub ? acc[0][e] - sub[(size_t)k * S + o] : acc[0][e];
+        out[base + o] = v;
         qs[0] += (double)v * (double)v;
     }
     if (partials) {
         double q1[1] = {qs[0]};
         wg_reduce_store<1>(q1, red, partials + slot_of());
+    }
+}
+
+// out_k = sum over parts p (in order) of part[p][item], per item (slice k):
+// the adjoint's source shares added in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_dense_sum(Geom g, DevState<T> s, const T *__restrict__ part, T *__restrict__ out, const Item *__restrict__ items,
+            int nitems, int nsplit)
+{
+    const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;
+    const size_t S = (size_t)g.nx * g.ny;
+    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < S; e += (size_t)gridDim.x * NT) {
+        T acc = part[(size_t)blockIdx.z * S + e];
+        for (int p = 1; p < nsplit; ++p) acc += part[((size_t)p * nitems + blockIdx.z) * S + e];
+        out[(size_t)it.k * S + e] = acc;
     }
 }
 
@@ -1396,19 +1421,33 @@ hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
 template <typename T>
 hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, const T *pk, const T *in,
                         const T *sub, T *out, const Item *items, int nitems, int mode, double *partials,
-                        hipStream_t st)
+                        hipStream_t st, int nsplit, T *part)
 {
     if (nitems <= 0) return hipSuccess;
+    if (nsplit > 1) {
+        // adjoint over source shares into part, then their fixed-order sum
+        if (mode != DM_HT || !part) return hipErrorInvalidValue;
+        const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems * nsplit);
+        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true>), grid, dim3(NT), 0, st, g, prm, s,
+                                                pk, in, sub, part, items, mode, nullptr, nsplit));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const size_t S = (size_t)g.nx * g.ny;
+        const int gx = (int)std::min<size_t>((S + 4 * NT - 1) / (4 * NT), 1024);
+        hipLaunchKernelGGL(k_dense_sum<T>, dim3(gx, 1, nitems), dim3(NT), 0, st, g, s, (const T *)part, out, items,
+                           nitems, nsplit);
+        return hipGetLastError();
+    }
     const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems);
     if (mode == DM_DIRS) {
         BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 2, false>), grid, dim3(NT), 0, st, g, prm, s,
-                                                pk, in, sub, out, items, mode, partials));
+                                                pk, in, sub, out, items, mode, partials, 1));
     } else if (mode == DM_HT) {
         BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true>), grid, dim3(NT), 0, st, g, prm, s,
-                                                pk, in, sub, out, items, mode, partials));
+                                                pk, in, sub, out, items, mode, partials, 1));
     } else {
         BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, false>), grid, dim3(NT), 0, st, g, prm, s,
-                                                pk, in, sub, out, items, mode, partials));
+                                                pk, in, sub, out, items, mode, partials, 1));
     }
     return hipGetLastError();
 }
@@ -1442,7 +1481,7 @@ hipError_t launch_dense_update(const Geom &g, const DevState<T> &s, const Item *
 #define BD3MG_INSTANTIATE_DENSE(T)                                                                \
     template hipError_t launch_dense<T>(const Geom &, const Params &, const DevState<T> &, const T *,  \
                                         const T *, const T *, T *, const Item *, int, int, double *,    \
-                                        hipStream_t);                                                   \
+                                        hipStream_t, int, T *);                                         \
     template hipError_t launch_dense_update<T>(const Geom &, const DevState<T> &, const Item *, int,    \
                                                const int2 *, const double *, hipStream_t);
 
