@@ -164,8 +164,9 @@ template <typename T>
 hipError_t dense_grad(bd3mg_problem p, const DevState<T> &s, const T *r, const T *x, T *out,
                       const Item *items, int n, int mode, double *partials, bool split = false)
 {
-    T *ht = (T *)p->tmp[3];
     const int ns = split ? dense_split(p, n) : 1;
+    // shares of H^T r stay in d_hts and the gradient kernel adds them
+    T *ht = ns > 1 ? nullptr : (T *)p->tmp[3];
     hipError_t e = launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, r, nullptr, ht, items, n, DM_HT,
                                    nullptr, p->stream, ns, (T *)p->d_hts);
     if (e != hipSuccess) return e;
@@ -173,7 +174,8 @@ hipError_t dense_grad(bd3mg_problem p, const DevState<T> &s, const T *r, const T
     g1.rz = 0;
     DevState<T> s1 = s;
     s1.gz = (const T *)p->d_ones;
-    return launch_grad<T>(g1, p->prm, s1, ht, x, out, items, n, mode, partials, p->stream);
+    return launch_grad<T>(g1, p->prm, s1, ns > 1 ? (const T *)p->d_hts : ht, x, out, items, n, mode, partials,
+                          p->stream, ns > 1 ? ns : 0);
 }
 
 bd3mg_status check_finite(const double *v, size_t n, const char *what)

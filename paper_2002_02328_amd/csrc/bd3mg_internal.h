@@ -113,10 +113,12 @@ enum GradMode : int {
     GM_GRAD = 3    // out = grad f
 };
 
+// nshare > 0 (one-tap z table only): q holds nshare shares of the data term
+// per item, [share][item][ny][nx], added in order.
 template <typename T>
 hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *q,
                        const T *x, T *out, const Item *items, int nitems, int mode,
-                       double *partials, hipStream_t st);
+                       double *partials, hipStream_t st, int nshare = 0);
 
 // Direction pass over nunits units (first item, 1 or 2 consecutive slices of
 // a block); stores H d1, H d2 of item i at slot i of s.hd.
@@ -159,7 +161,8 @@ constexpr int KZDMAX = 21;  // largest z extent of a dense kernel
 enum : int { DM_H = 0, DM_DIRS = 1, DM_HT = 2 };
 // nsplit > 1 (DM_HT only): the source slices of every item are shared out
 // over nsplit workgroups writing to part ([nsplit][nitems] slices), then
-// summed in order into out (more workgroups when there are few items).
+// summed in order into out, or left as shares when out is null (more
+// workgroups when there are few items).
 template <typename T>
 hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, const T *pk,
                         const T *in, const T *sub, T *out, const Item *items, int nitems, int mode,

@@ -243,7 +243,8 @@ __device__ __forceinline__ size_t slot_of()
 template <typename T, int KZ>
 __global__ void __launch_bounds__(NT)
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
-       T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials)
+       T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
+       int nshare)
 {
     constexpr int RZ = KZ / 2;
     constexpr int XW = TX + 3, XH = TY + 3;  // x at (y0-1+jj, x0-1+ii)
@@ -286,14 +287,24 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
             dv[qq] = rg.inb[qq] ? v : T(0);
         }
     }
+    if (KZ == 1 && nshare > 0) {
+        // the data term is given as nshare shares per item (the general-kernel
+        // adjoint split over workgroups), q = [share][item][ny][nx]: added in order
+        for (int p = 0; p < nshare; ++p) {
+            const T *qp = q + ((size_t)p * gridDim.z + blockIdx.z) * S;
 #pragma unroll
-    for (int c = -RZ; c <= RZ; ++c) {
-        const int m = k + c;
-        if (m < 0 || m >= g.nz) continue;
-        const T w = s.gz[(size_t)m * KZ + (c + RZ)];
-        const T *qm = q + (size_t)m * S;
+            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += ldo(qp, rg.off[qq]);
+        }
+    } else {
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldo(qm, rg.off[qq]);
+        for (int c = -RZ; c <= RZ; ++c) {
+            const int m = k + c;
+            if (m < 0 || m >= g.nz) continue;
+            const T w = s.gz[(size_t)m * KZ + (c + RZ)];
+            const T *qm = q + (size_t)m * S;
+#pragma unroll
+            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldo(qm, rg.off[qq]);
+        }
     }
     if (mode == GM_ZCOMB) {
 #pragma unroll
@@ -1307,12 +1318,14 @@ static dim3 grid_of(const Geom &g, int nitems, int ty = TY)
 
 template <typename T>
 hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, const T *q, const T *x,
-                       T *out, const Item *items, int nitems, int mode, double *partials, hipStream_t st)
+                       T *out, const Item *items, int nitems, int mode, double *partials, hipStream_t st,
+                       int nshare)
 {
     if (nitems <= 0) return hipSuccess;
+    if (nshare > 0 && g.rz != 0) return hipErrorInvalidValue;
     BD3MG_KZ_SWITCH(2 * g.rz + 1,
                     hipLaunchKernelGGL((k_grad<T, KZ>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
-                                       s, q, x, out, items, mode, partials));
+                                       s, q, x, out, items, mode, partials, nshare));
     return hipGetLastError();
 }
 
@@ -1431,7 +1444,7 @@ hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, 
         BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true>), grid, dim3(NT), 0, st, g, prm, s,
                                                 pk, in, sub, part, items, mode, nullptr, nsplit));
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        if (e != hipSuccess || !out) return e;  // no out: the shares are the result
         const size_t S = (size_t)g.nx * g.ny;
         const int gx = (int)std::min<size_t>((S + 4 * NT - 1) / (4 * NT), 1024);
         hipLaunchKernelGGL(k_dense_sum<T>, dim3(gx, 1, nitems), dim3(NT), 0, st, g, s, (const T *)part, out, items,
@@ -1466,7 +1479,7 @@ hipError_t launch_dense_update(const Geom &g, const DevState<T> &s, const Item *
 #define BD3MG_INSTANTIATE(T)                                                                      \
     template hipError_t launch_grad<T>(const Geom &, const Params &, const DevState<T> &,          \
                                        const T *, const T *, T *, const Item *, int, int,         \
-                                       double *, hipStream_t);                                    \
+                                       double *, hipStream_t, int);                               \
     template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
                                        const Item *, const int2 *, int, double *, hipStream_t);   \
     template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Item *, int,      \

@@ -39,7 +39,8 @@ MUTATIONS = {
                                   "            block_direction(p, x, dprev, z0, nslices[b], dn, NULL);\n"
                                   "            for (size_t q = (size_t)z0 * nslice(p); q < (size_t)(z0 + nslices[b]) * nslice(p); ++q)"
                                   " { x[q] += dn[q]; dprev[q] = dn[q]; dn[q] = 0.0; }\n"),
-    "lipschitz-tv-term": ("8.0 * p->lambda / p->delta", "p->lambda / p->delta"),
+    "lipschitz-tv-term": ("return hh + 2.0 * p->eta + 8.0 * p->lambda / p->delta",
+                          "return hh + 2.0 * p->eta + p->lambda / p->delta"),
     "dense-kernel-of-input-slice": ("double w = psf_w(p, k, c, b, a);", "double w = psf_w(p, kk, c, b, a);"),
     "dense-adjoint-kernel-of-output-slice": ("double w = psf_w(p, kk, c, b, a);", "double w = psf_w(p, k, c, b, a);"),
     "dense-tap-flipped-in-z": ("p->pk[(((size_t)k * p->kz + (c + rz)) * p->ky",
