@@ -166,3 +166,50 @@ def test_full_size_rotated_workload_one_sweep_against_oracle(orc):
     x, d = y.copy(), np.zeros(y.shape)
     o.run(x, d, w.nslices, order, 1, history=False)
     assert rel(g.get_x(), x) <= 1e-5
+
+
+def test_set_psf_dense_rejects_bad_kernels(orc):
+    g = binding.Problem(20, 16, 6, binding.FP32)
+    ok = np.full((6, 3, 3, 3), 1.0 / 27)
+    g.set_psf_dense(ok)
+    for bad in (np.ones((6, 3, 4, 3)), np.ones((6, 3, 3, 13)), np.ones((6, 23, 3, 3)), np.ones((6, 2, 3, 3))):
+        with pytest.raises(binding.Bd3mgError) as e:
+            g.set_psf_dense(bad)
+        assert e.value.status == binding.ERR_ARG
+    nan = ok.copy()
+    nan[2, 1, 1, 1] = np.nan
+    with pytest.raises(binding.Bd3mgError):
+        g.set_psf_dense(nan)
+    with pytest.raises(ValueError):
+        g.set_psf_dense(np.ones((5, 3, 3, 3)))
+    g.close()
+
+
+def test_switching_between_separable_and_general_psf(orc):
+    """A separable PSF given as general kernels (tensor products) and as
+    factors gives the same trajectory, and switching back and forth works."""
+    shape, nslices = (8, 30, 70), [3, 2, 3]
+    nz, ny, nx = shape
+    rng = np.random.default_rng(40)
+    gx, gy, gz = (oracle.gauss_table(rng.uniform(0.6, 1.8, nz), k) for k in (5, 5, 3))
+    pk = np.einsum("kc,kb,ka->kcba", gz, gy, gx)
+    w = inputs.tiny(shape, 41)
+    y = oracle.Problem(np.zeros(shape), gx, gy, gz).H(w.xbar) + w.noise
+    g = binding.Problem(nx, ny, nz, binding.FP64)
+    g.set_params(0.01, 0.05, 0.01)
+    g.set_data(y)
+    g.set_psf_separable(gx, gy, gz)
+    g.set_blocks(nslices)
+    g.set_x0(None)
+    g.run(5)
+    xs = g.get_x()
+    g.set_psf_dense(pk)
+    g.set_x0(None)
+    g.run(5)
+    xd = g.get_x()
+    assert rel(xd, xs) <= 1e-12
+    g.set_psf_separable(gx, gy, gz)
+    g.set_x0(None)
+    g.run(5)
+    assert np.array_equal(g.get_x(), xs)
+    g.close()
