@@ -96,7 +96,7 @@ def kernel_variant(w, kernel, tile_rows):
     return {"grad": "k_grad<%s, %d>" % (t, kz),
             "dirs": "k_dirs<%s, %d, %d, %d>" % (t, kz, r, tile_rows["dirs"]),
             "solve": "k_solve",
-            "update": "k_update<%s, %d, %d>" % (t, r, tile_rows["update"])}[kernel]
+            "update": "k_update<%s, %d, %d, false>" % (t, r, tile_rows["update"])}[kernel]
 
 
 def measured_traffic(workload, variant):
