@@ -153,9 +153,9 @@ DevState<T> dev_state(bd3mg_problem p)
 // mode).
 // Source shares of the adjoint for n output slices: enough workgroups to
 // fill the GPU when a group has few slices (at least two sources a share).
-int dense_split(bd3mg_problem p, int n)
+int dense_split(bd3mg_problem p, int n, int ty)
 {
-    const int wgs = n * tiles_of(p->geom, DENSE_TILE_ROWS);
+    const int wgs = n * tiles_of(p->geom, ty);
     const int ns = (1024 + wgs - 1) / std::max(wgs, 1);
     return std::max(1, std::min(ns, (p->kz + 1) / 2));
 }
@@ -164,7 +164,7 @@ template <typename T>
 hipError_t dense_grad(bd3mg_problem p, const DevState<T> &s, const T *r, const T *x, T *out,
                       const Item *items, int n, int mode, double *partials, bool split = false)
 {
-    const int ns = split ? dense_split(p, n) : 1;
+    const int ns = split ? dense_split(p, n, p->geom.ty_dirs) : 1;
     // shares of H^T r stay in d_hts and the gradient kernel adds them
     T *ht = ns > 1 ? nullptr : (T *)p->tmp[3];
     hipError_t e = launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, r, nullptr, ht, items, n, DM_HT,
@@ -475,7 +475,9 @@ bd3mg_status build_schedule(bd3mg_problem p)
     if (p->dense) {
         ST_TRY(ensure_tmp(p, 4));  // H^T r of the gradient pass
         size_t sl = 1;
-        for (auto &grp : p->groups) sl = std::max(sl, (size_t)dense_split(p, grp.g_cnt) * grp.g_cnt);
+        // for either tile height (the autotuner may change it after this)
+        for (auto &grp : p->groups)
+            for (int ty : {16, 32}) sl = std::max(sl, (size_t)dense_split(p, grp.g_cnt, ty) * grp.g_cnt);
         ST_TRY(realloc_dev(&p->d_hts, &p->hts_alloc, sl * p->nx * p->ny * p->esz, "adjoint source shares"));
     }
     HIP_TRY(hipStreamSynchronize(p->stream));
@@ -548,7 +550,7 @@ bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, doub
         if (p->dense) {
             HIP_TRY(launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, xin, (const T *)p->y, (T *)p->tmp[0],
                                     p->d_vol, p->nz, DM_H, p->d_pr, p->stream));
-            HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, DENSE_TILE_ROWS) * p->nz, 1, p->d_sum + NQE,
+            HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, p->geom.ty_dirs) * p->nz, 1, p->d_sum + NQE,
                                p->stream));
         } else {
             HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, (T *)p->tmp[0], p->d_vol, p->nz, p->d_pr,
@@ -617,7 +619,7 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
         if (prof) ST_TRY(prof_end(p));
         if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
         HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,
-                             tiles_of(p->geom, DENSE_TILE_ROWS), p->d_pg, p->d_pd, p->d_u, p->d_info, stop,
+                             tiles_of(p->geom, p->geom.ty_dirs), p->d_pg, p->d_pd, p->d_u, p->d_info, stop,
                              p->stream));
         if (prof) ST_TRY(prof_end(p));
         if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
@@ -1262,11 +1264,12 @@ bd3mg_status bd3mg_autotune(bd3mg_problem p, int sweeps, int *chosen, double *ms
     p->profile = false;
     std::vector<int> cand = {16};
     if (p->prec == BD3MG_FP32) cand.push_back(32);
-    if (p->dense) cand = {p->geom.ty_dirs};  // the dense kernels have one tile shape
+    std::vector<int> cand_u = cand;
+    if (p->dense) cand_u = {p->geom.ty_update};  // the general-kernel passes use the direction tile only
     double best = -1.0;
     int bd = p->geom.ty_dirs, bu = p->geom.ty_update;
     for (int td : cand)
-        for (int tu : cand) {
+        for (int tu : cand_u) {
             p->geom.ty_dirs = td;
             p->geom.ty_update = tu;
             bd3mg_result r;

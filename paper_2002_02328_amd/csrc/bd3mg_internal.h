@@ -154,8 +154,7 @@ hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out
 // DM_DIRS H d1, H d2 of the items' blocks (d1 = -g, d2 = dp) -> s.hd at the
 //         item's slot, partials NQD per (item, tile);
 // DM_HT   out = H^T in.
-// Tiles are TX x DENSE_TILE_ROWS.
-constexpr int DENSE_TILE_ROWS = 32;
+// Tiles are TX x g.ty_dirs (16 or 32 rows).
 constexpr int RDMAX = 5;    // largest in-slice radius of a dense kernel (11 wide)
 constexpr int KZDMAX = 21;  // largest z extent of a dense kernel
 enum : int { DM_H = 0, DM_DIRS = 1, DM_HT = 2 };

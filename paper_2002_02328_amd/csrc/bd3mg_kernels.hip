@@ -1060,16 +1060,15 @@ k_check(const double *__restrict__ partials, int nslot, double thr, int sweep, i
 // to the radius R of the kernel instance; pk is [nz][kz][2R+1][2R+1]):
 //   forward  (H x)_k[j][i]   = sum_{c,b,a} P_k[c][b][a]     x_{k-c}[j-b][i-a],
 //   adjoint  (H^T r)_s[j][i] = sum_{c,b,a} P_{s+c}[c][b][a] r_{s+c}[j+b][i+a].
-// A workgroup computes a TX x TYD output tile of one slice: for each source
+// A workgroup computes a TX x TYD output tile of one slice (TYD = 16 or 32,
+// the direction-pass tile height of the problem): for each source
 // slice in turn, the source tile plus an R halo is staged in LDS (the next
 // source's loads are in flight while the current one is consumed), and each
 // thread slides the 2D stencil over NRD consecutive rows of its column: for
 // each tap column it reads the NRD + 2R values of the column once.
 // ---------------------------------------------------------------------------
-constexpr int TYD = DENSE_TILE_ROWS;  // rows of a dense-kernel tile
-constexpr int NRD = TYD / (NT / TX);   // rows per thread: 8
 
-template <typename T, int R, int NCH, bool ADJ>
+template <typename T, int R, int NCH, bool ADJ, int NRD>
 __device__ __forceinline__ void dense_accumulate(const T *L, int ldw, const T *__restrict__ w,
                                                  T (&acc)[NCH][NRD], int nch_stride)
 {
@@ -1098,12 +1097,13 @@ __device__ __forceinline__ void dense_accumulate(const T *L, int ldw, const T *_
     }
 }
 
-template <typename T, int R, int NCH, bool ADJ>
+template <typename T, int R, int NCH, bool ADJ, int TYD>
 __global__ void __launch_bounds__(NT)
 k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__restrict__ in,
         const T *__restrict__ sub, T *__restrict__ out, const Item *__restrict__ items, int mode,
         double *__restrict__ partials, int nsplit)
 {
+    constexpr int NRD = TYD / (NT / TX);  // rows per thread
     constexpr int K = 2 * R + 1, W = TX + 2 * R, H = TYD + 2 * R;
     constexpr int LT = padded<W, H>();
     __shared__ T L[NCH * LT];
@@ -1158,7 +1158,7 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
         // forward: tap c = k - sl of output slice k; adjoint: tap c = sl - k of source slice sl
         const T *w = ADJ ? pk + ((size_t)sl * kz + (sl - k + rz)) * K * K
                          : pk + ((size_t)k * kz + (k - sl + rz)) * K * K;
-        dense_accumulate<T, R, NCH, ADJ>(L, W, w, acc, LT);
+        dense_accumulate<T, R, NCH, ADJ, NRD>(L, W, w, acc, LT);
         __syncthreads();
     }
 
@@ -1437,12 +1437,17 @@ hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, 
                         hipStream_t st, int nsplit, T *part)
 {
     if (nitems <= 0) return hipSuccess;
+    if (g.ty_dirs != 16 && g.ty_dirs != 32) return hipErrorInvalidValue;
+#define BD3MG_DENSE_TY(CALL)                             \
+    if (g.ty_dirs == 16) { constexpr int TYD = 16; CALL; } \
+    else { constexpr int TYD = 32; CALL; }
     if (nsplit > 1) {
         // adjoint over source shares into part, then their fixed-order sum
         if (mode != DM_HT || !part) return hipErrorInvalidValue;
-        const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems * nsplit);
-        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true>), grid, dim3(NT), 0, st, g, prm, s,
-                                                pk, in, sub, part, items, mode, nullptr, nsplit));
+        BD3MG_DENSE_TY(
+            const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems * nsplit);
+            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true, TYD>), grid, dim3(NT), 0, st, g,
+                                                    prm, s, pk, in, sub, part, items, mode, nullptr, nsplit)));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess || !out) return e;  // no out: the shares are the result
         const size_t S = (size_t)g.nx * g.ny;
@@ -1451,17 +1456,19 @@ hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, 
                            nitems, nsplit);
         return hipGetLastError();
     }
-    const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems);
-    if (mode == DM_DIRS) {
-        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 2, false>), grid, dim3(NT), 0, st, g, prm, s,
-                                                pk, in, sub, out, items, mode, partials, 1));
-    } else if (mode == DM_HT) {
-        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true>), grid, dim3(NT), 0, st, g, prm, s,
-                                                pk, in, sub, out, items, mode, partials, 1));
-    } else {
-        BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, false>), grid, dim3(NT), 0, st, g, prm, s,
-                                                pk, in, sub, out, items, mode, partials, 1));
-    }
+    BD3MG_DENSE_TY(
+        const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems);
+        if (mode == DM_DIRS) {
+            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 2, false, TYD>), grid, dim3(NT), 0, st, g,
+                                                    prm, s, pk, in, sub, out, items, mode, partials, 1));
+        } else if (mode == DM_HT) {
+            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true, TYD>), grid, dim3(NT), 0, st, g,
+                                                    prm, s, pk, in, sub, out, items, mode, partials, 1));
+        } else {
+            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, false, TYD>), grid, dim3(NT), 0, st, g,
+                                                    prm, s, pk, in, sub, out, items, mode, partials, 1));
+        })
+#undef BD3MG_DENSE_TY
     return hipGetLastError();
 }
 
