@@ -91,7 +91,8 @@ def kernel_variant(w, kernel, tile_rows):
     t = "double" if w.fp64 else "float"
     kz, r = w.kz, max(w.kxy // 2, 1)
     if is_dense(w):
-        return {"grad": "k_dense<%s, %d, 1, true>" % (t, r), "dirs": "k_dense<%s, %d, 2, false>" % (t, r),
+        ty = tile_rows["dirs"]
+        return {"grad": "k_dense<%s, %d, 1, true, %d>" % (t, r, ty), "dirs": "k_dense<%s, %d, 2, false, %d>" % (t, r, ty),
                 "solve": "k_solve", "update": "k_dense_update<%s>" % t}[kernel]
     return {"grad": "k_grad<%s, %d>" % (t, kz),
             "dirs": "k_dirs<%s, %d, %d, %d>" % (t, kz, r, tile_rows["dirs"]),
