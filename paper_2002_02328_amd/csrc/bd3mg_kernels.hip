@@ -241,7 +241,7 @@ __device__ __forceinline__ size_t slot_of()
 // the z-stencil of q to out.
 // ---------------------------------------------------------------------------
 template <typename T, int KZ>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
        int nshare)
@@ -294,6 +294,18 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
             const T *qp = q + ((size_t)p * gridDim.z + blockIdx.z) * S;
 #pragma unroll
             for (int qq = 0; qq < rg.E; ++qq) ht[qq] += ldo(qp, rg.off[qq]);
+        }
+    } else if (KZ <= 7 && sizeof(T) == 4) {
+        // taps past the volume read the nearest slice with weight 0: no
+        // branch per tap, so every tap's loads can be in flight together
+        // (up to 7 taps in single precision: more would spill registers)
+#pragma unroll
+        for (int c = -RZ; c <= RZ; ++c) {
+            const int m = min(max(k + c, 0), g.nz - 1);
+            const T w = (k + c == m) ? s.gz[(size_t)m * KZ + (c + RZ)] : T(0);
+            const T *qm = q + (size_t)m * S;
+#pragma unroll
+            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldo(qm, rg.off[qq]);
         }
     } else {
 #pragma unroll
