@@ -158,10 +158,10 @@ hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out
 constexpr int RDMAX = 5;    // largest in-slice radius of a dense kernel (11 wide)
 constexpr int KZDMAX = 21;  // largest z extent of a dense kernel
 enum : int { DM_H = 0, DM_DIRS = 1, DM_HT = 2 };
-// nsplit > 1 (DM_HT only): the source slices of every item are shared out
-// over nsplit workgroups writing to part ([nsplit][nitems] slices), then
-// summed in order into out, or left as shares when out is null (more
-// workgroups when there are few items).
+// nsplit > 1 (DM_HT only, out null): the source slices of every item are
+// shared out over nsplit workgroups writing to part ([nsplit][nitems]
+// slices), for a reader that adds the shares in order (more workgroups when
+// there are few items).
 template <typename T>
 hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, const T *pk,
                         const T *in, const T *sub, T *out, const Item *items, int nitems, int mode,

@@ -1122,7 +1122,7 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
     __shared__ double red[(NT / 64) * NQD];
     // nsplit > 1 (adjoint only): workgroup z = item nsplit + part, each part
     // a contiguous share of the item's source slices, written to the plane
-    // out + part (number of items) S + item S for a fixed-order sum later
+    // out + part (number of items) S + item S, added in order by the reader
     const int ii = nsplit > 1 ? (int)blockIdx.z / nsplit : (int)blockIdx.z;
     const int part = nsplit > 1 ? (int)blockIdx.z - ii * nsplit : 0;
     const Item it = items[ii];
@@ -1227,23 +1227,6 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
     if (partials) {
         double q1[1] = {qs[0]};
         wg_reduce_store<1>(q1, red, partials + slot_of());
-    }
-}
-
-// out_k = sum over parts p (in order) of part[p][item], per item (slice k):
-// the adjoint's source shares added in a fixed order.
-template <typename T>
-__global__ void __launch_bounds__(NT)
-k_dense_sum(Geom g, DevState<T> s, const T *__restrict__ part, T *__restrict__ out, const Item *__restrict__ items,
-            int nitems, int nsplit)
-{
-    const Item it = items[blockIdx.z];
-    if (s.stop && *s.stop) return;
-    const size_t S = (size_t)g.nx * g.ny;
-    for (size_t e = (size_t)blockIdx.x * NT + threadIdx.x; e < S; e += (size_t)gridDim.x * NT) {
-        T acc = part[(size_t)blockIdx.z * S + e];
-        for (int p = 1; p < nsplit; ++p) acc += part[((size_t)p * nitems + blockIdx.z) * S + e];
-        out[(size_t)it.k * S + e] = acc;
     }
 }
 
@@ -1454,18 +1437,12 @@ hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, 
     if (g.ty_dirs == 16) { constexpr int TYD = 16; CALL; } \
     else { constexpr int TYD = 32; CALL; }
     if (nsplit > 1) {
-        // adjoint over source shares into part, then their fixed-order sum
-        if (mode != DM_HT || !part) return hipErrorInvalidValue;
+        // adjoint over source shares into part; the gradient kernel adds them
+        if (mode != DM_HT || !part || out) return hipErrorInvalidValue;
         BD3MG_DENSE_TY(
             const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems * nsplit);
             BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true, TYD>), grid, dim3(NT), 0, st, g,
                                                     prm, s, pk, in, sub, part, items, mode, nullptr, nsplit)));
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess || !out) return e;  // no out: the shares are the result
-        const size_t S = (size_t)g.nx * g.ny;
-        const int gx = (int)std::min<size_t>((S + 4 * NT - 1) / (4 * NT), 1024);
-        hipLaunchKernelGGL(k_dense_sum<T>, dim3(gx, 1, nitems), dim3(NT), 0, st, g, s, (const T *)part, out, items,
-                           nitems, nsplit);
         return hipGetLastError();
     }
     BD3MG_DENSE_TY(
