@@ -199,7 +199,32 @@ __device__ __forceinline__ void load_taps(T (&w)[2 * R + 1], const T *__restrict
     for (int a = 0; a < 2 * R + 1; ++a) w[a] = t[a];
 }
 
-// Workgroup reduction of NV doubles (shuffle tree per wavefront, then the
+// One DPP move of a double (both halves with the same lane pattern); lanes of
+// rows outside ROWS receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront in registers: butterflies inside each
+// row of 16 lanes (quad permutes, half-row and row mirrors), then the two row
+// broadcasts. Lane 63 ends with the total; the other lanes hold partial sums.
+__device__ __forceinline__ double wave_sum_last(double s)
+{
+    s += dpp_move<0xb1, 0xf>(s);   // quad_perm [1,0,3,2]
+    s += dpp_move<0x4e, 0xf>(s);   // quad_perm [2,3,0,1]
+    s += dpp_move<0x141, 0xf>(s);  // row_half_mirror
+    s += dpp_move<0x140, 0xf>(s);  // row_mirror
+    s += dpp_move<0x142, 0xa>(s);  // row_bcast:15 into rows 1 and 3
+    s += dpp_move<0x143, 0xc>(s);  // row_bcast:31 into rows 2 and 3
+    return s;
+}
+
+// Workgroup reduction of NV doubles (DPP sum per wavefront, then the
 // wavefronts in order); thread v < NV stores the total of value v to dst[v].
 template <int NV>
 __device__ __forceinline__ void wg_reduce_store(double (&q)[NV], double *red, double *dst)
@@ -207,10 +232,8 @@ __device__ __forceinline__ void wg_reduce_store(double (&q)[NV], double *red, do
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        double s = q[v];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-        if (lane == 0) red[wave * NV + v] = s;
+        const double s = wave_sum_last(q[v]);
+        if (lane == 63) red[wave * NV + v] = s;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
@@ -490,10 +513,8 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        double sv = acc[v];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) sv += __shfl_down(sv, off, 64);
-        if (lane == 0) red[wave][v] = sv;
+        const double sv = wave_sum_last(acc[v]);
+        if (lane == 63) red[wave][v] = sv;
     }
     __syncthreads();
     if (threadIdx.x < NV) {
