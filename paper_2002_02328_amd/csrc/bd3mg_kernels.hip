@@ -21,7 +21,7 @@
 // and the update pass keeps q current: q_m += XY^T_m (H d')_m.
 //
 // Inner products are accumulated in double: per thread in index order, a
-// wavefront shuffle tree, the four wavefronts in order, then the slots of a
+// fixed DPP sum per wavefront, the four wavefronts in order, then the slots of a
 // block in slot order (k_solve) -- a fixed order, so runs are bitwise
 // reproducible.
 #include "bd3mg_internal.h"
