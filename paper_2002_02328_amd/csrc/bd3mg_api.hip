@@ -86,7 +86,7 @@ struct bd3mg_problem_s {
     int *d_sblk = nullptr;  // block of every slice
     int2 *d_pairs = nullptr;  // (direction slot, block) sources of the update items
     size_t pairs_alloc = 0;
-    int2 *d_units = nullptr;  // (first direction item, slice count) of the direction workgroups
+    Item *d_units = nullptr;  // direction workgroups: slice, block, first direction item, slice count
     size_t units_alloc = 0;
     int dirs_slices = 0;      // slices per direction workgroup (0: by group size)
     void *d_hd = nullptr;     // H d1 then H d2 of a launch group's direction items
@@ -322,7 +322,7 @@ void color_blocks(bd3mg_problem p)
 // H d2 on the item's slice make up H d' there.
 void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<Item> &gi,
                  std::vector<Item> &di, std::vector<Item> &ui, std::vector<int2> &pairs,
-                 std::vector<int2> &units, std::vector<BlockRange> &br, bd3mg_problem_s::Group &grp,
+                 std::vector<Item> &units, std::vector<BlockRange> &br, bd3mg_problem_s::Group &grp,
                  bool round = false)
 {
     const int rz = p->kz / 2;
@@ -346,7 +346,7 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
         dend.push_back((int)di.size() - grp.d_off);
         if (!round)
             for (int k = std::max(0, z0 - rz); k < std::min(p->nz, z0 + n + rz); ++k) {
-                ui.push_back(Item{k, b, z0, n, (int)pairs.size(), 1});
+                ui.push_back(Item{k, b, z0, n, (int)pairs.size(), 1, r.d0 + k - lo, b});
                 pairs.push_back(int2{r.d0 + k - lo, b});
                 halo[k] = 1;
             }
@@ -367,7 +367,8 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
                 const int c = blocks[t], z0 = p->z0[c], z1 = z0 + p->nsl[c];
                 if (k >= z0 - rz && k < z1 + rz) pairs.push_back(int2{dfirst[t] + k - dlo[t], c});
             }
-            ui.push_back(Item{k, b, p->z0[b], p->nsl[b], h0, (int)pairs.size() - h0});
+            const int2 first = (int)pairs.size() > h0 ? pairs[h0] : int2{0, 0};
+            ui.push_back(Item{k, b, p->z0[b], p->nsl[b], h0, (int)pairs.size() - h0, first.x, first.y});
             halo[k] = 1;
         }
     }
@@ -380,7 +381,10 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     const int per = p->dirs_slices > 0 ? p->dirs_slices
                                        : ((double)ndir * p->nx * p->ny >= (double)(1 << 23) ? 2 : 1);
     for (size_t t = 0; t < dfirst.size(); ++t)
-        for (int i = dfirst[t]; i < dend[t]; i += per) units.push_back(int2{i, std::min(per, dend[t] - i)});
+        for (int i = dfirst[t]; i < dend[t]; i += per) {
+            const Item &d = di[grp.d_off + i];
+            units.push_back(Item{d.k, d.block, d.z0, d.n, i, std::min(per, dend[t] - i), 0, 0});
+        }
     grp.round = round;
     grp.du_cnt = (int)units.size() - grp.du_off;
     grp.g_cnt = (int)gi.size() - grp.g_off;
@@ -410,7 +414,8 @@ bd3mg_status build_schedule(bd3mg_problem p)
     color_blocks(p);
     const int nb = (int)p->nsl.size();
     std::vector<Item> gi, di, ui;
-    std::vector<int2> pairs, units;
+    std::vector<int2> pairs;
+    std::vector<Item> units;
     std::vector<BlockRange> br;
     p->groups.assign(p->ncolors + nb, bd3mg_problem_s::Group{});
     for (int c = 0; c < p->ncolors; ++c) {
@@ -438,8 +443,8 @@ bd3mg_status build_schedule(bd3mg_problem p)
     ST_TRY(realloc_dev((void **)&p->d_pairs, &p->pairs_alloc, pairs.size() * sizeof(int2), "update sources"));
     HIP_TRY(hipMemcpyAsync(p->d_pairs, pairs.data(), pairs.size() * sizeof(int2), hipMemcpyHostToDevice,
                            p->stream));
-    ST_TRY(realloc_dev((void **)&p->d_units, &p->units_alloc, units.size() * sizeof(int2), "direction units"));
-    HIP_TRY(hipMemcpyAsync(p->d_units, units.data(), units.size() * sizeof(int2), hipMemcpyHostToDevice,
+    ST_TRY(realloc_dev((void **)&p->d_units, &p->units_alloc, units.size() * sizeof(Item), "direction units"));
+    HIP_TRY(hipMemcpyAsync(p->d_units, units.data(), units.size() * sizeof(Item), hipMemcpyHostToDevice,
                            p->stream));
     {
         std::vector<int> sblk(p->nz);
@@ -632,8 +637,7 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
                            p->d_pg, p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
-    HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, it + gr.d_off, p->d_units + gr.du_off, gr.du_cnt, p->d_pd,
-                           p->stream));
+    HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, p->d_units + gr.du_off, gr.du_cnt, p->d_pd, p->stream));
     if (prof) ST_TRY(prof_end(p));
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
     HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,

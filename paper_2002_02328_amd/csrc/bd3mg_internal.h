@@ -64,8 +64,13 @@ struct Item {
     int n;
     // update items: the source pairs [h0, h0 + hn) of the launch group's pair
     // list, each (direction slot, block) whose stored H d1, H d2 on slice k
-    // enter H d' on slice k
+    // enter H d' on slice k; direction units: the first direction item h0 and
+    // the hn (1 or 2) consecutive slices the workgroup takes
     int h0, hn;
+    // update items: a copy of the first pair (slot ps, block pb), so that a
+    // single-source item starts its loads without a dependent read of the
+    // pair list
+    int ps, pb;
 };
 
 // Work items of one block inside the item lists of a launch group.
@@ -120,11 +125,12 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
                        const T *x, T *out, const Item *items, int nitems, int mode,
                        double *partials, hipStream_t st, int nshare = 0);
 
-// Direction pass over nunits units (first item, 1 or 2 consecutive slices of
-// a block); stores H d1, H d2 of item i at slot i of s.hd.
+// Direction pass over nunits units (slice k of a block with the block's z0,
+// n; first direction item h0 and hn = 1 or 2 consecutive slices); stores
+// H d1, H d2 of item i at slot i of s.hd.
 template <typename T>
-hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
-                       const int2 *units, int nunits, double *partials, hipStream_t st);
+hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *units,
+                       int nunits, double *partials, hipStream_t st);
 
 // Update pass from the stored H d1, H d2 (pairs: (slot, block) per source;
 // multi: items may have more than one source, as in a round).

@@ -89,6 +89,30 @@ __device__ __forceinline__ T ldo(const T *base, uint32_t eoff)
     return *(const T *)((const char *)base + eoff * (uint32_t)sizeof(T));
 }
 
+// Buffer descriptor of n elements from p (gfx9 format word): loads through it
+// take the base in scalar registers and a 32-bit byte offset in a vector
+// register, so the many loads of a slice that share per-thread offsets need
+// no 64-bit address arithmetic each (the plain pointer form above loses the
+// scalar base once the offsets are hoisted out of a loop).
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_of(const T *p, size_t n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)(n * sizeof(T)), 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T ldbuf(__amdgpu_buffer_rsrc_t r, uint32_t boff);
+template <>
+__device__ __forceinline__ float ldbuf<float>(__amdgpu_buffer_rsrc_t r, uint32_t boff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, boff, 0, 0));
+}
+template <>
+__device__ __forceinline__ double ldbuf<double>(__amdgpu_buffer_rsrc_t r, uint32_t boff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
+}
+
 // x pass from I (rows of width WI, at least ROWS rows) to O (rows of width WO,
 // padded to a multiple of NT), WO output columns over ROWS rows:
 //   forward O[r][c] = sum_a wx[a] I[r][c + OFF - a],
@@ -300,13 +324,17 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
             xr[qq] = rx.inb[qq] ? v : T(0);
         }
     }
+    uint32_t bo[rg.E];
 #pragma unroll
-    for (int qq = 0; qq < rg.E; ++qq) ht[qq] = dv[qq] = 0;
+    for (int qq = 0; qq < rg.E; ++qq) {
+        ht[qq] = dv[qq] = 0;
+        bo[qq] = rg.off[qq] * (uint32_t)sizeof(T);
+    }
     if (block) {
-        const T *ds = s.dp[0] + (size_t)k * S;
+        const __amdgpu_buffer_rsrc_t ds = buf_of(s.dp[0] + (size_t)k * S, S);
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
-            const T v = ldo(ds, rg.off[qq]);
+            const T v = ldbuf<T>(ds, bo[qq]);
             dv[qq] = rg.inb[qq] ? v : T(0);
         }
     }
@@ -314,9 +342,9 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         // the data term is given as nshare shares per item (the general-kernel
         // adjoint split over workgroups), q = [share][item][ny][nx]: added in order
         for (int p = 0; p < nshare; ++p) {
-            const T *qp = q + ((size_t)p * gridDim.z + blockIdx.z) * S;
+            const __amdgpu_buffer_rsrc_t qp = buf_of(q + ((size_t)p * gridDim.z + blockIdx.z) * S, S);
 #pragma unroll
-            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += ldo(qp, rg.off[qq]);
+            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += ldbuf<T>(qp, bo[qq]);
         }
     } else if (KZ <= 7 && sizeof(T) == 4) {
         // taps past the volume read the nearest slice with weight 0: no
@@ -326,9 +354,9 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         for (int c = -RZ; c <= RZ; ++c) {
             const int m = min(max(k + c, 0), g.nz - 1);
             const T w = (k + c == m) ? s.gz[(size_t)m * KZ + (c + RZ)] : T(0);
-            const T *qm = q + (size_t)m * S;
+            const __amdgpu_buffer_rsrc_t qm = buf_of(q + (size_t)m * S, S);
 #pragma unroll
-            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldo(qm, rg.off[qq]);
+            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldbuf<T>(qm, bo[qq]);
         }
     } else {
 #pragma unroll
@@ -336,9 +364,9 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
             const int m = k + c;
             if (m < 0 || m >= g.nz) continue;
             const T w = s.gz[(size_t)m * KZ + (c + RZ)];
-            const T *qm = q + (size_t)m * S;
+            const __amdgpu_buffer_rsrc_t qm = buf_of(q + (size_t)m * S, S);
 #pragma unroll
-            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldo(qm, rg.off[qq]);
+            for (int qq = 0; qq < rg.E; ++qq) ht[qq] += w * ldbuf<T>(qm, bo[qq]);
         }
     }
     if (mode == GM_ZCOMB) {
@@ -663,8 +691,7 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
 
 template <typename T, int KZ, int R, int TYK>
 __global__ void __launch_bounds__(NT)
-k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ units,
-       double *__restrict__ partials)
+k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double *__restrict__ partials)
 {
     constexpr int RZ = KZ / 2;
     constexpr int W = TX + 2 * R, H = TYK + 2 * R;
@@ -678,11 +705,12 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, const 
     static_assert(padded<TX, H>() <= padded<WS, H>(), "x pass of d2 must fit the d1 tile");
     static_assert((NT / 64) * NQD * sizeof(double) <= padded<WS, H>() * sizeof(T), "reduction must fit");
 
-    const int2 un = units[blockIdx.z];  // first direction item, 1 or 2 slices
-    const Item it = items[un.x];
-    if (s.stop && *s.stop) return;  // read with the item, not before it
+    // slice k of the block [z0, z0 + n): direction items h0 and, when hn is
+    // 2, h0 + 1 (slice k + 1)
+    const Item it = units[blockIdx.z];
+    if (s.stop && *s.stop) return;  // read with the unit, not before it
     const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
-    const bool two = un.y > 1;
+    const bool two = it.hn > 1;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
     const size_t S = (size_t)g.nx * g.ny;
     const T *__restrict__ gg = s.g;
@@ -696,18 +724,22 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, const 
     // single slice's sum)
     Region<W, H, R, R> rg(g, x0, y0);
     T a1[rg.E], a2[rg.E], b1[rg.E], b2[rg.E];
+    uint32_t bo[rg.E];
 #pragma unroll
-    for (int qq = 0; qq < rg.E; ++qq) a1[qq] = a2[qq] = b1[qq] = b2[qq] = 0;
+    for (int qq = 0; qq < rg.E; ++qq) {
+        a1[qq] = a2[qq] = b1[qq] = b2[qq] = 0;
+        bo[qq] = rg.off[qq] * (uint32_t)sizeof(T);
+    }
 #pragma unroll
     for (int t = KZ; t >= 0; --t) {
         const int sl = k - RZ + t;
         if (sl < z0 || sl >= z1 || (t == KZ && !two)) continue;
         const T wa = t < KZ ? wz0[KZ - 1 - t] : T(0);
         const T wb = t > 0 && two ? wz1[KZ - t] : T(0);
-        const T *gs = gg + (size_t)sl * S, *ds = dpv + (size_t)sl * S;
+        const __amdgpu_buffer_rsrc_t gs = buf_of(gg + (size_t)sl * S, S), ds = buf_of(dpv + (size_t)sl * S, S);
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
-            const T gv = ldo(gs, rg.off[qq]), dv = ldo(ds, rg.off[qq]);
+            const T gv = ldbuf<T>(gs, bo[qq]), dv = ldbuf<T>(ds, bo[qq]);
             if (t < KZ) {
                 a1[qq] -= wa * gv;
                 a2[qq] += wa * dv;
@@ -718,10 +750,10 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ items, const 
             }
         }
     }
-    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)un.x, a1, a2, rg.off, rg.inb, A1, A2, B1, partials);
+    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)it.h0, a1, a2, rg.off, rg.inb, A1, A2, B1, partials);
     if (two) {
         __syncthreads();  // the reduction of slice k read A2
-        dirs_finish<T, R, TYK>(g, prm, s, it, k + 1, (size_t)un.x + 1, b1, b2, rg.off, rg.inb, A1, A2, B1,
+        dirs_finish<T, R, TYK>(g, prm, s, it, k + 1, (size_t)it.h0 + 1, b1, b2, rg.off, rg.inb, A1, A2, B1,
                                partials);
     }
 }
@@ -765,26 +797,30 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     // their latency overlaps the loads of H d' (no pass of this launch writes
     // H d1 or H d2)
     const bool ins = (m >= it.z0 && m < it.z0 + it.n);
-    const T *qs = s.q + (size_t)m * S, *xs = s.x + (size_t)m * S;
-    const T *ds = s.dp[0] + (size_t)m * S, *gs = s.g + (size_t)m * S;
+    const __amdgpu_buffer_rsrc_t qs = buf_of(s.q + (size_t)m * S, S), xs = buf_of(s.x + (size_t)m * S, S);
+    const __amdgpu_buffer_rsrc_t ds = buf_of(s.dp[0] + (size_t)m * S, S), gs = buf_of(s.g + (size_t)m * S, S);
     T qv[NRK], xv[NRK], dv[NRK], gv[NRK];
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row<NRK>(e), i = x0 + tx;
-        const uint32_t o = (i < g.nx && j < g.ny) ? (uint32_t)(j * g.nx + i) : 0u;
-        qv[e] = ldo(qs, o);
+        const uint32_t o = (i < g.nx && j < g.ny) ? (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T) : 0u;
+        qv[e] = ldbuf<T>(qs, o);
         xv[e] = dv[e] = gv[e] = 0;
         if (ins) {
-            xv[e] = ldo(xs, o);
-            dv[e] = ldo(ds, o);
-            gv[e] = ldo(gs, o);
+            xv[e] = ldbuf<T>(xs, o);
+            dv[e] = ldbuf<T>(ds, o);
+            gv[e] = ldbuf<T>(gs, o);
         }
     }
     {
         Region<W2, H2, R, R> rg(g, x0, y0);
         T v[rg.E];
+        uint32_t bo[rg.E];
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) v[qq] = 0;
+        for (int qq = 0; qq < rg.E; ++qq) {
+            v[qq] = 0;
+            bo[qq] = rg.off[qq] * (uint32_t)sizeof(T);
+        }
         // sources two at a time, so that the loads of both are in flight
         // together (a round has several per slice; a colour has one, and
         // its instance carries no code for more)
@@ -793,22 +829,27 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
             const int2 pa = pairs[it.h0 + p], pb = pairs[it.h0 + p + 1];
             const T a1 = (T)u[2 * pa.y], a2 = (T)u[2 * pa.y + 1];
             const T b1 = (T)u[2 * pb.y], b2 = (T)u[2 * pb.y + 1];
-            const T *ha1 = s.hd[0] + (size_t)pa.x * S, *ha2 = s.hd[1] + (size_t)pa.x * S;
-            const T *hb1 = s.hd[0] + (size_t)pb.x * S, *hb2 = s.hd[1] + (size_t)pb.x * S;
+            const __amdgpu_buffer_rsrc_t ha1 = buf_of(s.hd[0] + (size_t)pa.x * S, S);
+            const __amdgpu_buffer_rsrc_t ha2 = buf_of(s.hd[1] + (size_t)pa.x * S, S);
+            const __amdgpu_buffer_rsrc_t hb1 = buf_of(s.hd[0] + (size_t)pb.x * S, S);
+            const __amdgpu_buffer_rsrc_t hb2 = buf_of(s.hd[1] + (size_t)pb.x * S, S);
 #pragma unroll
             for (int qq = 0; qq < rg.E; ++qq) {
-                const T xa1 = ldo(ha1, rg.off[qq]), xa2 = ldo(ha2, rg.off[qq]);
-                const T xb1 = ldo(hb1, rg.off[qq]), xb2 = ldo(hb2, rg.off[qq]);
+                const T xa1 = ldbuf<T>(ha1, bo[qq]), xa2 = ldbuf<T>(ha2, bo[qq]);
+                const T xb1 = ldbuf<T>(hb1, bo[qq]), xb2 = ldbuf<T>(hb2, bo[qq]);
                 v[qq] += a1 * xa1 + a2 * xa2;
                 v[qq] += b1 * xb1 + b2 * xb2;
             }
         }
         if (p < it.hn) {
-            const int2 pr = pairs[it.h0 + p];
+            // the first pair is carried by the item itself
+            const int2 pr = p == 0 ? int2{it.ps, it.pb} : pairs[it.h0 + p];
             const T c1 = (T)u[2 * pr.y], c2 = (T)u[2 * pr.y + 1];
-            const T *h1 = s.hd[0] + (size_t)pr.x * S, *h2 = s.hd[1] + (size_t)pr.x * S;
+            const __amdgpu_buffer_rsrc_t h1 = buf_of(s.hd[0] + (size_t)pr.x * S, S);
+            const __amdgpu_buffer_rsrc_t h2 = buf_of(s.hd[1] + (size_t)pr.x * S, S);
 #pragma unroll
-            for (int qq = 0; qq < rg.E; ++qq) v[qq] += c1 * ldo(h1, rg.off[qq]) + c2 * ldo(h2, rg.off[qq]);
+            for (int qq = 0; qq < rg.E; ++qq)
+                v[qq] += c1 * ldbuf<T>(h1, bo[qq]) + c2 * ldbuf<T>(h2, bo[qq]);
         }
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
@@ -1346,13 +1387,13 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
 }
 
 template <typename T>
-hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *items,
-                       const int2 *units, int nunits, double *partials, hipStream_t st)
+hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *units,
+                       int nunits, double *partials, hipStream_t st)
 {
     if (nunits <= 0) return hipSuccess;
     BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
                     hipLaunchKernelGGL((k_dirs<T, KZ, R, TYK>), grid_of(g, nunits, TYK), dim3(NT), 0,
-                                       st, g, prm, s, items, units, partials))));
+                                       st, g, prm, s, units, partials))));
     return hipGetLastError();
 }
 
@@ -1498,7 +1539,7 @@ hipError_t launch_dense_update(const Geom &g, const DevState<T> &s, const Item *
                                        const T *, const T *, T *, const Item *, int, int,         \
                                        double *, hipStream_t, int);                               \
     template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
-                                       const Item *, const int2 *, int, double *, hipStream_t);   \
+                                       const Item *, int, double *, hipStream_t);                 \
     template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Item *, int,      \
                                          const int2 *, const double *, bool, hipStream_t);        \
     template hipError_t launch_refresh<T>(const Geom &, const DevState<T> &, const T *, T *,       \
