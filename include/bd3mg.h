@@ -255,9 +255,11 @@ typedef enum {
 } bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
 
-/* Autotuner: times `sweeps` sweeps (after one warm-up sweep) for every
- * combination of tile heights of the direction and update passes on this
- * problem, keeps the fastest, and restores the solver state it started from
+/* Autotuner: after `sweeps` warm-up sweeps at the current tiles, times
+ * `sweeps` sweeps (after one more warm-up sweep) for every combination of tile
+ * heights of the direction and update passes on this problem, twice (forward,
+ * then reverse order), keeps the combination with the fastest of its two
+ * times, and restores the solver state it started from
  * (x, previous steps, q, sweep count), so the call does not advance the
  * method.  chosen (may be NULL) receives {rows of the direction pass, rows of
  * the update pass}; ms (may be NULL) the best time per sweep in milliseconds.

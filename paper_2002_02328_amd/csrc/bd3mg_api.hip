@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/bd3mg.h"
@@ -1270,22 +1271,30 @@ bd3mg_status bd3mg_autotune(bd3mg_problem p, int sweeps, int *chosen, double *ms
     if (p->prec == BD3MG_FP32) cand.push_back(32);
     std::vector<int> cand_u = cand;
     if (p->dense) cand_u = {p->geom.ty_update};  // the general-kernel passes use the direction tile only
-    double best = -1.0;
-    int bd = p->geom.ty_dirs, bu = p->geom.ty_update;
+    std::vector<std::pair<int, int>> combos;
     for (int td : cand)
-        for (int tu : cand_u) {
-            p->geom.ty_dirs = td;
-            p->geom.ty_update = tu;
+        for (int tu : cand_u) combos.emplace_back(td, tu);
+    // a warm-up at the current tiles first (clocks and caches settle), then
+    // every candidate twice, in forward and then reverse order, keeping its
+    // faster time: a single pass in a fixed order favours the later ones
+    ST_TRY(bd3mg_run(p, sweeps, 0.0, 0, nullptr));
+    std::vector<double> tmin(combos.size(), -1.0);
+    for (int rep = 0; rep < 2; ++rep)
+        for (size_t c0 = 0; c0 < combos.size(); ++c0) {
+            const size_t c = rep ? combos.size() - 1 - c0 : c0;
+            p->geom.ty_dirs = combos[c].first;
+            p->geom.ty_update = combos[c].second;
             bd3mg_result r;
             ST_TRY(bd3mg_run(p, 1, 0.0, 0, nullptr));
             ST_TRY(bd3mg_run(p, sweeps, 0.0, 0, &r));
             const double t = r.seconds * 1e3 / sweeps;
-            if (best < 0.0 || t < best) {
-                best = t;
-                bd = td;
-                bu = tu;
-            }
+            if (tmin[c] < 0.0 || t < tmin[c]) tmin[c] = t;
         }
+    size_t bc = 0;
+    for (size_t c = 1; c < combos.size(); ++c)
+        if (tmin[c] < tmin[bc]) bc = c;
+    const double best = tmin[bc];
+    const int bd = combos[bc].first, bu = combos[bc].second;
     p->geom.ty_dirs = bd;
     p->geom.ty_update = bu;
     p->profile = prof0;
