@@ -113,6 +113,16 @@ __device__ __forceinline__ double ldbuf<double>(__amdgpu_buffer_rsrc_t r, uint32
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
 }
 
+__device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, boff, 0, 0);
+}
+__device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, uint32_t boff, double v)
+{
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, 0);
+}
+
 // x pass from I (rows of width WI, at least ROWS rows) to O (rows of width WO,
 // padded to a multiple of NT), WO output columns over ROWS rows:
 //   forward O[r][c] = sum_a wx[a] I[r][c + OFF - a],
@@ -250,13 +260,16 @@ __device__ __forceinline__ double wave_sum_last(double s)
 
 // Workgroup reduction of NV doubles (DPP sum per wavefront, then the
 // wavefronts in order); thread v < NV stores the total of value v to dst[v].
+// Values v >= nlive are zero on every thread (a uniform condition) and are
+// stored as 0 without their wavefront sums.
 template <int NV>
-__device__ __forceinline__ void wg_reduce_store(double (&q)[NV], double *red, double *dst)
+__device__ __forceinline__ void wg_reduce_store(double (&q)[NV], double *red, double *dst, int nlive = NV)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const double s = wave_sum_last(q[v]);
+        double s = 0.0;
+        if (v < nlive) s = wave_sum_last(q[v]);
         if (lane == 63) red[wave * NV + v] = s;
     }
     __syncthreads();
@@ -511,7 +524,7 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
     // each thread sums its slots in order, then one tree over the threads;
     // the slots are read CH per thread at a time, gradient and direction
     // slots together, so their loads are in flight at once
-    constexpr int CH = 2;
+    constexpr int CH = 4;
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
@@ -644,14 +657,14 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
     {
         // stored for the update pass, which combines them with the step
         // coefficients instead of blurring the new step again
-        T *o1 = s.hd[0] + i * S, *o2 = s.hd[1] + i * S;
+        const __amdgpu_buffer_rsrc_t o1 = buf_of(s.hd[0] + i * S, S), o2 = buf_of(s.hd[1] + i * S, S);
 #pragma unroll
         for (int e = 0; e < NRK; ++e) {
             const int j = y0 + out_row<NRK>(e), ii = x0 + tx;
             if (ii >= g.nx || j >= g.ny) continue;
-            const size_t o = (size_t)j * g.nx + ii;
-            o1[o] = h1[e];
-            o2[o] = h2[e];
+            const uint32_t o = (uint32_t)(j * g.nx + ii) * (uint32_t)sizeof(T);
+            stbuf(o1, o, h1[e]);
+            stbuf(o2, o, h2[e]);
         }
     }
     double qs[NQD];
@@ -686,7 +699,9 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
             qs[5] += z2v * z2v;
         }
     }
-    wg_reduce_store<NQD>(qs, red, partials + ((i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * NQD);
+    // without the VZ term the last three sums are zero
+    wg_reduce_store<NQD>(qs, red, partials + ((i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * NQD,
+                         prm.kappa != 0.0 ? NQD : 3);
 }
 
 template <typename T, int KZ, int R, int TYK>
@@ -862,14 +877,15 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     // which frees their registers for the blur passes
     if (ins) {
         const T u1 = (T)u[2 * it.block], u2 = (T)u[2 * it.block + 1];
+        const __amdgpu_buffer_rsrc_t xo = buf_of(s.x + (size_t)m * S, S), dpo = buf_of(s.dp[1] + (size_t)m * S, S);
 #pragma unroll
         for (int e = 0; e < NRK; ++e) {
             const int j = y0 + out_row<NRK>(e), i = x0 + tx;
             if (i >= g.nx || j >= g.ny) continue;
-            const size_t o = vidx(g, m, j, i);
+            const uint32_t o = (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T);
             const T d = u2 * dv[e] - u1 * gv[e];
-            s.x[o] = xv[e] + d;
-            s.dp[1][o] = d;
+            stbuf(xo, o, xv[e] + d);
+            stbuf(dpo, o, d);
         }
     }
     __syncthreads();
@@ -877,11 +893,12 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     __syncthreads();
     T v[NRK];
     ypass_out<T, R, TX, R, true, NRK>(B, v, wy);
+    const __amdgpu_buffer_rsrc_t qo = buf_of(s.q + (size_t)m * S, S);
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
-        s.q[vidx(g, m, j, i)] = qv[e] + v[e];
+        stbuf(qo, (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T), qv[e] + v[e]);
     }
 }
 
