@@ -330,10 +330,10 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
     Region<GW, GH, 0, 0> rg(g, x0, y0);
     T xr[rx.E], ht[rg.E], dv[rg.E];
     if (mode != GM_ZCOMB) {
-        const T *xs = x + (size_t)k * S;
+        const __amdgpu_buffer_rsrc_t xs = buf_of(x + (size_t)k * S, S);
 #pragma unroll
         for (int qq = 0; qq < rx.E; ++qq) {
-            const T v = ldo(xs, rx.off[qq]);
+            const T v = ldbuf<T>(xs, rx.off[qq] * (uint32_t)sizeof(T));
             xr[qq] = rx.inb[qq] ? v : T(0);
         }
     }
@@ -424,6 +424,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
     const T lam = (T)prm.lambda, eta2 = (T)(2.0 * prm.eta), kap2 = (T)(2.0 * prm.kappa),
             lo = (T)prm.xmin, hi = (T)prm.xmax;
     double qs[NQG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const __amdgpu_buffer_rsrc_t go = buf_of(s.g + (size_t)k * S, S);
 #pragma unroll
     for (int qq = 0; qq < rg.E; ++qq) {
         const int e = threadIdx.x + qq * NT;
@@ -452,7 +453,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
             }
             if (interior) {
                 if (block) {
-                    s.g[o] = gv;
+                    stbuf(go, bo[qq], gv);
                     const double gd = (double)gv, dd = (double)dv[qq];
                     qs[0] += gd * gd;
                     qs[1] += gd * dd;
