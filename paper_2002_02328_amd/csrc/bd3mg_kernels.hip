@@ -280,6 +280,22 @@ __device__ __forceinline__ void wg_reduce_store(double (&q)[NV], double *red, do
     }
 }
 
+// Tile (x, y) and item (z) of this workgroup, XCD-aware: the dispatcher
+// hands linear workgroup h to XCD h mod 8, so each XCD's workgroups are
+// mapped here to one contiguous run of the (x, y, z) order (a bijection of
+// the grid). Neighbouring tiles of a slice then run on the same XCD, and the
+// halo rows they share are found in that XCD's L2 (the update pass, whose
+// reads are one source slice per item with its halo).
+__device__ __forceinline__ uint3 xcd_block()
+{
+    constexpr unsigned NXCD = 8;
+    const unsigned gx = gridDim.x, gxy = gridDim.x * gridDim.y, n = gxy * gridDim.z;
+    const unsigned h = blockIdx.x + gx * blockIdx.y + gxy * blockIdx.z;
+    const unsigned per = n / NXCD, rem = n % NXCD, c = h % NXCD;
+    const unsigned t = c * per + min(c, rem) + h / NXCD;
+    return make_uint3(t % gx, (t / gx) % gridDim.y, t / gxy);
+}
+
 __device__ __forceinline__ size_t slot_of()
 {
     return ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -723,6 +739,10 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
 
     // slice k of the block [z0, z0 + n): direction items h0 and, when hn is
     // 2, h0 + 1 (slice k + 1)
+    // the plain workgroup order already puts the same tile of consecutive
+    // slices, which share KZ - 1 source slices, on one XCD close in time
+    // (grids of a multiple of 8 tiles); the XCD-aware order of the update
+    // pass would spread them out and lose that reuse
     const Item it = units[blockIdx.z];
     if (s.stop && *s.stop) return;  // read with the unit, not before it
     const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
@@ -800,10 +820,11 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     __shared__ __align__(16) T A[padded<WS2, H2>()];
     __shared__ __align__(16) T B[padded<TX, H2>()];
 
-    const Item it = items[blockIdx.z];
+    const uint3 bk = xcd_block();
+    const Item it = items[bk.z];
     if (s.stop && *s.stop) return;  // read with the item, not before it
     const int m = it.k;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
+    const int x0 = bk.x * TX, y0 = bk.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
     T wx[K], wy[K];
