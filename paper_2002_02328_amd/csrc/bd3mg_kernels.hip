@@ -296,6 +296,21 @@ __device__ __forceinline__ uint3 xcd_block()
     return make_uint3(t % gx, (t / gx) % gridDim.y, t / gxy);
 }
 
+// Tile of this workgroup within its slice, XCD-aware: when a slice has a
+// multiple of 8 tiles, the plain order sends tile l of every slice to XCD
+// l mod 8 (no two neighbouring tiles on one XCD); here XCD c takes instead
+// the contiguous tiles [c n/8, (c + 1) n/8) of each slice, neighbours that
+// share their halos in its L2, still slice after slice, so the same tile of
+// consecutive slices (which share source slices) stays on one XCD, n/8
+// workgroups apart.
+__device__ __forceinline__ uint2 xcd_slice_tile()
+{
+    const unsigned gx = gridDim.x, n = gridDim.x * gridDim.y;
+    unsigned l = blockIdx.x + gx * blockIdx.y;
+    if (n % 8 == 0) l = (l % 8) * (n / 8) + l / 8;
+    return make_uint2(l % gx, l / gx);
+}
+
 __device__ __forceinline__ size_t slot_of()
 {
     return ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
@@ -642,7 +657,7 @@ template <typename T, int R, int TYK, int E>
 __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, const DevState<T> &s,
                                             const Item &it, int kk, size_t i, const T (&v1)[E],
                                             const T (&v2)[E], const uint32_t (&off)[E], const bool (&inb)[E],
-                                            T *A1, T *A2, T *B1, double *partials)
+                                            T *A1, T *A2, T *B1, double *partials, uint2 tl)
 {
     constexpr int NRK = TYK / (NT / TX);
     constexpr int K = 2 * R + 1, W = TX + 2 * R, H = TYK + 2 * R, N = W * H;
@@ -650,7 +665,7 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
     T *const B2 = A1;
     double *const red = reinterpret_cast<double *>(A2);
     const int z0 = it.z0, z1 = it.z0 + it.n;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
+    const int x0 = tl.x * TX, y0 = tl.y * TYK;
     const int tx = threadIdx.x & (TX - 1);
     const size_t S = (size_t)g.nx * g.ny;
     T wx[K], wy[K];
@@ -717,7 +732,7 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
         }
     }
     // without the VZ term the last three sums are zero
-    wg_reduce_store<NQD>(qs, red, partials + ((i * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x) * NQD,
+    wg_reduce_store<NQD>(qs, red, partials + ((i * gridDim.y + tl.y) * gridDim.x + tl.x) * NQD,
                          prm.kappa != 0.0 ? NQD : 3);
 }
 
@@ -739,15 +754,16 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
 
     // slice k of the block [z0, z0 + n): direction items h0 and, when hn is
     // 2, h0 + 1 (slice k + 1)
-    // the plain workgroup order already puts the same tile of consecutive
-    // slices, which share KZ - 1 source slices, on one XCD close in time
-    // (grids of a multiple of 8 tiles); the XCD-aware order of the update
-    // pass would spread them out and lose that reuse
+    // tiles in the XCD-aware order within the slice; slices in plain order,
+    // which keeps the same tile of consecutive slices (sharing KZ - 1
+    // source slices) on one XCD close in time (the whole-grid order of the
+    // update pass would spread them out and lose that reuse)
+    const uint2 tl = xcd_slice_tile();
     const Item it = units[blockIdx.z];
     if (s.stop && *s.stop) return;  // read with the unit, not before it
     const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
     const bool two = it.hn > 1;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TYK;
+    const int x0 = tl.x * TX, y0 = tl.y * TYK;
     const size_t S = (size_t)g.nx * g.ny;
     const T *__restrict__ gg = s.g;
     const T *__restrict__ dpv = s.dp[0];
@@ -786,11 +802,11 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
             }
         }
     }
-    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)it.h0, a1, a2, rg.off, rg.inb, A1, A2, B1, partials);
+    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)it.h0, a1, a2, rg.off, rg.inb, A1, A2, B1, partials, tl);
     if (two) {
         __syncthreads();  // the reduction of slice k read A2
         dirs_finish<T, R, TYK>(g, prm, s, it, k + 1, (size_t)it.h0 + 1, b1, b2, rg.off, rg.inb, A1, A2, B1,
-                               partials);
+                               partials, tl);
     }
 }
 
