@@ -349,10 +349,14 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
     __shared__ T D[padded<GW, GH>()];
     __shared__ double red[(NT / 64) * NQG];
 
+    // tiles in the XCD-aware order within the slice (neighbours share their
+    // halos in L2; the same tile of consecutive slices stays on one XCD)
+    const uint2 tl = xcd_slice_tile();
+    const size_t slot = ((size_t)blockIdx.z * gridDim.y + tl.y) * gridDim.x + tl.x;
     const Item it = items[blockIdx.z];
     if (s.stop && *s.stop) return;  // read with the item, not before it
     const int k = it.k;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int x0 = tl.x * TX, y0 = tl.y * TY;
     const size_t S = (size_t)g.nx * g.ny;
     const bool block = (mode == GM_BLOCK);
 
@@ -528,10 +532,10 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
             qs[4] += w * (dx1 * dx2 + dy1 * dy2);
             qs[5] += w * (dx2 * dx2 + dy2 * dy2);
         }
-        wg_reduce_store<NQG>(qs, red, partials + slot_of() * NQG);
+        wg_reduce_store<NQG>(qs, red, partials + slot * NQG);
     } else if (mode == GM_EVAL) {
         double q4[NQE] = {qs[0], qs[1], qs[2], qs[3]};
-        wg_reduce_store<NQE>(q4, red, partials + slot_of() * NQE);
+        wg_reduce_store<NQE>(q4, red, partials + slot * NQE);
     }
 }
 
