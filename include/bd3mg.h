@@ -249,7 +249,7 @@ typedef enum {
     BD3MG_OPT_TILE_ROWS_AUX = 4,
     /* Output slices per workgroup of the direction pass: 1, 2 (consecutive
      * slices of a block share the reads of their common source slices), or 0
-     * (the default: 2 for a launch group with at least 2^23 direction output
+     * (the default: 2 for a launch group with at least 2^20 direction output
      * voxels, else 1).  Results are bitwise the same for every setting. */
     BD3MG_OPT_DIRS_SLICES = 5
 } bd3mg_option;

@@ -377,10 +377,10 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     // A direction workgroup takes two consecutive slices of a block (sharing
     // the reads of their common source slices) when the group has enough
     // direction outputs to keep every compute unit busy with half as many
-    // workgroups (at least 2^23 voxels), else one.
+    // workgroups (at least 2^20 voxels), else one.
     const int ndir = (int)di.size() - grp.d_off;
     const int per = p->dirs_slices > 0 ? p->dirs_slices
-                                       : ((double)ndir * p->nx * p->ny >= (double)(1 << 23) ? 2 : 1);
+                                       : ((double)ndir * p->nx * p->ny >= (double)(1 << 20) ? 2 : 1);
     for (size_t t = 0; t < dfirst.size(); ++t)
         for (int i = dfirst[t]; i < dend[t]; i += per) {
             const Item &d = di[grp.d_off + i];
