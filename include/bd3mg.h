@@ -22,8 +22,9 @@
  *       (H x)_{k,j,i} = sum_{c,b,a} gz_k[c] gy_k[b] gx_k[a] x_{k-c, j-b, i-a},
  *     zero padding; table rows are indexed [k][a + r], a in [-r, r].
  *   - "on_device" pointers are device memory of the calling process on the
- *     current HIP device; the library reads/writes them in order on its own
- *     stream and synchronises before returning.  Host pointers may be
+ *     problem's HIP device; the library reads/writes them in order on the
+ *     problem's stream (its own, or the caller's, see bd3mg_create) and
+ *     synchronises that stream before returning.  Host pointers may be
  *     pageable.
  *   - Ownership: every input is copied before the call returns; the library
  *     keeps no caller pointer.  A problem handle owns all of its device
@@ -100,9 +101,18 @@ const char *bd3mg_last_error(void);
 bd3mg_status bd3mg_psf_gaussian(int nz, int k, const double *sigma, double *table);
 
 /* Create a problem of nx*ny*nz voxels in the given precision (bd3mg_precision)
- * on the current HIP device.  ERR_ARG: a dimension < 1, precision unknown, or
- * one slice (nx*ny elements) of 2 GiB or more. */
-bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, bd3mg_problem *out);
+ * on the current HIP device (the problem statement of Sec. 2, eq. "P", on the
+ * volume of Sec. 3.1).  hip_stream is the hipStream_t on which every pass,
+ * copy and evaluation of this problem is enqueued: NULL gives the problem a
+ * non-blocking stream of its own (created here, destroyed by bd3mg_destroy);
+ * a caller's stream (for instance a torch stream's handle) is used as given,
+ * is not destroyed, must outlive the problem and must belong to the current
+ * device.  Work the caller enqueues on that stream before a call is ordered
+ * before it, so device buffers written there may be passed with on_device = 1
+ * without further synchronisation.  ERR_ARG: a dimension < 1, precision
+ * unknown, or one slice (nx*ny elements) of 2 GiB or more. */
+bd3mg_status bd3mg_create(int nx, int ny, int nz, int precision, void *hip_stream,
+                          bd3mg_problem *out);
 
 /* Release the handle and all its device memory.  NULL is accepted. */
 bd3mg_status bd3mg_destroy(bd3mg_problem p);
@@ -190,9 +200,14 @@ bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device);
  * gives bitwise the same state as run(a + b).  Stops after max_sweeps
  * sweeps, or, when grad_rtol > 0, at the first check with ||grad f(x)|| <=
  * grad_rtol * ||grad f(y)||; a check happens every check_every sweeps and
- * after the last sweep.  With grad_rtol <= 0 and check_every == 0 nothing is
- * evaluated (res->f and res->grad_norm are NaN) and the call only enqueues
- * the sweeps and waits for them.  res may be NULL.  ERR_ARG: max_sweeps < 0
+ * after the last sweep.  A check runs on the device from the maintained q;
+ * a check that passes is confirmed on a residual rebuilt from x (in scratch,
+ * q untouched), and when the rebuilt gradient is above the threshold q is
+ * replaced by the rebuilt residual and the run goes on.  res->f and
+ * res->grad_norm are evaluated at the returned x from a rebuilt residual.
+ * With grad_rtol <= 0 and check_every == 0 nothing is evaluated (res->f and
+ * res->grad_norm are NaN) and the call only enqueues the sweeps and waits for
+ * them.  res may be NULL.  ERR_ARG: max_sweeps < 0
  * or check_every < 0.  ERR_STATE: PSF, data or blocks not set.
  * ERR_NOT_CONVERGED: grad_rtol > 0 and not reached (state still valid). */
 bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,

@@ -30,7 +30,7 @@ SIGNATURES = {
     "bd3mg_version": ([], C.c_int),
     "bd3mg_last_error": ([], C.c_char_p),
     "bd3mg_psf_gaussian": ([_i, _i, _dp, _dp], C.c_int),
-    "bd3mg_create": ([_i, _i, _i, _i, C.POINTER(_dp)], C.c_int),
+    "bd3mg_create": ([_i, _i, _i, _i, _dp, C.POINTER(_dp)], C.c_int),
     "bd3mg_destroy": ([_dp], C.c_int),
     "bd3mg_set_psf_separable": ([_dp, _i, _i, _i, _dp, _dp, _dp], C.c_int),
     "bd3mg_set_psf_gaussian": ([_dp, _i, _i, _dp, _dp], C.c_int),
@@ -140,10 +140,14 @@ def probe_copy(nbytes, iters=5):
 class Problem:
     """Handle of one BD3MG problem living on the GPU."""
 
-    def __init__(self, nx, ny, nz, precision=FP32):
+    def __init__(self, nx, ny, nz, precision=FP32, stream=None):
+        """stream: None for a stream of the problem's own, or the integer
+        handle of a caller's HIP stream (e.g. torch.cuda.Stream().cuda_stream)."""
         L = load()
         h = _dp()
-        _check(L.bd3mg_create(nx, ny, nz, precision, C.byref(h)))
+        _check(L.bd3mg_create(nx, ny, nz, precision, None if stream is None else C.c_void_p(int(stream)),
+                              C.byref(h)))
+        self.stream = stream
         self._h = h
         self.shape = (nz, ny, nx)
         self.precision = precision

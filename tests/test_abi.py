@@ -69,7 +69,7 @@ def test_create_rejects_bad_sizes_without_touching_the_device(lib):
         binding.Problem(4, 4, 4, precision=7)
     assert e.value.status == binding.ERR_ARG
     h = C.c_void_p()
-    assert lib.bd3mg_create(4, 4, 4, 0, None) == binding.ERR_ARG
+    assert lib.bd3mg_create(4, 4, 4, 0, None, None) == binding.ERR_ARG
     assert lib.bd3mg_destroy(None) == binding.OK
 
 
