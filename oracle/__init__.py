@@ -31,7 +31,14 @@ class _Problem(C.Structure):
         ("dense", C.c_int),
         ("mu", C.c_double),
         ("pk", C.c_void_p),
+        ("method", C.c_int),
+        ("lip", C.c_double),
+        ("n_inner", C.c_int),
+        ("tol_inner", C.c_double),
     ]
+
+# Block steps of the ablation study (Sec. 3.2): BD3MG and its variants.
+BD3MG, ASYNC_GD, ASYNC_CG, ASYNC_MM = 0, 1, 2, 3
 
 
 def lib():
@@ -60,6 +67,7 @@ def lib():
         L.orc_dot.restype = C.c_double
         L.orc_majorant_form.argtypes = [P, dp, dp, dp, C.c_int, C.c_int]
         L.orc_majorant_form.restype = C.c_double
+        L.orc_majorant_apply.argtypes = [P, dp, dp, dp, C.c_int, C.c_int]
         L.orc_pinv2.argtypes = [dp, dp]
         L.orc_color_schedule.argtypes = [C.c_int, dp, C.c_int, dp, dp]
         L.orc_color_schedule.restype = C.c_int
@@ -138,6 +146,7 @@ class Problem:
 
     def __init__(self, y, gx, gy, gz, lam=0.0, delta=1.0, eta=0.0, kappa=0.0,
                  xmin=0.0, xmax=1.0, dense=False, mu=0.0):
+        """method etc.: see set_method (BD3MG unless changed)."""
         self.y = _f64(y)
         assert self.y.ndim == 3
         self.nz, self.ny, self.nx = self.y.shape
@@ -152,8 +161,21 @@ class Problem:
                            self.gx.shape[1], self.gy.shape[1], self.gz.shape[1],
                            self.gx.ctypes.data, self.gy.ctypes.data, self.gz.ctypes.data,
                            self.y.ctypes.data, self.lam, self.delta, self.eta, self.kappa,
-                           self.xmin, self.xmax, int(self.dense), self.mu, None)
+                           self.xmin, self.xmax, int(self.dense), self.mu, None,
+                           BD3MG, 0.0, 0, 0.0)
         self.pk = None
+
+    def set_method(self, method, lip=None, n_inner=10, tol_inner=0.0):
+        """Block step of the ablation study (Sec. 3.2): BD3MG, ASYNC_GD (step
+        -grad / L), ASYNC_CG (BD3MG's subspace [-grad, d_prev] with the metric
+        L Id, which gives Async-GD's step up to rounding) or
+        ASYNC_MM (d' = -A_S(x)^{-1} grad_S f by at most n_inner BiCG
+        iterations, stopping once ||r|| <= tol_inner ||r_0||).  lip: L of the
+        metric L Id (default: the Lipschitz bound of grad f)."""
+        self._s.method = int(method)
+        self._s.lip = float(self.lipschitz_bound() if lip is None else lip)
+        self._s.n_inner = int(n_inner)
+        self._s.tol_inner = float(tol_inner)
 
     @property
     def shape(self):
@@ -211,6 +233,15 @@ class Problem:
         x, u, v = _f64(x), _f64(u), _f64(v)
         return float(lib().orc_majorant_form(self._p(), _ptr(x), _ptr(u), _ptr(v),
                                              int(z0), int(self.nz if z1 is None else z1)))
+
+    def majorant_apply(self, x, u, z0=0, z1=None):
+        """[A(x) u]_S for u supported on the slices [z0, z1) (zero elsewhere;
+        plus mu u): the principal submatrix of the majorant times u."""
+        x, u = _f64(x), _f64(u)
+        out = np.zeros(self.shape)
+        lib().orc_majorant_apply(self._p(), _ptr(x), _ptr(u), _ptr(out), int(z0),
+                                 int(self.nz if z1 is None else z1))
+        return out
 
     def block_step(self, x, dprev, z0, n):
         """One worker step plus master update, in place on x and dprev.

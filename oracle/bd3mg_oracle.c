@@ -57,6 +57,14 @@ typedef struct {
     int dense;                   /* 1: triple-sum definition of H; 0: separable twin */
     double mu;                   /* curvature inflation of every block majorant (Assumption C); 0: none */
     const double *pk;            /* general kernels [nz][kz][ky][kx] (triple sum), or NULL */
+    /* Block step of the ablation study (Sec. 3.2, "Ablation study and
+     * comparative analysis"): 0 BD3MG; 1 Async-GD (subspace {-grad}, metric
+     * L Id); 2 Async-CG (subspace {-grad, d_prev}, metric L Id); 3 Async-MM
+     * (d' = -A_S(x)^{-1} grad_S f by linear BiCG).  mu adds to every metric. */
+    int method;
+    double lip;                  /* L of the metric L Id (methods 1 and 2) */
+    int n_inner;                 /* Async-MM: BiCG iterations at most */
+    double tol_inner;            /* Async-MM: stop when ||r_k|| <= tol_inner ||r_0|| (0: never) */
 } orc_problem;
 
 #define VOX(p, k, j, i) (((size_t)(k) * (size_t)(p)->ny + (size_t)(j)) * (size_t)(p)->nx + (size_t)(i))
@@ -530,6 +538,48 @@ double orc_majorant_form(const orc_problem *p, const double *x, const double *u,
     return quad + 2.0 * p->eta * box + p->lambda * tv + 2.0 * p->kappa * zz;
 }
 
+/* Majorant matrix applied to a block vector (Sec. 2.2, eq. "maj": the
+ * half-quadratic A(x) of the criterion; A_(S) its principal submatrix on the
+ * block S = [z0, z1)): for u supported on S (zero elsewhere),
+ *   out_S = [H^T H u + 2 eta u + lambda (V^X^T(w V^X u) + V^Y^T(w V^Y u))
+ *            + 2 kappa V^Z^T V^Z u]_S + mu u_S,   w = omega(x),
+ * and out is left untouched outside S.  <v, out> equals the bilinear form
+ * orc_majorant_form(u, v) (+ mu <u, v>) for v supported on S. */
+void orc_majorant_apply(const orc_problem *p, const double *x, const double *u, double *out,
+                        int z0, int z1)
+{
+    int rz = p->kz / 2;
+    size_t N = nvox(p), S = nslice(p);
+    if (z0 < 0) z0 = 0;
+    if (z1 > p->nz) z1 = p->nz;
+    if (z0 >= z1) return;
+    int h0 = z0 - rz < 0 ? 0 : z0 - rz, h1 = z1 + rz > p->nz ? p->nz : z1 + rz;
+    double *hu = scratch_get(SCR_HU, N);
+    orc_H(p, u, hu, h0, h1);
+    orc_HT(p, hu, out, z0, z1);
+    scratch_clear(hu, h0, h1, S);
+#pragma omp parallel for schedule(static)
+    for (int k = z0; k < z1; ++k)
+        for (int j = 0; j < p->ny; ++j)
+            for (int i = 0; i < p->nx; ++i) {
+                size_t v = VOX(p, k, j, i);
+                double acc = out[v] + 2.0 * p->eta * u[v];
+                double tv = 0.0;
+                if (i >= 1) tv += omega_at(p, x, k, j, i - 1) * dX(p, u, k, j, i - 1);
+                if (i < p->nx - 1) tv -= omega_at(p, x, k, j, i) * dX(p, u, k, j, i);
+                if (j >= 1) tv += omega_at(p, x, k, j - 1, i) * dY(p, u, k, j - 1, i);
+                if (j < p->ny - 1) tv -= omega_at(p, x, k, j, i) * dY(p, u, k, j, i);
+                acc += p->lambda * tv;
+                if (p->kappa != 0.0) {
+                    double zz = 0.0;
+                    if (k >= 1) zz += dZ(p, u, k - 1, j, i);
+                    if (k < p->nz - 1) zz -= dZ(p, u, k, j, i);
+                    acc += 2.0 * p->kappa * zz;
+                }
+                out[v] = acc + p->mu * u[v];
+            }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Moore-Penrose inverse of the symmetric PSD 2x2 matrix [[b11, b12],[b12, b22]]
  * (Sec. 2.3, eq. "minimizer").  Full rank when det > 1e-12 b11 b22: exact
@@ -602,10 +652,119 @@ int orc_color_schedule(int nblocks, const int *nslices, int min_gap, int *order,
  * problem's mu > 0 (the curvature inflation of Assumption C), u = -B^+ D^T g,
  * d' = D u.
  * d' is written to dout on S only; x and dprev are not changed. */
+/* Async-MM's inner solve (Sec. 3.2: the Worker's direction becomes
+ * d' = -A_(S)(x)^{-1} grad_S f(x), the inversion done by a linear biconjugate
+ * gradient solver): BiCG on A_S(x) v = b, b = -g_S, from v = 0, with the
+ * shadow residual started at the residual.  At most n_inner iterations;
+ * stops early when ||r_k|| <= tol_inner ||r_0|| or when <rt, r> or
+ * <pt, A p> vanishes.  v (on S) is written to vout; returns the iterations
+ * done and stores ||r||^2 at the end in *rr_end. */
+static int bicg_block(const orc_problem *p, const double *x, const double *g, double *vout, int z0, int n,
+                      double *rr_end)
+{
+    size_t N = nvox(p), S = nslice(p);
+    size_t off = (size_t)z0 * S, cnt = (size_t)n * S;
+    int z1 = z0 + n;
+    double *r = (double *)calloc(N, sizeof(double));
+    double *rt = (double *)calloc(N, sizeof(double));
+    double *pv = (double *)calloc(N, sizeof(double));
+    double *pt = (double *)calloc(N, sizeof(double));
+    double *ap = (double *)calloc(N, sizeof(double));
+    double *apt = (double *)calloc(N, sizeof(double));
+    for (size_t q = off; q < off + cnt; ++q) {
+        vout[q] = 0.0;
+        r[q] = -g[q];  /* r_0 = b - A v_0, v_0 = 0 */
+        rt[q] = r[q];
+        pv[q] = r[q];
+        pt[q] = rt[q];
+    }
+    double r0 = sqrt(dot_slices(p, r, r, z0, z1));
+    double rho = dot_slices(p, rt, r, z0, z1);
+    int it = 0;
+    while (it < p->n_inner && rho != 0.0) {
+        orc_majorant_apply(p, x, pv, ap, z0, z1);
+        /* A_S(x) is symmetric, so the shadow system's A^T pt is A pt */
+        orc_majorant_apply(p, x, pt, apt, z0, z1);
+        double den = dot_slices(p, pt, ap, z0, z1);
+        if (den == 0.0) break;
+        double alpha = rho / den;
+        for (size_t q = off; q < off + cnt; ++q) {
+            vout[q] += alpha * pv[q];
+            r[q] -= alpha * ap[q];
+            rt[q] -= alpha * apt[q];
+        }
+        ++it;
+        if (p->tol_inner > 0.0 && sqrt(dot_slices(p, r, r, z0, z1)) <= p->tol_inner * r0) break;
+        double rho1 = dot_slices(p, rt, r, z0, z1);
+        double beta = rho1 / rho;
+        rho = rho1;
+        for (size_t q = off; q < off + cnt; ++q) {
+            pv[q] = r[q] + beta * pv[q];
+            pt[q] = rt[q] + beta * pt[q];
+        }
+    }
+    if (rr_end) *rr_end = dot_slices(p, r, r, z0, z1);
+    free(r); free(rt); free(pv); free(pt); free(ap); free(apt);
+    return it;
+}
+
+/* The Worker's direction for the ablation variants of Sec. 3.2 (p->method
+ * 1-3), from the gradient g on S; d' to dout on S.  info as for BD3MG:
+ * GD and CG give {B11, B12, B22, c1, c2, u1, u2, ||g||^2} of their metric
+ * L Id (GD: B12 = B22 = c2 = u2 = 0); MM gives {iterations, ||r_end||^2,
+ * 0, c1, 0, 0, 0, ||g||^2}. */
+static void ablation_direction(const orc_problem *p, const double *x, const double *dprev, const double *g,
+                               int z0, int n, double *dout, double *info)
+{
+    size_t S = nslice(p);
+    size_t off = (size_t)z0 * S, cnt = (size_t)n * S;
+    int z1 = z0 + n;
+    double gg = dot_slices(p, g, g, z0, z1);
+    double lm = p->lip + p->mu;
+    double B[3] = {0, 0, 0}, c1 = -gg, c2 = 0.0, u1 = 0.0, u2 = 0.0;
+    if (p->method == 1) {
+        /* D = [-g], A_S = L Id: B = L <g, g>, c = <-g, g>, u = -B^+ c */
+        B[0] = lm * gg;
+        u1 = B[0] > 0.0 ? -c1 / B[0] : 0.0;
+        for (size_t q = off; q < off + cnt; ++q) dout[q] = u1 * -g[q];
+    } else if (p->method == 2) {
+        /* BD3MG's Worker step with the basic metric A_S = L Id: D = [-g, d],
+         * B = L D^T D, c = D^T g, u = -B^+ c.  Since -g lies in the range of
+         * D, D u = -g / L: the step of Async-GD, up to rounding. */
+        double gd = dot_slices(p, g, dprev, z0, z1), dd = dot_slices(p, dprev, dprev, z0, z1);
+        B[0] = lm * gg;
+        B[1] = -lm * gd;
+        B[2] = lm * dd;
+        c2 = gd;
+        double P[3];
+        orc_pinv2(B, P);
+        u1 = -(P[0] * c1 + P[1] * c2);
+        u2 = -(P[1] * c1 + P[2] * c2);
+        for (size_t q = off; q < off + cnt; ++q) dout[q] = u1 * -g[q] + u2 * dprev[q];
+    } else {
+        double rr = 0.0;
+        int it = bicg_block(p, x, g, dout, z0, n, &rr);
+        B[0] = (double)it;
+        B[1] = rr;
+    }
+    if (info) {
+        info[0] = B[0]; info[1] = B[1]; info[2] = B[2];
+        info[3] = c1; info[4] = c2; info[5] = u1; info[6] = u2;
+        info[7] = gg;
+    }
+}
+
 static void block_direction(const orc_problem *p, const double *x, const double *dprev, int z0, int n,
                             double *dout, double *info)
 {
     size_t N = nvox(p), S = nslice(p);
+    if (p->method != 0) {
+        double *ga = scratch_get(SCR_G, N);
+        orc_grad_slices(p, x, ga, z0, z0 + n);
+        ablation_direction(p, x, dprev, ga, z0, n, dout, info);
+        scratch_clear(ga, z0, z0 + n, S);
+        return;
+    }
     size_t off = (size_t)z0 * S, cnt = (size_t)n * S;
     double *g = scratch_get(SCR_G, N);
     double *d1 = scratch_get(SCR_D1, N);

@@ -47,6 +47,14 @@ MUTATIONS = {
                                "p->pk[(((size_t)k * p->kz + (rz - c)) * p->ky"),
     "rotation-direction": ("double u = a * ct + b * st, v = -a * st + b * ct;",
                            "double u = a * ct - b * st, v = a * st + b * ct;"),
+    "majorant-apply-box-factor": ("double acc = out[v] + 2.0 * p->eta * u[v];",
+                                  "double acc = out[v] + 1.0 * p->eta * u[v];"),
+    "majorant-apply-tv-weight-index": ("if (i >= 1) tv += omega_at(p, x, k, j, i - 1) * dX(p, u, k, j, i - 1);",
+                                       "if (i >= 1) tv += omega_at(p, x, k, j, i) * dX(p, u, k, j, i - 1);"),
+    "bicg-residual-sign": ("r[q] -= alpha * ap[q];", "r[q] += alpha * ap[q];"),
+    "bicg-direction-update": ("pv[q] = r[q] + beta * pv[q];", "pv[q] = r[q] + rho * pv[q];"),
+    "async-gd-step-without-L": ("u1 = B[0] > 0.0 ? -c1 / B[0] : 0.0;", "u1 = B[0] > 0.0 ? -c1 / gg : 0.0;"),
+    "async-cg-metric-offdiagonal-sign": ("B[1] = -lm * gd;", "B[1] = lm * gd;"),
     "dense-lipschitz-column-sums": ("if (k + t >= 0 && k + t < p->nz) c += fabs(p->pk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);",
                                     "if (k + t >= 0 && k + t < p->nz) c += 0.5 * fabs(p->pk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);"),
 }
@@ -68,7 +76,8 @@ NET_MUTATIONS = {
     "net-bf16-ties-away": ("u += 0x7fffu + lsb;", "u += 0x8000u; (void)lsb;"),
 }
 
-PIN_FILES = {SRC: ["test_oracle_pins.py", "test_oracle_round.py", "test_oracle_dense.py"],
+PIN_FILES = {SRC: ["test_oracle_pins.py", "test_oracle_round.py", "test_oracle_dense.py",
+                   "test_oracle_ablation.py"],
              NET_SRC: ["test_oracle_convnet.py"]}
 
 
