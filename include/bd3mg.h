@@ -213,6 +213,31 @@ bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device);
 bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,
                        bd3mg_result *res);
 
+/* bd3mg_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, hosts that forbid hipMalloc): the same
+ * sweeps with the same kernels, but no call of hipMalloc, hipFree or any
+ * allocating routine.  Its partial sums, per-block coefficients, stop-test
+ * control block and stored directions H d1, H d2 come from a fixed scratch
+ * array of 64 MiB per GPU, held from the library's first use on that GPU until
+ * the process ends; the problem's own buffers of these are left untouched.
+ * Needed: 2 (n_c + 2 r_z b_c) nx ny slices of the storage type for the
+ * stored directions of the largest launch group (see bd3mg_set_blocks), plus
+ * the partial sums (about 0.2 % of a slice each per work item); a problem
+ * needing more than 64 MiB is refused with ERR_ARG and the needed size in
+ * bd3mg_last_error().  Every call on one GPU shares that GPU's array: calls
+ * that overlap in time on one GPU (any problems, any streams) race and must
+ * be ordered by the caller.  The stop-test control block is cleared at the
+ * start of every call; every other part is written before it is read.
+ * Differences from bd3mg_run: a passing check is confirmed on q rebuilt in
+ * place from x (then kept), and res->f is formed from q rebuilt in place;
+ * profiling is not recorded.  Needs the separable PSF and a built schedule
+ * (bd3mg_get_schedule, bd3mg_run or bd3mg_eval after the last change of
+ * blocks or PSF): ERR_STATE otherwise, as for a missing PSF, data or
+ * blocks.  x^0 = y, the reference norm ||grad f(y)|| and q are formed in
+ * place when not yet current. */
+bd3mg_status bd3mg_run_noalloc(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,
+                               bd3mg_result *res);
+
 /* Copy the current iterate out (storage type). */
 bd3mg_status bd3mg_get_x(bd3mg_problem p, void *x, int on_device);
 

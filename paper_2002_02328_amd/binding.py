@@ -42,6 +42,7 @@ SIGNATURES = {
     "bd3mg_get_schedule": ([_dp, _dp, _dp, _dp], C.c_int),
     "bd3mg_set_x0": ([_dp, _dp, _i], C.c_int),
     "bd3mg_run": ([_dp, _i, _d, _i, _dp], C.c_int),
+    "bd3mg_run_noalloc": ([_dp, _i, _d, _i, _dp], C.c_int),
     "bd3mg_get_x": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_dprev": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_state": ([_dp, _dp, _dp, _dp, _dp, _i], C.c_int),
@@ -245,6 +246,16 @@ class Problem:
             check_every = 1 if grad_rtol > 0 else max(int(max_sweeps), 1)
         res = Result()
         _check(load().bd3mg_run(self._h, max_sweeps, grad_rtol, check_every, C.byref(res)),
+               allow=(ERR_NOT_CONVERGED,))
+        return res.as_dict()
+
+    def run_noalloc(self, max_sweeps, grad_rtol=0.0, check_every=None):
+        """bd3mg_run_noalloc: run with the library's fixed scratch array (no
+        device allocation); the schedule must be built (get_schedule)."""
+        if check_every is None:
+            check_every = 1 if grad_rtol > 0 else max(int(max_sweeps), 1)
+        res = Result()
+        _check(load().bd3mg_run_noalloc(self._h, max_sweeps, grad_rtol, check_every, C.byref(res)),
                allow=(ERR_NOT_CONVERGED,))
         return res.as_dict()
 

@@ -94,6 +94,7 @@ struct bd3mg_problem_s {
     int dirs_slices = 0;      // slices per direction workgroup (0: by group size)
     void *d_hd = nullptr;     // H d1 then H d2 of a launch group's direction items
     size_t hd_alloc = 0, hd_slots = 0;
+    int maxg = 1, maxd = 1;   // most gradient and direction items of a launch group
 
     // reductions
     double *d_pg = nullptr, *d_pd = nullptr, *d_pe = nullptr, *d_pr = nullptr;
@@ -473,6 +474,8 @@ bd3mg_status build_schedule(bd3mg_problem p)
         maxg = std::max(maxg, grp.g_cnt);
         maxd = std::max(maxd, grp.d_cnt);
     }
+    p->maxg = maxg;
+    p->maxd = maxd;
     ST_TRY(realloc_dev((void **)&p->d_pg, &p->pg_cap, (size_t)maxg * p->ntiles * NQG * sizeof(double),
                        "gradient partial sums"));
     ST_TRY(realloc_dev((void **)&p->d_pd, &p->pd_cap,
@@ -540,10 +543,11 @@ bd3mg_status check(bd3mg_problem p, double thr, int sweep, int *stop)
 }
 
 // ||grad f(xin)|| from the blurred residual qin, and, when f is wanted, f(xin)
-// (which needs the residual itself: one H pass into a scratch volume).  Sums
-// are reduced in a fixed order on the device.
+// (which needs the residual itself: one H pass into a volume, hbuf, or the
+// problem's scratch volume when null).  Sums are reduced in a fixed order on
+// the device.
 template <typename T>
-bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, double *gn)
+bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, double *gn, T *hbuf)
 {
     DevState<T> s = dev_state<T>(p);
     const int nslot = p->ntiles * p->nz;
@@ -556,15 +560,17 @@ bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, doub
     }
     HIP_TRY(launch_sum(p->d_pe, nslot, NQE, p->d_sum, p->stream));
     if (f) {
-        ST_TRY(ensure_tmp(p, 1));
+        if (!hbuf) {
+            ST_TRY(ensure_tmp(p, 1));
+            hbuf = (T *)p->tmp[0];
+        }
         if (p->dense) {
-            HIP_TRY(launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, xin, (const T *)p->y, (T *)p->tmp[0],
+            HIP_TRY(launch_dense<T>(p->geom, p->prm, s, (const T *)p->d_pk, xin, (const T *)p->y, hbuf,
                                     p->d_vol, p->nz, DM_H, p->d_pr, p->stream));
             HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, p->geom.ty_dirs) * p->nz, 1, p->d_sum + NQE,
                                p->stream));
         } else {
-            HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, (T *)p->tmp[0], p->d_vol, p->nz, p->d_pr,
-                                p->stream));
+            HIP_TRY(launch_H<T>(p->geom, s, xin, (const T *)p->y, hbuf, p->d_vol, p->nz, p->d_pr, p->stream));
             HIP_TRY(launch_sum(p->d_pr, tiles_of(p->geom, p->geom.ty_aux) * p->nz, 1, p->d_sum + NQE,
                                p->stream));
         }
@@ -578,11 +584,12 @@ bd3mg_status eval_t(bd3mg_problem p, const T *xin, const T *qin, double *f, doub
     return BD3MG_OK;
 }
 
-bd3mg_status eval_at(bd3mg_problem p, const void *xin, const void *qin, double *f, double *gn)
+bd3mg_status eval_at(bd3mg_problem p, const void *xin, const void *qin, double *f, double *gn,
+                     void *hbuf = nullptr)
 {
     return p->prec == BD3MG_FP64
-               ? eval_t<double>(p, (const double *)xin, (const double *)qin, f, gn)
-               : eval_t<float>(p, (const float *)xin, (const float *)qin, f, gn);
+               ? eval_t<double>(p, (const double *)xin, (const double *)qin, f, gn, (double *)hbuf)
+               : eval_t<float>(p, (const float *)xin, (const float *)qin, f, gn, (float *)hbuf);
 }
 
 bd3mg_status ensure_ready(bd3mg_problem p)
@@ -704,6 +711,214 @@ bd3mg_status apply_t(bd3mg_problem p, int op, T *ti, T *to, T *tr, T *tr2 = null
 bd3mg_status validate_handle(bd3mg_problem p)
 {
     if (!p) return fail(BD3MG_ERR_ARG, "null problem handle");
+    return BD3MG_OK;
+}
+
+// Scratch buffers of the run loop: partial sums, per-block coefficients, the
+// stop-test control block and the stored directions.  bd3mg_run_noalloc
+// points them into the per-device scratch array for one call and restores
+// the problem's own afterwards.
+struct WorkBuffers {
+    double *pg, *pd, *pe, *pr, *u, *info, *sum;
+    bd3mg_problem_s::Ctl *ctl;
+    void *hd;
+};
+
+WorkBuffers work_of(bd3mg_problem p)
+{
+    return WorkBuffers{p->d_pg, p->d_pd, p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_hd};
+}
+
+void set_work(bd3mg_problem p, const WorkBuffers &w)
+{
+    p->d_pg = w.pg;
+    p->d_pd = w.pd;
+    p->d_pe = w.pe;
+    p->d_pr = w.pr;
+    p->d_u = w.u;
+    p->d_info = w.info;
+    p->d_sum = w.sum;
+    p->d_ctl = w.ctl;
+    p->d_hd = w.hd;
+}
+
+// Lay the run loop's scratch buffers of p out from base, each 256-byte
+// aligned, with the sizes of the problem's own (schedule built); returns the
+// bytes needed, and sets *w only when they fit in avail.
+size_t carve_work(bd3mg_problem p, char *base, size_t avail, WorkBuffers *w)
+{
+    const size_t nb = p->nsl.size();
+    const size_t nslot = (size_t)p->ntiles * p->nz;
+    const size_t sizes[9] = {
+        sizeof(bd3mg_problem_s::Ctl),
+        2 * nb * sizeof(double),
+        8 * nb * sizeof(double),
+        (NQE + 1) * sizeof(double),
+        (size_t)p->maxg * p->ntiles * NQG * sizeof(double),
+        (size_t)p->maxd * tiles_of(p->geom, 16) * NQD * sizeof(double),
+        nslot * NQE * sizeof(double),
+        nslot * sizeof(double),
+        2 * (size_t)p->hd_slots * p->nx * p->ny * p->esz,
+    };
+    size_t off[9], total = 0;
+    for (int i = 0; i < 9; ++i) {
+        off[i] = total;
+        total += (sizes[i] + 255) / 256 * 256;
+    }
+    if (total <= avail && w) {
+        w->ctl = (bd3mg_problem_s::Ctl *)(base + off[0]);
+        w->u = (double *)(base + off[1]);
+        w->info = (double *)(base + off[2]);
+        w->sum = (double *)(base + off[3]);
+        w->pg = (double *)(base + off[4]);
+        w->pd = (double *)(base + off[5]);
+        w->pe = (double *)(base + off[6]);
+        w->pr = (double *)(base + off[7]);
+        w->hd = base + off[8];
+    }
+    return total;
+}
+
+// The set-up of bd3mg_run without allocating: the schedule must be built
+// already; x^0 = y, the reference gradient norm and q are formed in place.
+bd3mg_status ensure_ready_noalloc(bd3mg_problem p)
+{
+    if (!p->psf_set) return fail(BD3MG_ERR_STATE, "the PSF is not set");
+    if (!p->data_set) return fail(BD3MG_ERR_STATE, "the data y is not set");
+    if (p->dense) return fail(BD3MG_ERR_STATE, "bd3mg_run_noalloc takes the separable PSF only");
+    if (!p->blocks_set) return fail(BD3MG_ERR_STATE, "blocks are not set");
+    if (p->sched_dirty)
+        return fail(BD3MG_ERR_STATE, "the schedule is not built (bd3mg_get_schedule builds it)");
+    if (!p->x_set) {
+        HIP_TRY(hipMemcpyAsync(p->x, p->y, p->N * p->esz, hipMemcpyDeviceToDevice, p->stream));
+        ST_TRY(zero_steps(p));
+        p->x_set = true;
+        p->q_stale = true;
+        p->sweeps_done = 0;
+    }
+    if (!p->gnorm_ref_valid) {
+        ST_TRY(refresh(p, p->y, p->q));
+        ST_TRY(eval_at(p, p->y, p->q, nullptr, &p->gnorm_ref));
+        p->gnorm_ref_valid = true;
+        p->q_stale = true;
+    }
+    if (p->q_stale) {
+        ST_TRY(refresh(p, p->x, p->q));
+        p->q_stale = false;
+    }
+    return BD3MG_OK;
+}
+
+// The run loop of bd3mg_run and bd3mg_run_noalloc.  noalloc: the set-up is
+// done in place (no scratch volume is taken), a stop is confirmed on q
+// rebuilt in place from x, and f at the end is formed in g (not read again
+// before the next gradient pass writes it).
+bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,
+                      bd3mg_result *res, bool noalloc)
+{
+    ST_TRY(validate_handle(p));
+    if (max_sweeps < 0) return fail(BD3MG_ERR_ARG, "max_sweeps < 0");
+    if (check_every < 0) return fail(BD3MG_ERR_ARG, "check_every < 0");
+    const bool checking = grad_rtol > 0.0 || check_every > 0;
+    if (grad_rtol > 0.0 && check_every == 0) check_every = max_sweeps > 0 ? max_sweeps : 1;
+    ST_TRY(noalloc ? ensure_ready_noalloc(p) : ensure_ready(p));
+    const double vol = (double)p->N * p->esz;
+    // The stop test runs on the device: a check that meets the tolerance
+    // raises a flag and every later pass returns without writing, so the host only
+    // waits once per chunk of sweeps.
+    constexpr int CHUNK = 16;
+    const bool stopping = grad_rtol > 0.0;
+    int *stop = stopping ? &p->d_ctl->stop : nullptr;
+    const double thr = stopping ? grad_rtol * p->gnorm_ref : -1.0;
+    HIP_TRY(hipMemsetAsync(p->d_ctl, 0, sizeof(bd3mg_problem_s::Ctl), p->stream));
+    HIP_TRY(hipEventRecord(p->ev0, p->stream));
+    const int cur0 = p->cur;
+    const long long sweeps0 = p->sweeps_done;
+    int done = max_sweeps;
+    bool conv = false;
+    bd3mg_problem_s::Ctl ctl{0, 0, NAN};
+    for (int s = 0; s < max_sweeps;) {
+        const int end = std::min(max_sweeps, s + CHUNK);
+        for (; s < end; ++s) {
+            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile, stop));
+            p->cur ^= 1;
+            const long long sw = sweeps0 + s + 1;
+            if (p->refresh_every > 0 && (sw % p->refresh_every) == 0) {
+                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 3.0 * vol));
+                ST_TRY(refresh(p, p->x, p->q, stop));
+                ST_TRY(prof_end(p));
+            }
+            if (checking && (((s + 1) % check_every) == 0 || s + 1 == max_sweeps)) {
+                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol));
+                ST_TRY(check(p, thr, s + 1, stop));
+                ST_TRY(prof_end(p));
+            }
+        }
+        if (checking) {
+            HIP_TRY(hipMemcpyAsync(&ctl, p->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, p->stream));
+            HIP_TRY(hipStreamSynchronize(p->stream));
+            if (ctl.stop) {
+                // The device test read the maintained residual q, which drifts
+                // from XY^T (H x - y) by rounding between refreshes.  Confirm
+                // on a residual rebuilt from x (a scratch volume, so the
+                // state and the bitwise equality of chained runs are kept);
+                // if the rebuilt gradient is still above the threshold, take
+                // the rebuilt residual as q and continue from the stop sweep.
+                const int ss = ctl.stop_sweep;
+                p->cur = cur0 ^ (ss & 1);
+                double gfresh = 0.0;
+                void *qf = p->q;  // rebuilt in place when nothing may be allocated
+                if (!noalloc) {
+                    ST_TRY(ensure_tmp(p, 2));
+                    qf = p->tmp[1];
+                }
+                ST_TRY(refresh(p, p->x, qf));
+                ST_TRY(eval_at(p, p->x, qf, nullptr, &gfresh));
+                if (gfresh <= thr) {
+                    done = ss;
+                    conv = true;
+                    break;
+                }
+                if (qf != p->q)
+                    HIP_TRY(hipMemcpyAsync(p->q, qf, vol, hipMemcpyDeviceToDevice, p->stream));
+                HIP_TRY(hipMemsetAsync(p->d_ctl, 0, sizeof(bd3mg_problem_s::Ctl), p->stream));
+                ctl = bd3mg_problem_s::Ctl{0, 0, gfresh};
+                s = ss;
+                if (ss >= max_sweeps) break;
+            }
+        }
+        if (p->pending.size() > 4096) ST_TRY(prof_collect(p));
+    }
+    p->cur = cur0 ^ (done & 1);
+    p->sweeps_done = sweeps0 + done;
+    HIP_TRY(hipEventRecord(p->ev1, p->stream));
+    double gn = ctl.gnorm, f = NAN;
+    if (checking) {
+        // f and ||grad f|| of the returned x from a residual rebuilt from x
+        if (noalloc) {
+            ST_TRY(refresh(p, p->x, p->q));
+            ST_TRY(eval_at(p, p->x, p->q, &f, &gn, p->g));
+        } else {
+            ST_TRY(ensure_tmp(p, 2));
+            ST_TRY(refresh(p, p->x, p->tmp[1]));
+            ST_TRY(eval_at(p, p->x, p->tmp[1], &f, &gn));
+        }
+    }
+    HIP_TRY(hipEventSynchronize(p->ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    ST_TRY(prof_collect(p));
+    if (res) {
+        res->sweeps = done;
+        res->converged = conv ? 1 : 0;
+        res->f = f;
+        res->grad_norm = gn;
+        res->grad_norm_ref = p->gnorm_ref;
+        res->seconds = ms * 1e-3;
+    }
+    if (grad_rtol > 0.0 && !conv)
+        return fail(BD3MG_ERR_NOT_CONVERGED, "||grad f|| / ||grad f(y)|| = %.3e after %d sweeps",
+                    gn / p->gnorm_ref, done);
     return BD3MG_OK;
 }
 
@@ -1112,100 +1327,30 @@ bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device)
 bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,
                        bd3mg_result *res)
 {
+    return run_impl(p, max_sweeps, grad_rtol, check_every, res, false);
+}
+
+bd3mg_status bd3mg_run_noalloc(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,
+                               bd3mg_result *res)
+{
     ST_TRY(validate_handle(p));
-    if (max_sweeps < 0) return fail(BD3MG_ERR_ARG, "max_sweeps < 0");
-    if (check_every < 0) return fail(BD3MG_ERR_ARG, "check_every < 0");
-    const bool checking = grad_rtol > 0.0 || check_every > 0;
-    if (grad_rtol > 0.0 && check_every == 0) check_every = max_sweeps > 0 ? max_sweeps : 1;
-    ST_TRY(ensure_ready(p));
-    const double vol = (double)p->N * p->esz;
-    // The stop test runs on the device: a check that meets the tolerance
-    // raises a flag and every later pass returns without writing, so the host only
-    // waits once per chunk of sweeps.
-    constexpr int CHUNK = 16;
-    const bool stopping = grad_rtol > 0.0;
-    int *stop = stopping ? &p->d_ctl->stop : nullptr;
-    const double thr = stopping ? grad_rtol * p->gnorm_ref : -1.0;
-    HIP_TRY(hipMemsetAsync(p->d_ctl, 0, sizeof(bd3mg_problem_s::Ctl), p->stream));
-    HIP_TRY(hipEventRecord(p->ev0, p->stream));
-    const int cur0 = p->cur;
-    const long long sweeps0 = p->sweeps_done;
-    int done = max_sweeps;
-    bool conv = false;
-    bd3mg_problem_s::Ctl ctl{0, 0, NAN};
-    for (int s = 0; s < max_sweeps;) {
-        const int end = std::min(max_sweeps, s + CHUNK);
-        for (; s < end; ++s) {
-            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile, stop));
-            p->cur ^= 1;
-            const long long sw = sweeps0 + s + 1;
-            if (p->refresh_every > 0 && (sw % p->refresh_every) == 0) {
-                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 3.0 * vol));
-                ST_TRY(refresh(p, p->x, p->q, stop));
-                ST_TRY(prof_end(p));
-            }
-            if (checking && (((s + 1) % check_every) == 0 || s + 1 == max_sweeps)) {
-                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol));
-                ST_TRY(check(p, thr, s + 1, stop));
-                ST_TRY(prof_end(p));
-            }
-        }
-        if (checking) {
-            HIP_TRY(hipMemcpyAsync(&ctl, p->d_ctl, sizeof(ctl), hipMemcpyDeviceToHost, p->stream));
-            HIP_TRY(hipStreamSynchronize(p->stream));
-            if (ctl.stop) {
-                // The device test read the maintained residual q, which drifts
-                // from XY^T (H x - y) by rounding between refreshes.  Confirm
-                // on a residual rebuilt from x (a scratch volume, so the
-                // state and the bitwise equality of chained runs are kept);
-                // if the rebuilt gradient is still above the threshold, take
-                // the rebuilt residual as q and continue from the stop sweep.
-                const int ss = ctl.stop_sweep;
-                p->cur = cur0 ^ (ss & 1);
-                double gfresh = 0.0;
-                ST_TRY(ensure_tmp(p, 2));
-                ST_TRY(refresh(p, p->x, p->tmp[1]));
-                ST_TRY(eval_at(p, p->x, p->tmp[1], nullptr, &gfresh));
-                if (gfresh <= thr) {
-                    done = ss;
-                    conv = true;
-                    break;
-                }
-                HIP_TRY(hipMemcpyAsync(p->q, p->tmp[1], vol, hipMemcpyDeviceToDevice, p->stream));
-                HIP_TRY(hipMemsetAsync(p->d_ctl, 0, sizeof(bd3mg_problem_s::Ctl), p->stream));
-                ctl = bd3mg_problem_s::Ctl{0, 0, gfresh};
-                s = ss;
-                if (ss >= max_sweeps) break;
-            }
-        }
-        if (p->pending.size() > 4096) ST_TRY(prof_collect(p));
-    }
-    p->cur = cur0 ^ (done & 1);
-    p->sweeps_done = sweeps0 + done;
-    HIP_TRY(hipEventRecord(p->ev1, p->stream));
-    double gn = ctl.gnorm, f = NAN;
-    if (checking) {
-        // f and ||grad f|| of the returned x from a residual rebuilt from x
-        ST_TRY(ensure_tmp(p, 2));
-        ST_TRY(refresh(p, p->x, p->tmp[1]));
-        ST_TRY(eval_at(p, p->x, p->tmp[1], &f, &gn));
-    }
-    HIP_TRY(hipEventSynchronize(p->ev1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-    ST_TRY(prof_collect(p));
-    if (res) {
-        res->sweeps = done;
-        res->converged = conv ? 1 : 0;
-        res->f = f;
-        res->grad_norm = gn;
-        res->grad_norm_ref = p->gnorm_ref;
-        res->seconds = ms * 1e-3;
-    }
-    if (grad_rtol > 0.0 && !conv)
-        return fail(BD3MG_ERR_NOT_CONVERGED, "||grad f|| / ||grad f(y)|| = %.3e after %d sweeps",
-                    gn / p->gnorm_ref, done);
-    return BD3MG_OK;
+    if (!p->blocks_set || p->sched_dirty || p->dense || !p->psf_set || !p->data_set)
+        return ensure_ready_noalloc(p);  // fails, naming what is missing
+    void *base = nullptr;
+    HIP_TRY(scratch_base(p->device, &base));
+    WorkBuffers w{};
+    const size_t need = carve_work(p, (char *)base, SCRATCH_BYTES, &w);
+    if (need > SCRATCH_BYTES)
+        return fail(BD3MG_ERR_ARG, "this problem needs %zu bytes of scratch; bd3mg_run_noalloc has %zu",
+                    need, SCRATCH_BYTES);
+    const WorkBuffers own = work_of(p);
+    const bool prof = p->profile;
+    set_work(p, w);
+    p->profile = false;  // event records would create events
+    const bd3mg_status st = run_impl(p, max_sweeps, grad_rtol, check_every, res, true);
+    p->profile = prof;
+    set_work(p, own);
+    return st;
 }
 
 bd3mg_status bd3mg_get_x(bd3mg_problem p, void *x, int on_device)

@@ -191,6 +191,12 @@ hipError_t launch_check(const double *partials, int nslot, double thr, int sweep
 // Fixed-order sum of nslot slots of nq doubles into out[nq].
 hipError_t launch_sum(const double *partials, int nslot, int nq, double *out, hipStream_t st);
 
+// Bytes of the per-device scratch array of bd3mg_run_noalloc, and its device
+// address on a device (taken once per device with hipGetSymbolAddress, that
+// device current; later calls return the cached address).
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+hipError_t scratch_base(int device, void **ptr);
+
 // Streaming copy of n 16-byte words (bandwidth probe).
 hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st);
 

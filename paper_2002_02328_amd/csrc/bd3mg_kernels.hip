@@ -24,6 +24,8 @@
 // fixed DPP sum per wavefront, the four wavefronts in order, then the slots of a
 // block in slot order (k_solve) -- a fixed order, so runs are bitwise
 // reproducible.
+#include <mutex>
+
 #include "bd3mg_internal.h"
 
 namespace bd3mg {
@@ -1591,6 +1593,44 @@ hipError_t launch_dense_update(const Geom &g, const DevState<T> &s, const Item *
     const int gx = (int)std::min<size_t>((S + 4 * NT - 1) / (4 * NT), 1024);
     hipLaunchKernelGGL(k_dense_update<T>, dim3(gx, 1, nitems), dim3(NT), 0, st, g, s, items, pairs, u);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch memory of the entry point that allocates nothing
+// (bd3mg_run_noalloc): its partial sums, per-block coefficients, stop-test
+// control block and stored directions H d1, H d2 are carved from this array
+// instead of from buffers of the problem.  Each GPU the library runs on holds
+// its own copy, at its own address, until the process ends.  In host code the
+// array's name is not a device address: only the pointer returned by
+// scratch_base is passed to kernels and copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+hipError_t scratch_base(int device, void **ptr)
+{
+    constexpr int MAXDEV = 64;
+    static std::mutex mu;
+    static void *base[MAXDEV] = {};
+    if (device < 0 || device >= MAXDEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!base[device]) {
+        // once per device, with that device current
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        base[device] = p;
+    }
+    *ptr = base[device];
+    return hipSuccess;
 }
 
 #define BD3MG_INSTANTIATE(T)                                                                      \

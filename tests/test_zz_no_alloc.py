@@ -1,0 +1,84 @@
+"""bd3mg_run_noalloc, the entry point that allocates nothing (for callers that
+cannot allocate device memory), against bd3mg_run on the same problem.
+
+It runs the same kernels in the same order with its scratch buffers taken
+from the library's fixed per-device array, so iterates, previous steps, stop
+sweeps, f and ||grad f|| are expected bitwise equal to bd3mg_run's.  Two
+calls in a row on different problems, the second smaller, check that nothing
+left in the shared array by the first call is read by the second."""
+import numpy as np
+import pytest
+
+from paper_2002_02328_amd import binding
+from gpu_common import pair
+
+pytestmark = pytest.mark.gpu
+
+CASES = [((16, 45, 130), [3, 2, 4, 1, 6], 21, 5), ((6, 21, 67), [2, 1, 3], 22, 3)]
+
+
+def _twin(orc, shape, nsl, seed, kz, prec):
+    a, _, _ = pair(orc, shape, prec, seed=seed, kx=5, ky=3, kz=kz, lam=0.02, delta=0.03, eta=0.2,
+                   nslices=nsl)
+    b, _, _ = pair(orc, shape, prec, seed=seed, kx=5, ky=3, kz=kz, lam=0.02, delta=0.03, eta=0.2,
+                   nslices=nsl)
+    for p in (a, b):
+        p.get_schedule()  # builds the schedule (the entry point that allocates nothing needs it)
+        p.set_x0(None)
+    return a, b
+
+
+def _same(a, b):
+    assert np.array_equal(a.get_x(), b.get_x())
+    assert np.array_equal(a.get_dprev(), b.get_dprev())
+
+
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
+def test_noalloc_equals_run_on_two_calls_the_second_smaller(orc, prec):
+    for shape, nsl, seed, kz in CASES:  # the second case is the smaller input
+        print("run_noalloc vs run: shape", shape, "blocks", nsl, "precision", prec, flush=True)
+        a, b = _twin(orc, shape, nsl, seed, kz, prec)
+        ra = a.run(12, check_every=0)
+        rb = b.run_noalloc(12, check_every=0)
+        assert rb["sweeps"] == ra["sweeps"] == 12
+        _same(a, b)
+        # the problem's own buffers are back in use afterwards, state intact
+        a.run(4, check_every=0)
+        b.run(4, check_every=0)
+        _same(a, b)
+        # with a tolerance: device checks, a stop confirmed on a rebuilt
+        # residual (kept as q by the entry point that allocates nothing, so
+        # only the results of this call are compared)
+        ra = a.run(3000, grad_rtol=1e-3, check_every=1)
+        rb = b.run_noalloc(3000, grad_rtol=1e-3, check_every=1)
+        assert ra["converged"] and rb["converged"]
+        assert rb["sweeps"] == ra["sweeps"]
+        assert rb["f"] == ra["f"] and rb["grad_norm"] == ra["grad_norm"]
+        assert rb["grad_norm_ref"] == ra["grad_norm_ref"]
+        _same(a, b)
+        a.close()
+        b.close()
+
+
+def test_noalloc_refuses_what_it_cannot_do_without_allocating(orc):
+    g, _, _ = pair(orc, (6, 21, 67), binding.FP64, seed=3, kz=3, nslices=[2, 1, 3])
+    with pytest.raises(binding.Bd3mgError) as e:  # the schedule is not built yet
+        g.run_noalloc(2)
+    assert e.value.status == binding.ERR_STATE
+    g.get_schedule()
+    g.run_noalloc(2)
+    g.close()
+    # stored directions of 154 slices of 256 x 256 doubles (161 MB) exceed the array
+    nz, ny, nx = 64, 256, 256
+    big = binding.Problem(nx, ny, nz, binding.FP64)
+    big.set_psf_gaussian(5, 7, np.linspace(0.5, 2.0, nz), np.linspace(1.0, 2.0, nz))
+    big.set_params(0.01, 0.02, 0.01)
+    big.set_data(np.zeros((nz, ny, nx)))
+    big.set_blocks([4] * 16, binding.SCHED_ROUND)
+    big.get_schedule()
+    with pytest.raises(binding.Bd3mgError) as e:
+        big.run_noalloc(1)
+    assert e.value.status == binding.ERR_ARG
+    assert "scratch" in str(e.value)
+    big.run(1)  # the allocating entry point still serves it
+    big.close()
