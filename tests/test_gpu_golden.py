@@ -16,7 +16,16 @@ and rounded to FP32 once.
   where the TV weight is small), and the FP64 run stopped at the same 1e-6 is
   8.1e-4 from x*; reaching 1e-5 takes a gradient tolerance near 1e-8, below
   the FP32 floor (||grad f(fl32(x*))|| = 3.9e-7 ||grad f(y)||).  The FP32 bound
-  on x is 2e-3, 2.5x the FP64 distance at the same tolerance.
+  on x at the stop is 1e-3 (measured 5.5e-4 coloured, 7.3e-4 in rounds; the
+  FP64 iterate at the same gradient ratio is 5.5e-4 from x*).
+* FP64 trajectory: x* is the oracle's iterate after its last recorded sweep
+  count; the GPU's FP64 iterate after the same number of sweeps equals it
+  within 1e-12 (rounding order only; measured about 1e-15).
+* FP32 floor, run far past the 1e-6 stop (13500 sweeps, where FP64 reaches
+  1e-9): the gradient ratio stays near the rounding floor (measured 4.5e-7,
+  bound 2x the stored floor) and x stays 2.4e-4 from x* (bound 4e-4; 2.1e-4
+  after 20000 sweeps): single precision storage cannot reach the 1e-5
+  target on x, whatever the sweep count; f is within 1e-9 of f*.
 """
 import json
 import os
@@ -54,7 +63,9 @@ def data(golden):
     return w, gxy, gz, y
 
 
-def solve(data, prec, schedule, tol):
+def solve(data, prec, schedule, tol, sweeps=40000):
+    """Run to the tolerance (tol > 0) or exactly `sweeps` sweeps (tol = 0,
+    then f and ||grad f|| are evaluated at the end)."""
     w, gxy, gz, y = data
     nz, ny, nx = w.shape
     g = binding.Problem(nx, ny, nz, prec)
@@ -63,7 +74,10 @@ def solve(data, prec, schedule, tol):
     g.set_data(y.astype(g.dtype))
     g.set_blocks(w.nslices, schedule)
     g.set_x0(None)
-    res = g.run(40000, grad_rtol=tol, check_every=1)
+    if tol > 0:
+        res = g.run(sweeps, grad_rtol=tol, check_every=1)
+    else:
+        res = g.run(sweeps, check_every=sweeps)
     x = g.get_x().astype(np.float64).ravel()
     g.close()
     return res, x
@@ -100,4 +114,22 @@ def test_fp32_stop_tolerance_against_oracle_minimiser(golden, data, schedule):
     print("FP32 schedule %d to 1e-6: %d sweeps, |x - x*| / |x*| = %.3e, |f - f*| / f* = %.3e"
           % (schedule, res["sweeps"], ex, ef))
     assert ef <= 1e-7
-    assert ex <= 2e-3
+    assert ex <= 1e-3
+
+
+def test_fp64_trajectory_equals_the_oracle_run(golden, data):
+    res, x = solve(data, binding.FP64, binding.SCHED_COLORED, 0.0, sweeps=golden["sweeps"])
+    ex, ef = errors(golden, res, x)
+    print("FP64, %d sweeps: |x - x_oracle| / |x_oracle| = %.3e" % (golden["sweeps"], ex))
+    assert ex <= 1e-12 and ef <= 1e-13
+
+
+def test_fp32_floor_far_past_the_stop_tolerance(golden, data):
+    res, x = solve(data, binding.FP32, binding.SCHED_COLORED, 0.0, sweeps=13500)
+    ex, ef = errors(golden, res, x)
+    gr = res["grad_norm"] / golden["grad_ref"]
+    print("FP32, 13500 sweeps: ||grad f|| / ||grad f(y)|| = %.3e, |x - x*| / |x*| = %.3e, "
+          "|f - f*| / f* = %.3e" % (gr, ex, ef))
+    assert gr <= 2 * golden["fp32_floor_grad_ratio"]
+    assert ex <= 4e-4
+    assert ef <= 1e-9
