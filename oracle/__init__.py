@@ -79,6 +79,8 @@ def lib():
         L.orc_lipschitz_bound.argtypes = [P]
         L.orc_lipschitz_bound.restype = C.c_double
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         L.orcnet_num_params.argtypes = [C.c_int, C.c_int]
         L.orcnet_num_params.restype = C.c_size_t
         L.orcnet_round_bf16.argtypes = [C.c_double]
@@ -100,6 +102,11 @@ def _ptr(a):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (OpenMP)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def gauss_table(sigma, k: int) -> np.ndarray:

@@ -81,6 +81,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads used by later calls (timing the oracle on one core or on all). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Reusable zero-filled scratch volumes.  A buffer handed out by scratch_get
  * is all zeros; its user zeroes the slices it wrote before scratch_put, so the
  * oracle does not clear whole volumes on every block update.  (Storage only:

@@ -17,8 +17,8 @@ NET_SRC = os.path.join(ROOT, "oracle", "convnet_oracle.c")
 MUTATIONS = {
     "box-gradient-factor": ("acc += 2.0 * p->eta * (x[v]", "acc += 1.0 * p->eta * (x[v]"),
     "box-curvature-factor": ("return quad + 2.0 * p->eta * box", "return quad + 1.0 * p->eta * box"),
-    "tv-adjoint-sign": ("if (i >= 1) tv += omega_at(p, x, k, j, i - 1)",
-                        "if (i >= 1) tv -= omega_at(p, x, k, j, i - 1)"),
+    "tv-adjoint-sign": ("if (i >= 1) tv += omega_at(p, x, k, j, i - 1) * dX(p, x, k, j, i - 1);",
+                        "if (i >= 1) tv -= omega_at(p, x, k, j, i - 1) * dX(p, x, k, j, i - 1);"),
     "tv-adjoint-weight-index": ("if (j >= 1) tv += omega_at(p, x, k, j - 1, i) * dY(p, x, k, j - 1, i);",
                                 "if (j >= 1) tv += omega_at(p, x, k, j, i) * dY(p, x, k, j - 1, i);"),
     "tv-curvature-drops-y": ("s += w * (dX(p, u, k, j, i) * dX(p, v, k, j, i) + dY(p, u, k, j, i) * dY(p, v, k, j, i));",
@@ -32,7 +32,8 @@ MUTATIONS = {
     "pinv-offdiagonal-sign": ("P[1] = -b12 / det;", "P[1] = b12 / det;"),
     "coloring-gap-off-by-one": ("if (gap < min_gap) { ok = 0; break; }",
                                 "if (gap < min_gap - 1) { ok = 0; break; }"),
-    "z-penalty-factor": ("acc += 2.0 * p->kappa * zz;", "acc += p->kappa * zz;"),
+    "z-penalty-factor": ("zz -= dZ(p, x, k, j, i);\n                    acc += 2.0 * p->kappa * zz;",
+                         "zz -= dZ(p, x, k, j, i);\n                    acc += p->kappa * zz;"),
     "inflation-dropped": ("B[0] += p->mu * dot_slices(p, d1, d1, z0, z0 + n);",
                           "B[0] += 0.0 * dot_slices(p, d1, d1, z0, z0 + n);"),
     "round-applies-in-sequence": ("            block_direction(p, x, dprev, z0, nslices[b], dn, NULL);\n",
