@@ -6,20 +6,36 @@ direction, 2x2 solve and update passes for each colour of blocks) over the
 phantom, depth-variant Gaussian PSF 7x7x7 (sigma_xy 0.5 -> 3.0, sigma_z 1 -> 2),
 noise 0.02, lambda = 0.01, delta = 0.02, eta = 0.01, 16 uneven blocks of 2..6
 slices.  Inputs are synthetic and seeded; the observation y = H xbar + noise
-is formed with the library's own H on the GPU.
+is formed by the library's H in FP64 with the PSF tables rounded to the
+storage precision, then rounded once (as the stored oracle minimiser's inputs
+are).
 
-Prints one JSON line: voxel-iterations/s over exactly --steps sweeps (after
---warmup untimed sweeps), the roofline figure of the dominant kernel (HIP
-events on the library's stream, algorithmic bytes from the library), the
-time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y and from the learned
-warm start x0 = y + net(y) (network inference inside the clock), the same
-under the asynchronous-round schedule, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+Prints one JSON line:
+* voxel-iterations/s over exactly --steps sweeps (after --warmup untimed sweeps);
+* the roofline of the dominant pass (most device time per sweep) against the
+  method's own bytes: per block voxel the gradient pass must read x, r and the
+  previous step and write g (4 words), the direction pass read g and the
+  previous step (2 words), the update pass read x, g, the previous step and r
+  and write x, the step and r (7 words); per launch, times the block voxels of
+  its colour, over its mean launch time from HIP events on the library's
+  stream (one event between consecutive launches); the sweep as a whole
+  against 11 words per voxel-sweep (44 B in FP32); the design's own bytes
+  (stored H d1, H d2 included) and the HBM traffic measured with counters
+  beside them;
+* the same for the 512x512x128 workload (20 sweeps), the case that does not
+  fit the last-level cache;
+* the time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y and from the
+  learned warm start x0 = y + net(y) (network inference inside the clock), and
+  the distance of the result to the FP64 oracle's minimiser (stored samples);
+* the same under asynchronous rounds, with the paper's majorant (outside
+  Assumption C) and with the inflation that Assumption C asks for;
+* the FP64 CPU oracle timed on a bounded sample, on all host cores and on one.
 """
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -34,6 +50,11 @@ BF16_PEAK_TFLOPS = 2500.0
 FP32_VALU_PEAK_TFLOPS = 157.3  # MI355X vector FP32 (FP64: 78.6)
 FP64_VALU_PEAK_TFLOPS = 78.6
 WEIGHTS = os.path.join(ROOT, "paper_2002_02328_amd", "weights", "warmstart_c16.bin")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "plain_fp32_256x256x64.json")
+# words the method must move per block voxel and pass (reads and writes of
+# x, r, g and the previous step), and per voxel-sweep
+METHOD_WORDS = {"grad": 4, "dirs": 2, "update": 7}
+SWEEP_WORDS = 11
 
 
 def net_flops(nvox, c=16):
@@ -52,16 +73,28 @@ def is_dense(w):
 
 
 def make_problem(binding, w):
+    """The workload's problem in its storage precision.  PSF tables rounded to
+    the storage type once; y = H xbar + noise formed in FP64 (the library's
+    H with those tables), then rounded once."""
     nz, ny, nx = w.shape
+    st = np.float64 if w.fp64 else np.float32
     g = binding.Problem(nx, ny, nz, binding.FP64 if w.fp64 else binding.FP32)
+    twin = binding.Problem(nx, ny, nz, binding.FP64)
     if is_dense(w):
         ps = w.extra["psf"]
-        g.set_psf_dense(binding.psf_rotated_gaussian(ps["sx"], ps["sy"], ps["theta"], ps["sz"], w.kxy, w.kz))
+        pk = binding.psf_rotated_gaussian(ps["sx"], ps["sy"], ps["theta"], ps["sz"], w.kxy, w.kz)
+        pk = pk.astype(st).astype(np.float64)
+        g.set_psf_dense(pk)
+        twin.set_psf_dense(pk)
     else:
-        g.set_psf_gaussian(w.kxy, w.kz, w.sigma_xy, w.sigma_z)
+        gxy = binding.psf_gaussian(w.sigma_xy, w.kxy).astype(st).astype(np.float64)
+        gz = binding.psf_gaussian(w.sigma_z, w.kz).astype(st).astype(np.float64)
+        g.set_psf_separable(gxy, gxy, gz)
+        twin.set_psf_separable(gxy, gxy, gz)
+    y = (twin.H(w.xbar) + w.noise).astype(st)  # degradation model y = H xbar + b
+    twin.close()
     g.set_params(w.lam, w.delta, w.eta, w.kappa)
-    y = g.H(w.xbar) + w.noise.astype(g.dtype)  # degradation model y = H xbar + b
-    g.set_data(y.astype(g.dtype))
+    g.set_data(y)
     g.set_blocks(w.nslices)
     return g
 
@@ -119,8 +152,103 @@ def measured_traffic(workload, variant):
     return rec["bytes_per_launch"].get(variant)
 
 
+def sweep_measurement(binding, w, steps, warmup):
+    """Problem of workload w, autotuned; sweeps per second over `steps` timed
+    sweeps, then the same number of sweeps again with every launch timed, and
+    the roofline figures of the dominant pass and of the whole sweep."""
+    nvox = int(np.prod(w.shape))
+    esz = 8 if w.fp64 else 4
+    g = make_problem(binding, w)
+    nc, order, color = g.get_schedule()
+    # tile heights picked by the autotuner on this problem (state is restored)
+    g.set_x0(None)
+    (td, tu), _ = g.autotune(5)
+    g.set_x0(None)
+    g.run(warmup, check_every=0)
+    t0 = time.perf_counter()
+    g.run(steps, check_every=0)  # returns after the device has finished
+    secs = time.perf_counter() - t0
+    ms_step = 1e3 * secs / steps
+
+    g.set_option(binding.OPT_PROFILE, 1)
+    g.run(steps, check_every=0)
+    prof = g.get_profile(reset=True)
+    g.set_option(binding.OPT_PROFILE, 0)
+    hot = {k: v for k, v in prof.items() if k != "eval" and v[0] > 0}
+    dom = max(hot, key=lambda k: hot[k][1])
+    variant = kernel_variant(w, dom, {"dirs": td, "update": tu})
+    kernels = {}
+    for k, (n, ms, by) in hot.items():
+        e = {"launches": n, "avg_us": 1e3 * ms / n, "design_bytes_per_launch": by / n,
+             "design_GBps": by / (ms * 1e-3) / 1e9}
+        if k in METHOD_WORDS:
+            mb = METHOD_WORDS[k] * esz * nvox * steps  # over all launches of the pass
+            e["method_bytes_per_launch"] = mb / n
+            e["method_GBps"] = mb / (ms * 1e-3) / 1e9
+            e["method_frac"] = e["method_GBps"] / HBM_PEAK_GBS
+        kernels[k] = e
+    n, ms, by = hot[dom]
+    sweep_bytes = SWEEP_WORDS * esz * nvox
+    sweep_gbs = sweep_bytes / (ms_step * 1e-3) / 1e9
+    if is_dense(w):
+        # the general-kernel passes are bound by vector arithmetic
+        fl = dense_flops(w, nc, color)
+        peak = FP64_VALU_PEAK_TFLOPS if w.fp64 else FP32_VALU_PEAK_TFLOPS
+        tf = fl[dom] / (ms * 1e-3 / steps) / 1e12 if dom in fl else 0.0
+        roof = {"bound": "alu", "kernel": dom, "variant": variant, "achieved": tf, "peak": peak,
+                "unit": "TFLOP/s", "frac": tf / peak, "traffic": measured_traffic(w.name, variant),
+                "avg_launch_us": 1e3 * ms / n, "flop_per_launch": fl.get(dom, 0.0) * steps / n,
+                "flop_per_sweep": fl}
+    else:
+        traffic = measured_traffic(w.name, variant)
+        kd = kernels[dom]
+        mbl = kd.get("method_bytes_per_launch", 0.0)
+        achieved = kd.get("method_GBps", 0.0)
+        roof = {"bound": "hbm", "kernel": dom, "variant": variant, "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": traffic, "avg_launch_us": kd["avg_us"],
+                "method_bytes_per_launch": mbl,
+                "method_words_per_block_voxel": METHOD_WORDS.get(dom),
+                "design_bytes_per_launch": kd["design_bytes_per_launch"],
+                "traffic_over_method": (traffic / mbl) if (traffic and mbl) else None,
+                "sweep": {"method_bytes_per_voxel": SWEEP_WORDS * esz, "achieved": sweep_gbs,
+                          "frac": sweep_gbs / HBM_PEAK_GBS,
+                          "design_bytes_per_voxel": sum(v[2] for v in hot.values()) / (nvox * steps)}}
+    info = {"workload": w.name, "value": nvox * steps / secs, "unit": "voxel-iterations/s",
+            "ms_per_step": ms_step, "colors": int(nc), "tile_rows": {"dirs": td, "update": tu},
+            "roofline": roof, "kernels": kernels}
+    return g, info
+
+
+def error_vs_oracle(res, x):
+    """Distance of a GPU result to the FP64 oracle's minimiser of the same
+    workload (stored: f* and x* at 4096 seeded voxels)."""
+    if not os.path.exists(GOLDEN):
+        return None
+    gold = json.load(open(GOLDEN))
+    idx = np.asarray(gold["sample_index"])
+    xs = np.asarray(gold["sample_x"])
+    xv = np.asarray(x, dtype=np.float64).ravel()
+    return {"x_rel": float(np.linalg.norm(xv[idx] - xs) / np.linalg.norm(xs)),
+            "f_rel": float(abs(res["f"] - gold["f_star"]) / abs(gold["f_star"])),
+            "reference": "FP64 oracle minimiser (||grad f|| <= 1e-9 ||grad f(y)||), x* at %d voxels"
+                         % len(idx)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, budget_s):
-    """FP64 oracle on the same workload: as many whole sweeps as fit the budget."""
+    """FP64 oracle on the same workload: as many whole sweeps as fit the budget,
+    on all the threads it is given, then on one thread (a quarter of the
+    budget, at least one sweep)."""
     import oracle
     if is_dense(w):
         ps = w.extra["psf"]
@@ -133,30 +261,39 @@ def cpu_baseline(w, budget_s):
         y = oracle.Problem(np.zeros(w.shape), gxy, gxy, gz).H(w.xbar) + w.noise
         o = oracle.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
     nc, order, _ = oracle.color_schedule(w.nslices, 2 * (w.kz // 2))
-    x = y.copy()
-    d = np.zeros(w.shape)
-    t0 = time.perf_counter()
-    o.run(x, d, w.nslices, order, 1, history=False)
-    t1 = time.perf_counter()
-    per = t1 - t0
-    more = max(0, int(budget_s / per) - 1)
-    if more:
-        o.run(x, d, w.nslices, order, more, history=False)
-    t2 = time.perf_counter()
-    sweeps = 1 + more
     nvox = int(np.prod(w.shape))
-    return {"value": nvox * sweeps / (t2 - t0), "unit": "voxel-iterations/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d sweeps of the %s workload from x0 = y (FP64, coloured order)"
-                      % (sweeps, w.name),
-            "seconds": t2 - t0}
+
+    def timed(budget):
+        x = y.copy()
+        d = np.zeros(w.shape)
+        t0 = time.perf_counter()
+        o.run(x, d, w.nslices, order, 1, history=False)
+        per = time.perf_counter() - t0
+        more = max(0, int(budget / per) - 1)
+        if more:
+            o.run(x, d, w.nslices, order, more, history=False)
+        return 1 + more, time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    sweeps, secs = timed(budget_s)
+    oracle.set_num_threads(1)
+    s1, t1 = timed(budget_s / 4)
+    oracle.set_num_threads(threads)
+    return {"value": nvox * sweeps / secs, "unit": "voxel-iterations/s",
+            "cores": threads, "kind": "oracle",
+            "sample": "%d sweeps of the %s workload from x0 = y (FP64, coloured order)" % (sweeps, w.name),
+            "seconds": secs, "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+            "one_core": {"value": nvox * s1 / t1, "sweeps": s1, "seconds": t1}}
 
 
 def round_schedule(binding, w, args):
     """The same workload under asynchronous rounds (every block steps from one
-    snapshot; one gradient, direction, solve and update launch per sweep) with
-    the paper's majorant (no inflation): sweep throughput, per-kernel device
-    time, and time to the tolerance from x0 = y and from the warm start."""
+    snapshot; one gradient, direction, solve and update launch per sweep):
+    sweep throughput and per-kernel device time with the paper's majorant
+    (mu = 0, outside Assumption C: nothing guarantees descent), time to the
+    tolerance from x0 = y and from the warm start, and the run with the
+    curvature inflation mu = L (2 sqrt(tau) + 1), tau = B - 1, under which
+    Assumption C holds."""
     nvox = int(np.prod(w.shape))
     r = make_problem(binding, w)
     r.set_blocks(w.nslices, binding.SCHED_ROUND)
@@ -171,30 +308,38 @@ def round_schedule(binding, w, args):
     r.run(args.steps, check_every=0)
     prof = r.get_profile(reset=True)
     r.set_option(binding.OPT_PROFILE, 0)
-    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
-                   "GB/s": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
+    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1)}
                for k, v in prof.items() if v[0] > 0 and k != "eval"}
+    L = r.lipschitz_bound()
     out = {"value": nvox * args.steps / secs, "unit": "voxel-iterations/s",
-           "ms_per_step": 1e3 * secs / args.steps, "mu": 0.0, "tile_rows": {"dirs": td, "update": tu},
-           "kernels": kernels, "lipschitz_bound": r.lipschitz_bound()}
+           "ms_per_step": 1e3 * secs / args.steps, "mu": 0.0,
+           "assumption_c": "not satisfied at mu = 0 (paper's majorant); convergence is not guaranteed",
+           "tile_rows": {"dirs": td, "update": tu}, "kernels": kernels, "lipschitz_bound": L}
     if not args.no_tol:
-        def to_tol(net):
+        def to_tol(net, tol, max_sweeps):
             r.set_x0(None)
             t0 = time.perf_counter()
             if net is not None:
                 net.infer(r)
-            res = r.run(args.max_sweeps_to_tol, grad_rtol=args.tol, check_every=1)
+            res = r.run(max_sweeps, grad_rtol=tol, check_every=1)
             return {"seconds": time.perf_counter() - t0, "sweeps": res["sweeps"],
                     "converged": bool(res["converged"]), "grad_rel": res["grad_norm"] / res["grad_norm_ref"],
-                    "f": res["f"], "tol": args.tol}
-        tt = {"plain_x0_y": to_tol(None), "warm_started": None}
+                    "f": res["f"], "tol": tol}
+        tt = {"plain_x0_y": to_tol(None, args.tol, args.max_sweeps_to_tol), "warm_started": None}
         if os.path.exists(WEIGHTS) and not is_dense(w):
             net = binding.Net()
             net.load(open(WEIGHTS, "rb").read())
             net.infer(r)
-            tt["warm_started"] = to_tol(net)
+            tt["warm_started"] = to_tol(net, args.tol, args.max_sweeps_to_tol)
             net.close()
         out["time_to_tol"] = tt
+        # Assumption C: inflation mu >= L (2 sqrt(tau) + 1) with tau = B - 1
+        tau = len(w.nslices) - 1
+        mu = L * (2.0 * np.sqrt(tau) + 1.0)
+        r.set_inflation(mu)
+        inf = to_tol(None, 1e-4, args.inflated_sweeps)
+        r.set_inflation(0.0)
+        out["inflated"] = {"mu": mu, "tau": tau, "time_to_1e-4": inf}
     r.close()
     return out
 
@@ -207,10 +352,14 @@ def main():
     ap.add_argument("--workload", default="plain-fp32-256x256x64")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-sweeps-to-tol", type=int, default=20000)
+    ap.add_argument("--inflated-sweeps", type=int, default=4000,
+                    help="sweep cap of the inflated round run (to 1e-4)")
     ap.add_argument("--no-tol", action="store_true", help="skip the time-to-tolerance run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--no-round", action="store_true", help="skip the asynchronous-round schedule")
+    ap.add_argument("--no-large", action="store_true", help="skip the 512x512x128 sub-line")
+    ap.add_argument("--large-steps", type=int, default=20)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -221,62 +370,19 @@ def main():
     from paper_2002_02328_amd import binding, inputs
     w = inputs.WORKLOADS[args.workload]()
     nvox = int(np.prod(w.shape))
-    g = make_problem(binding, w)
-    nc, order, color = g.get_schedule()
-
-    # tile heights picked by the autotuner on this problem (state is restored)
-    g.set_x0(None)
-    (td, tu), tuned_ms = g.autotune(5)
-
-    # timed sweeps
-    g.set_x0(None)
-    g.run(args.warmup, check_every=0)
-    t0 = time.perf_counter()
-    g.run(args.steps, check_every=0)  # returns after the device has finished
-    t1 = time.perf_counter()
-    secs = t1 - t0
-    value = nvox * args.steps / secs
-
-    # per-kernel device time over the same number of sweeps, events on the library's stream
-    g.set_option(binding.OPT_PROFILE, 1)
-    g.run(args.steps, check_every=0)
-    prof = g.get_profile(reset=True)
-    g.set_option(binding.OPT_PROFILE, 0)
-    hot = {k: v for k, v in prof.items() if k != "eval" and v[0] > 0}
-    dom = max(hot, key=lambda k: hot[k][1])
-    variant = kernel_variant(w, dom, {"dirs": td, "update": tu})
-    n, ms, by = hot[dom]
-    achieved = by / (ms * 1e-3) / 1e9
-    if is_dense(w):
-        # the general-kernel passes are bound by vector arithmetic
-        fl = dense_flops(w, nc, color)
-        peak = FP64_VALU_PEAK_TFLOPS if w.fp64 else FP32_VALU_PEAK_TFLOPS
-        tf = fl[dom] / (ms * 1e-3 / args.steps) / 1e12 if dom in fl else 0.0
-        roof = {"bound": "alu", "kernel": dom, "variant": variant, "achieved": tf, "peak": peak,
-                "unit": "TFLOP/s", "frac": tf / peak, "traffic": measured_traffic(w.name, variant),
-                "avg_launch_us": 1e3 * ms / n, "flop_per_launch": fl.get(dom, 0.0) * args.steps / n,
-                "flop_per_sweep": fl}
-    else:
-        roof = {"bound": "hbm", "kernel": dom, "variant": variant, "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(w.name, variant),
-                "avg_launch_us": 1e3 * ms / n, "bytes_per_launch": by / n}
-    kernels = {k: {"launches": v[0], "avg_us": 1e3 * v[1] / max(v[0], 1),
-                   "GB/s": (v[2] / (v[1] * 1e-3) / 1e9) if v[1] > 0 else None}
-               for k, v in prof.items() if v[0] > 0}
-    total_ms = sum(v[1] for v in hot.values())
-    all_bytes = sum(v[2] for v in hot.values())
-
+    g, main_info = sweep_measurement(binding, w, args.steps, args.warmup)
+    nc = main_info["colors"]
+    td, tu = main_info["tile_rows"]["dirs"], main_info["tile_rows"]["update"]
     probe_gbs, _ = binding.probe_copy(4 << 30, 5)
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main_info["value"],
         "unit": "voxel-iterations/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * secs / args.steps,
+        "ms_per_step": main_info["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -287,9 +393,8 @@ def main():
                    "blocks": int(len(w.nslices)), "colors": int(nc),
                    "reductions": "f64", "step": "one sweep (every block updated once)",
                    "tile_rows": {"dirs": td, "update": tu}},
-        "roofline": roof,
-        "kernels": kernels,
-        "sweep_algorithmic_GBps": all_bytes / (total_ms * 1e-3) / 1e9,
+        "roofline": main_info["roofline"],
+        "kernels": main_info["kernels"],
         "copy_probe_GBps": probe_gbs,
     }
 
@@ -307,8 +412,11 @@ def main():
                 net.infer(g)  # x0 = y + net(y), inside the clock
             res = g.run(args.max_sweeps_to_tol, grad_rtol=tol, check_every=1)
             t1 = time.perf_counter()
-            return {"seconds": t1 - t0, "sweeps": res["sweeps"], "converged": bool(res["converged"]),
+            out_ = {"seconds": t1 - t0, "sweeps": res["sweeps"], "converged": bool(res["converged"]),
                     "grad_rel": res["grad_norm"] / res["grad_norm_ref"], "f": res["f"], "tol": tol}
+            if w.name == "plain-fp32-256x256x64":
+                out_["error_vs_oracle"] = error_vs_oracle(res, g.get_x())
+            return out_
 
         tt = {"plain_x0_y": to_tol(args.tol, False), "warm_started": None}
         if net is not None:
@@ -329,9 +437,21 @@ def main():
                                "flop": flop, "weights": os.path.relpath(WEIGHTS, ROOT)}
             net.close()
         out["time_to_tol"] = tt
+        ev = tt["plain_x0_y"].get("error_vs_oracle")
+        if ev is not None:
+            out["error_vs_oracle"] = dict(ev, at="plain run stopped at ||grad f|| <= %g ||grad f(y)||"
+                                          % args.tol)
+    g.close()
 
     if not args.no_round:
         out["round_schedule"] = round_schedule(binding, w, args)
+
+    if not args.no_large and w.name == "plain-fp32-256x256x64":
+        wl = inputs.WORKLOADS["plain-fp32-512x512x128"]()
+        gl, large = sweep_measurement(binding, wl, args.large_steps, 3)
+        gl.close()
+        large["steps"] = args.large_steps
+        out["large"] = large
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)

@@ -326,10 +326,12 @@ bd3mg_status bd3mg_get_profile(bd3mg_problem p, long long *launches, double *ms,
                                int reset);
 
 /* Attainable device-memory bandwidth: copies a buffer of the given size
- * (rounded down to 16 B) with a plain streaming copy kernel, iters times on
- * the current device, and reports the best launch as read + write bytes per
- * second (*gbps, GB/s) and its duration (*ms).  Allocates and frees its two
- * buffers.  ERR_ARG: bytes < 1 MiB or iters < 1. */
+ * (rounded down to 16 B) with a streaming copy kernel in four launch shapes
+ * (1, 4 or 8 loads of 16 B in flight per lane; 8 to 32 workgroups per
+ * compute unit), iters times each on the current device, and reports the
+ * best launch as read + write bytes per second (*gbps, GB/s) and its
+ * duration (*ms).  Allocates and frees its two buffers.  ERR_ARG: bytes <
+ * 1 MiB or iters < 1. */
 bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms);
 
 /* ---------------------------------------------------------------------------

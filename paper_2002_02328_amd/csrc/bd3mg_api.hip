@@ -115,12 +115,15 @@ struct bd3mg_problem_s {
     long long sweeps_done = 0;  // sweeps since x^0 (drives the refresh of q)
     long long refresh_every = 0;
 
-    // profiling: event pairs of the launches not yet folded into the totals
+    // profiling: start and end events of the launches not yet folded into
+    // the totals (a single-kernel pass: the kernel's own start and end
+    // timestamps; a pass of several kernels: events recorded around them)
     bool profile = false;
     struct Pending {
         int kind;
         double bytes;
         hipEvent_t a, b;
+        bool own;  // a, b are the kernel's own start and stop events
     };
     std::vector<Pending> pending;
     std::vector<hipEvent_t> event_pool;
@@ -203,13 +206,18 @@ hipEvent_t pool_event(bd3mg_problem p)
     return e;
 }
 
-// Record the start of a profiled launch (no-op unless profiling).
-bd3mg_status prof_begin(bd3mg_problem p, int kind, double bytes)
+// Start of a profiled pass (no-op unless profiling).  A pass of one kernel
+// hands its events to the launcher (hipExtLaunchKernelGGL timestamps the
+// kernel itself); a pass of several kernels records events around them.
+bd3mg_status prof_begin(bd3mg_problem p, int kind, double bytes, bool one_kernel = true)
 {
     if (!p->profile) return BD3MG_OK;
-    bd3mg_problem_s::Pending q{kind, bytes, pool_event(p), pool_event(p)};
+    bd3mg_problem_s::Pending q{kind, bytes, pool_event(p), pool_event(p), one_kernel};
     if (!q.a || !q.b) return fail(BD3MG_ERR_HIP, "event creation failed");
-    HIP_TRY(hipEventRecord(q.a, p->stream));
+    if (one_kernel)
+        g_launch_events = LaunchEvents{q.a, q.b};
+    else
+        HIP_TRY(hipEventRecord(q.a, p->stream));
     p->pending.push_back(q);
     return BD3MG_OK;
 }
@@ -217,7 +225,10 @@ bd3mg_status prof_begin(bd3mg_problem p, int kind, double bytes)
 bd3mg_status prof_end(bd3mg_problem p)
 {
     if (!p->profile) return BD3MG_OK;
-    HIP_TRY(hipEventRecord(p->pending.back().b, p->stream));
+    if (p->pending.back().own)
+        g_launch_events = LaunchEvents{};
+    else
+        HIP_TRY(hipEventRecord(p->pending.back().b, p->stream));
     return BD3MG_OK;
 }
 
@@ -627,7 +638,7 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
     if (p->dense) {
         // general kernels: H^T r and grad f on S, H d1 and H d2 on S +- r_z by
         // the dense kernels, r += u1 H d1 + u2 H d2 elementwise
-        if (prof) ST_TRY(prof_begin(p, BD3MG_K_GRAD, gr.bytes[0]));
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_GRAD, gr.bytes[0], false));
         HIP_TRY(dense_grad<T>(p, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK, p->d_pg, true));
         if (prof) ST_TRY(prof_end(p));
         if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
@@ -849,7 +860,7 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
                 ST_TRY(prof_end(p));
             }
             if (checking && (((s + 1) % check_every) == 0 || s + 1 == max_sweeps)) {
-                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol));
+                ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol, false));
                 ST_TRY(check(p, thr, s + 1, stop));
                 ST_TRY(prof_end(p));
             }
@@ -1575,15 +1586,17 @@ bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms)
     } else if (hipMemsetAsync(a, 0, n16 * 16, st) != hipSuccess) {
         rc = fail(BD3MG_ERR_HIP, "probe memset");
     } else {
-        for (int it = 0; it <= iters && rc == BD3MG_OK; ++it) {  // first launch warms up
-            float t = 0.f;
-            if (hipEventRecord(e0, st) != hipSuccess || launch_copy(a, b, n16, st) != hipSuccess ||
-                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&t, e0, e1) != hipSuccess)
-                rc = fail(BD3MG_ERR_HIP, "probe launch");
-            else if (it > 0 && (best == 0.f || t < best))
-                best = t;
-        }
+        // every launch shape; the first launch of each warms up
+        for (int v = 0; v < COPY_VARIANTS && rc == BD3MG_OK; ++v)
+            for (int it = 0; it <= iters && rc == BD3MG_OK; ++it) {
+                float t = 0.f;
+                if (hipEventRecord(e0, st) != hipSuccess || launch_copy(a, b, n16, v, st) != hipSuccess ||
+                    hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+                    rc = fail(BD3MG_ERR_HIP, "probe launch");
+                else if (it > 0 && (best == 0.f || t < best))
+                    best = t;
+            }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -197,7 +197,18 @@ hipError_t launch_sum(const double *partials, int nslot, int nq, double *out, hi
 constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
 hipError_t scratch_base(int device, void **ptr);
 
-// Streaming copy of n 16-byte words (bandwidth probe).
-hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st);
+// Start and stop events for the next kernel launch of this host thread (set
+// around a profiled single-kernel pass, null otherwise): the launchers then
+// use hipExtLaunchKernelGGL, which timestamps the kernel's own start and end
+// rather than adding event packets to the stream.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+extern thread_local LaunchEvents g_launch_events;
+
+// Streaming copy of n 16-byte words (bandwidth probe), in one of
+// COPY_VARIANTS launch shapes (words per lane in flight, workgroups).
+constexpr int COPY_VARIANTS = 4;
+hipError_t launch_copy(const void *src, void *dst, size_t n16, int variant, hipStream_t st);
 
 }  // namespace bd3mg

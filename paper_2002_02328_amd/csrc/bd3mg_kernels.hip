@@ -24,6 +24,7 @@
 // fixed DPP sum per wavefront, the four wavefronts in order, then the slots of a
 // block in slot order (k_solve) -- a fixed order, so runs are bitwise
 // reproducible.
+#include <hip/hip_ext.h>
 #include <mutex>
 
 #include "bd3mg_internal.h"
@@ -1384,17 +1385,46 @@ k_dense_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2
     }
 }
 
-// Streaming copy, 16 bytes per lane per iteration, grid-stride.
+// Streaming copy of n 16-byte words, grid-stride over chunks of U NT words:
+// each lane issues its U loads (coalesced, NT words apart) before its U
+// stores, so U loads per lane are in flight at once.
+template <int U>
 __global__ void __launch_bounds__(NT) k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
                                              size_t n)
 {
-    const size_t stride = (size_t)gridDim.x * NT;
-    for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+    const size_t stride = (size_t)gridDim.x * NT * U;
+    for (size_t base = (size_t)blockIdx.x * NT * U + threadIdx.x; base < n; base += stride) {
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + (size_t)u * NT;
+            if (i < n) v[u] = src[i];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const size_t i = base + (size_t)u * NT;
+            if (i < n) dst[i] = v[u];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Launchers: dispatch on the z extent KZ and the in-slice radius R.
 // ---------------------------------------------------------------------------
+thread_local LaunchEvents g_launch_events;
+
+// A launch of the sweep kernels, timed by its own start and stop events when
+// the caller set them (g_launch_events, used by one launch only).
+#define BD3MG_LAUNCH(K, GRID, BLOCK, SHM, ST, ...)                                                   \
+    do {                                                                                           \
+        if (g_launch_events.start) {                                                               \
+            const LaunchEvents ev_ = g_launch_events;                                              \
+            g_launch_events = LaunchEvents{};                                                      \
+            hipExtLaunchKernelGGL(K, GRID, BLOCK, SHM, ST, ev_.start, ev_.stop, 0, __VA_ARGS__);   \
+        } else {                                                                                   \
+            hipLaunchKernelGGL(K, GRID, BLOCK, SHM, ST, __VA_ARGS__);                              \
+        }                                                                                          \
+    } while (0)
 #define BD3MG_R_SWITCH(r, CALL)                   \
     switch (r) {                                  \
     case 1: { constexpr int R = 1; CALL; } break; \
@@ -1442,7 +1472,7 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
     if (nitems <= 0) return hipSuccess;
     if (nshare > 0 && g.rz != 0) return hipErrorInvalidValue;
     BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                    hipLaunchKernelGGL((k_grad<T, KZ>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
+                    BD3MG_LAUNCH((k_grad<T, KZ>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
                                        s, q, x, out, items, mode, partials, nshare));
     return hipGetLastError();
 }
@@ -1453,7 +1483,7 @@ hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, c
 {
     if (nunits <= 0) return hipSuccess;
     BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
-                    hipLaunchKernelGGL((k_dirs<T, KZ, R, TYK>), grid_of(g, nunits, TYK), dim3(NT), 0,
+                    BD3MG_LAUNCH((k_dirs<T, KZ, R, TYK>), grid_of(g, nunits, TYK), dim3(NT), 0,
                                        st, g, prm, s, units, partials))));
     return hipGetLastError();
 }
@@ -1465,11 +1495,11 @@ hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items,
     if (nitems <= 0) return hipSuccess;
     if (multi) {
         BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
-                       hipLaunchKernelGGL((k_update<T, R, TYK, true>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                       BD3MG_LAUNCH((k_update<T, R, TYK, true>), grid_of(g, nitems, TYK), dim3(NT), 0,
                                           st, g, s, items, pairs, u)));
     } else {
         BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
-                       hipLaunchKernelGGL((k_update<T, R, TYK, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                       BD3MG_LAUNCH((k_update<T, R, TYK, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
                                           st, g, s, items, pairs, u)));
     }
     return hipGetLastError();
@@ -1481,7 +1511,7 @@ hipError_t launch_refresh(const Geom &g, const DevState<T> &s, const T *src, T *
 {
     if (nitems <= 0) return hipSuccess;
     BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_aux,
-                    hipLaunchKernelGGL((k_refresh<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                    BD3MG_LAUNCH((k_refresh<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0,
                                        st, g, s, src, qout, items))));
     return hipGetLastError();
 }
@@ -1492,7 +1522,7 @@ hipError_t launch_H(const Geom &g, const DevState<T> &s, const T *in, const T *s
 {
     if (nitems <= 0) return hipSuccess;
     BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_aux,
-                    hipLaunchKernelGGL((k_H<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
+                    BD3MG_LAUNCH((k_H<T, KZ, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
                                        g, s, in, sub, out, items, partials))));
     return hipGetLastError();
 }
@@ -1503,7 +1533,7 @@ hipError_t launch_blurT(const Geom &g, const DevState<T> &s, const T *in, T *out
 {
     if (nitems <= 0) return hipSuccess;
     BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_aux,
-                   hipLaunchKernelGGL((k_blurT<T, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
+                   BD3MG_LAUNCH((k_blurT<T, R, TYK>), grid_of(g, nitems, TYK), dim3(NT), 0, st,
                                       g, s, in, out, items)));
     return hipGetLastError();
 }
@@ -1513,7 +1543,7 @@ hipError_t launch_solve(const Params &prm, const BlockRange *br, int nbr, int nt
                         hipStream_t st)
 {
     if (nbr <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_solve, dim3(nbr), dim3(NT), 0, st, prm, br, ntiles_g, ntiles_d, pg, pd, u, info,
+    BD3MG_LAUNCH(k_solve, dim3(nbr), dim3(NT), 0, st, prm, br, ntiles_g, ntiles_d, pg, pd, u, info,
                        stop);
     return hipGetLastError();
 }
@@ -1532,10 +1562,26 @@ hipError_t launch_sum(const double *partials, int nslot, int nq, double *out, hi
     return hipGetLastError();
 }
 
-hipError_t launch_copy(const void *src, void *dst, size_t n16, hipStream_t st)
+hipError_t launch_copy(const void *src, void *dst, size_t n16, int variant, hipStream_t st)
 {
-    // 256 CUs x 8 workgroups keep every CU streaming
-    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(NT), 0, st, (const uint4 *)src, (uint4 *)dst, n16);
+    const uint4 *a = (const uint4 *)src;
+    uint4 *b = (uint4 *)dst;
+    switch (variant) {
+    case 0:  // one word per lane in flight, 8 workgroups per CU
+        hipLaunchKernelGGL(k_copy<1>, dim3(2048), dim3(NT), 0, st, a, b, n16);
+        break;
+    case 1:  // four words per lane in flight
+        hipLaunchKernelGGL(k_copy<4>, dim3(2048), dim3(NT), 0, st, a, b, n16);
+        break;
+    case 2:  // four words per lane, 32 workgroups per CU
+        hipLaunchKernelGGL(k_copy<4>, dim3(8192), dim3(NT), 0, st, a, b, n16);
+        break;
+    case 3:  // eight words per lane, 16 workgroups per CU
+        hipLaunchKernelGGL(k_copy<8>, dim3(4096), dim3(NT), 0, st, a, b, n16);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -1564,20 +1610,20 @@ hipError_t launch_dense(const Geom &g, const Params &prm, const DevState<T> &s, 
         if (mode != DM_HT || !part || out) return hipErrorInvalidValue;
         BD3MG_DENSE_TY(
             const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems * nsplit);
-            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true, TYD>), grid, dim3(NT), 0, st, g,
+            BD3MG_RD_SWITCH(g.R, BD3MG_LAUNCH((k_dense<T, R, 1, true, TYD>), grid, dim3(NT), 0, st, g,
                                                     prm, s, pk, in, sub, part, items, mode, nullptr, nsplit)));
         return hipGetLastError();
     }
     BD3MG_DENSE_TY(
         const dim3 grid(g.ntx, (g.ny + TYD - 1) / TYD, nitems);
         if (mode == DM_DIRS) {
-            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 2, false, TYD>), grid, dim3(NT), 0, st, g,
+            BD3MG_RD_SWITCH(g.R, BD3MG_LAUNCH((k_dense<T, R, 2, false, TYD>), grid, dim3(NT), 0, st, g,
                                                     prm, s, pk, in, sub, out, items, mode, partials, 1));
         } else if (mode == DM_HT) {
-            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, true, TYD>), grid, dim3(NT), 0, st, g,
+            BD3MG_RD_SWITCH(g.R, BD3MG_LAUNCH((k_dense<T, R, 1, true, TYD>), grid, dim3(NT), 0, st, g,
                                                     prm, s, pk, in, sub, out, items, mode, partials, 1));
         } else {
-            BD3MG_RD_SWITCH(g.R, hipLaunchKernelGGL((k_dense<T, R, 1, false, TYD>), grid, dim3(NT), 0, st, g,
+            BD3MG_RD_SWITCH(g.R, BD3MG_LAUNCH((k_dense<T, R, 1, false, TYD>), grid, dim3(NT), 0, st, g,
                                                     prm, s, pk, in, sub, out, items, mode, partials, 1));
         })
 #undef BD3MG_DENSE_TY
@@ -1591,7 +1637,7 @@ hipError_t launch_dense_update(const Geom &g, const DevState<T> &s, const Item *
     if (nitems <= 0) return hipSuccess;
     const size_t S = (size_t)g.nx * g.ny;
     const int gx = (int)std::min<size_t>((S + 4 * NT - 1) / (4 * NT), 1024);
-    hipLaunchKernelGGL(k_dense_update<T>, dim3(gx, 1, nitems), dim3(NT), 0, st, g, s, items, pairs, u);
+    BD3MG_LAUNCH(k_dense_update<T>, dim3(gx, 1, nitems), dim3(NT), 0, st, g, s, items, pairs, u);
     return hipGetLastError();
 }
 
