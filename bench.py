@@ -25,8 +25,10 @@ Prints one JSON line:
 * the same for the 512x512x128 workload (20 sweeps), the case that does not
   fit the last-level cache;
 * the time to ||grad f|| / ||grad f(y)|| <= 1e-6 from x0 = y and from the
-  learned warm start x0 = y + net(y) (network inference inside the clock), and
-  the distance of the result to the FP64 oracle's minimiser (stored samples);
+  learned warm start x0 = y + net(y) (network inference inside the clock),
+  with checks spaced by the trend of ||grad f|| (and, for comparison, after
+  every sweep), and the distance of the result to the FP64 oracle's minimiser
+  (stored samples);
 * the same under asynchronous rounds, with the paper's majorant (outside
   Assumption C) and with the inflation that Assumption C asks for;
 * the FP64 CPU oracle timed on a bounded sample, on all host cores and on one.
@@ -321,7 +323,7 @@ def round_schedule(binding, w, args):
             t0 = time.perf_counter()
             if net is not None:
                 net.infer(r)
-            res = r.run(max_sweeps, grad_rtol=tol, check_every=1)
+            res = r.run(max_sweeps, grad_rtol=tol, check_every=binding.CHECK_ADAPTIVE)
             return {"seconds": time.perf_counter() - t0, "sweeps": res["sweeps"],
                     "converged": bool(res["converged"]), "grad_rel": res["grad_norm"] / res["grad_norm_ref"],
                     "f": res["f"], "tol": tol}
@@ -405,20 +407,22 @@ def main():
             net.load(open(WEIGHTS, "rb").read())
             net.infer(g)  # sizes the network's buffers for this volume (untimed)
 
-        def to_tol(tol, warm):
+        def to_tol(tol, warm, check=binding.CHECK_ADAPTIVE):
             g.set_x0(None)
             t0 = time.perf_counter()
             if warm:
                 net.infer(g)  # x0 = y + net(y), inside the clock
-            res = g.run(args.max_sweeps_to_tol, grad_rtol=tol, check_every=1)
+            res = g.run(args.max_sweeps_to_tol, grad_rtol=tol, check_every=check)
             t1 = time.perf_counter()
             out_ = {"seconds": t1 - t0, "sweeps": res["sweeps"], "converged": bool(res["converged"]),
-                    "grad_rel": res["grad_norm"] / res["grad_norm_ref"], "f": res["f"], "tol": tol}
+                    "grad_rel": res["grad_norm"] / res["grad_norm_ref"], "f": res["f"], "tol": tol,
+                    "checks": "adaptive" if check == binding.CHECK_ADAPTIVE else "every %d sweeps" % check}
             if w.name == "plain-fp32-256x256x64":
                 out_["error_vs_oracle"] = error_vs_oracle(res, g.get_x())
             return out_
 
-        tt = {"plain_x0_y": to_tol(args.tol, False), "warm_started": None}
+        tt = {"plain_x0_y": to_tol(args.tol, False), "warm_started": None,
+              "plain_x0_y_check_every_sweep": to_tol(args.tol, False, 1)}
         if net is not None:
             tt["warm_started"] = to_tol(args.tol, True)
             tt["speedup"] = tt["plain_x0_y"]["seconds"] / tt["warm_started"]["seconds"]

@@ -207,9 +207,18 @@ bd3mg_status bd3mg_set_x0(bd3mg_problem p, const void *x0, int on_device);
  * res->grad_norm are evaluated at the returned x from a rebuilt residual.
  * With grad_rtol <= 0 and check_every == 0 nothing is evaluated (res->f and
  * res->grad_norm are NaN) and the call only enqueues the sweeps and waits for
- * them.  res may be NULL.  ERR_ARG: max_sweeps < 0
- * or check_every < 0.  ERR_STATE: PSF, data or blocks not set.
- * ERR_NOT_CONVERGED: grad_rtol > 0 and not reached (state still valid). */
+ * them.  res may be NULL.  check_every == BD3MG_CHECK_ADAPTIVE (grad_rtol >
+ * 0 only): checks are spaced by the trend of ||grad f||: a check after the
+ * first sweep, then, while the line through the last two checks (log
+ * ||grad f|| against sweeps) meets the threshold more than 8 sweeps ahead,
+ * one check after half that distance (at most 256 sweeps), else a check
+ * after every sweep; the run stops at the first check that meets the
+ * tolerance, as with check_every = 1 near the crossing, at the cost of far
+ * fewer evaluations.  ERR_ARG: max_sweeps < 0, check_every < -1, or
+ * adaptive checks without a tolerance.  ERR_STATE: PSF, data or blocks not
+ * set.  ERR_NOT_CONVERGED: grad_rtol > 0 and not reached (state still
+ * valid). */
+#define BD3MG_CHECK_ADAPTIVE (-1)
 bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int check_every,
                        bd3mg_result *res);
 

@@ -20,6 +20,7 @@ FP64, FP32 = 0, 1
 SCHED_COLORED, SCHED_SEQUENTIAL, SCHED_ROUND = 0, 1, 2
 OP_H, OP_HT, OP_GRAD = 0, 1, 2
 OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_HIP, ERR_NOT_CONVERGED = range(6)
+CHECK_ADAPTIVE = -1  # check_every of run(): checks spaced by the trend of ||grad f||
 OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
 OPT_TILE_ROWS_DIRS, OPT_TILE_ROWS_UPDATE, OPT_TILE_ROWS_AUX, OPT_DIRS_SLICES = 2, 3, 4, 5
 KERNEL_KINDS = ("grad", "dirs", "solve", "update", "eval")

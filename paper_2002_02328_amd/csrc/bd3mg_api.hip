@@ -829,7 +829,9 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
 {
     ST_TRY(validate_handle(p));
     if (max_sweeps < 0) return fail(BD3MG_ERR_ARG, "max_sweeps < 0");
-    if (check_every < 0) return fail(BD3MG_ERR_ARG, "check_every < 0");
+    if (check_every < BD3MG_CHECK_ADAPTIVE) return fail(BD3MG_ERR_ARG, "check_every < -1");
+    const bool adaptive = check_every == BD3MG_CHECK_ADAPTIVE;
+    if (adaptive && !(grad_rtol > 0.0)) return fail(BD3MG_ERR_ARG, "adaptive checks need grad_rtol > 0");
     const bool checking = grad_rtol > 0.0 || check_every > 0;
     if (grad_rtol > 0.0 && check_every == 0) check_every = max_sweeps > 0 ? max_sweeps : 1;
     ST_TRY(noalloc ? ensure_ready_noalloc(p) : ensure_ready(p));
@@ -848,8 +850,30 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
     int done = max_sweeps;
     bool conv = false;
     bd3mg_problem_s::Ctl ctl{0, 0, NAN};
+    // adaptive checks: the last two checks (sweep, ||grad f||)
+    int sa = -1, sb = -1;
+    double ga = 0.0, gb = 0.0;
     for (int s = 0; s < max_sweeps;) {
-        const int end = std::min(max_sweeps, s + CHUNK);
+        int end = std::min(max_sweeps, s + CHUNK);
+        bool every = true;  // adaptive: check after every sweep of the chunk, else after its last
+        if (adaptive) {
+            if (sb < 0) {
+                end = s + 1;  // a first check after one sweep
+            } else if (sa >= 0 && ga > 0.0 && gb > 0.0 && gb < ga && gb > thr) {
+                // ||grad f|| decreasing: where log ||grad f|| reaches log thr
+                // on the line through the last two checks
+                const double rate = std::log(gb / ga) / (double)(sb - sa);
+                const double ahead = std::log(thr / gb) / rate;
+                if (ahead > 8.0) {
+                    // far from it: half the predicted distance, one check at the end
+                    const int len = (int)std::min(256.0, 0.5 * ahead);
+                    end = std::min(max_sweeps, s + len);
+                    every = false;
+                }
+            } else if (gb > thr) {
+                every = false;  // no trend yet: one check at the end of the chunk
+            }
+        }
         for (; s < end; ++s) {
             for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile, stop));
             p->cur ^= 1;
@@ -859,7 +883,10 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
                 ST_TRY(refresh(p, p->x, p->q, stop));
                 ST_TRY(prof_end(p));
             }
-            if (checking && (((s + 1) % check_every) == 0 || s + 1 == max_sweeps)) {
+            // (check_every is 0 when nothing is checked: no modulo then)
+            const bool due = checking && (adaptive ? (every || s + 1 == end)
+                                                   : (((s + 1) % check_every) == 0 || s + 1 == max_sweeps));
+            if (due) {
                 ST_TRY(prof_begin(p, BD3MG_K_EVAL, 2.0 * vol, false));
                 ST_TRY(check(p, thr, s + 1, stop));
                 ST_TRY(prof_end(p));
@@ -896,6 +923,12 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
                 ctl = bd3mg_problem_s::Ctl{0, 0, gfresh};
                 s = ss;
                 if (ss >= max_sweeps) break;
+            }
+            if (adaptive) {
+                sa = sb;
+                ga = gb;
+                sb = s;
+                gb = ctl.gnorm;
             }
         }
         if (p->pending.size() > 4096) ST_TRY(prof_collect(p));

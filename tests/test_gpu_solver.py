@@ -105,6 +105,34 @@ def test_stop_rule_matches_oracle(orc):
     assert res2["converged"] == 0 and res2["sweeps"] == 3
 
 
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
+def test_adaptive_checks_stop_where_every_sweep_checks_do(orc, prec):
+    """Checks spaced by the trend of ||grad f|| (every sweep near the
+    predicted crossing) stop at the same sweep as a check after every sweep,
+    with the same iterate, and evaluate far less often."""
+    g, o, y, w = _c1(orc, inputs.small_plain_fp64(), _c1_y(orc), prec)
+    for tol in (1e-3, 1e-5):
+        g.set_x0(None)
+        g.set_option(binding.OPT_PROFILE, 1)
+        r1 = g.run(5000, grad_rtol=tol, check_every=1)
+        n1 = g.get_profile(reset=True)["eval"][0]
+        x1 = g.get_x()
+        g.set_x0(None)
+        ra = g.run(5000, grad_rtol=tol, check_every=binding.CHECK_ADAPTIVE)
+        na = g.get_profile(reset=True)["eval"][0]
+        g.set_option(binding.OPT_PROFILE, 0)
+        print("tol %g: every sweep %d sweeps, %d evaluations; adaptive %d sweeps, %d evaluations"
+              % (tol, r1["sweeps"], n1, ra["sweeps"], na))
+        assert r1["converged"] and ra["converged"]
+        assert ra["sweeps"] == r1["sweeps"]
+        assert np.array_equal(g.get_x(), x1)
+        assert ra["grad_norm"] == r1["grad_norm"]
+        assert na < n1 / 2
+    with pytest.raises(binding.Bd3mgError) as e:
+        g.run(3, check_every=binding.CHECK_ADAPTIVE)
+    assert e.value.status == binding.ERR_ARG
+
+
 def test_determinism_and_resume(orc):
     g, o, y, w = _c1(orc, inputs.small_plain_fp64(), _c1_y(orc), binding.FP32)
     g.set_option(binding.OPT_REFRESH_EVERY, 4)  # refreshes fall inside the chained runs
