@@ -160,6 +160,36 @@ bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, doub
  * (the default) is the paper's majorant.  ERR_ARG: mu < 0 or not finite. */
 bd3mg_status bd3mg_set_inflation(bd3mg_problem p, double mu);
 
+/* Block step of the ablation study (Sec. 3.2, "Ablation study and
+ * comparative analysis"), each a change of the Worker's step:
+ * BD3MG_METHOD_BD3MG (default): the memory-gradient subspace [-grad, d_prev]
+ *   with the half-quadratic majorant (Sec. 2.3);
+ * BD3MG_METHOD_ASYNC_GD: the subspace {-grad} with the metric L Id, so the
+ *   step is -grad_S f / L;
+ * BD3MG_METHOD_ASYNC_CG: BD3MG's subspace with the metric L Id (read
+ *   literally: -grad lies in the subspace, so the step equals Async-GD's up to
+ *   rounding);
+ * BD3MG_METHOD_ASYNC_MM: no subspace, d' = -A_S(x)^{-1} grad_S f, the linear
+ *   system solved by at most n_inner iterations of conjugate gradients from
+ *   0 (for the symmetric A_S these are the linear biconjugate gradient
+ *   iterates with the shadow residual started at the residual), stopping
+ *   early once ||r|| <= tol_inner ||r_0|| (tol_inner = 0: n_inner
+ *   iterations) or when a step is undefined; needs the separable PSF and the
+ *   coloured or sequential schedule (ERR_STATE at run otherwise).
+ * lip: L of the metric L Id (GD, CG); lip <= 0 takes bd3mg_lipschitz_bound
+ * at each run.  The inflation mu (bd3mg_set_inflation) adds to every metric.
+ * bd3mg_block_step's info for Async-MM is {iterations, ||r_end||^2, 0,
+ * -||g||^2, 0, 0, 0, ||g||^2}; for GD and CG {B11, B12, B22, c1, c2, u1, u2,
+ * ||g||^2} of the metric L Id.  ERR_ARG: unknown method, non-finite lip,
+ * n_inner outside [1, 10000] for Async-MM, tol_inner < 0. */
+typedef enum {
+    BD3MG_METHOD_BD3MG = 0,
+    BD3MG_METHOD_ASYNC_GD = 1,
+    BD3MG_METHOD_ASYNC_CG = 2,
+    BD3MG_METHOD_ASYNC_MM = 3
+} bd3mg_method;
+bd3mg_status bd3mg_set_method(bd3mg_problem p, int method, double lip, int n_inner, double tol_inner);
+
 /* An upper bound L of the Lipschitz constant of grad f (Assumption A) from
  * the PSF tables and parameters: ||H||_1 ||H||_inf + 2 eta + 8 lambda / delta
  * + 8 kappa (the in-slice difference operators have ||D||^2 <= 8 and

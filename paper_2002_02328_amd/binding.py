@@ -21,6 +21,7 @@ SCHED_COLORED, SCHED_SEQUENTIAL, SCHED_ROUND = 0, 1, 2
 OP_H, OP_HT, OP_GRAD = 0, 1, 2
 OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_HIP, ERR_NOT_CONVERGED = range(6)
 CHECK_ADAPTIVE = -1  # check_every of run(): checks spaced by the trend of ||grad f||
+METHOD_BD3MG, METHOD_ASYNC_GD, METHOD_ASYNC_CG, METHOD_ASYNC_MM = 0, 1, 2, 3
 OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
 OPT_TILE_ROWS_DIRS, OPT_TILE_ROWS_UPDATE, OPT_TILE_ROWS_AUX, OPT_DIRS_SLICES = 2, 3, 4, 5
 KERNEL_KINDS = ("grad", "dirs", "solve", "update", "eval")
@@ -44,6 +45,7 @@ SIGNATURES = {
     "bd3mg_set_x0": ([_dp, _dp, _i], C.c_int),
     "bd3mg_run": ([_dp, _i, _d, _i, _dp], C.c_int),
     "bd3mg_run_noalloc": ([_dp, _i, _d, _i, _dp], C.c_int),
+    "bd3mg_set_method": ([_dp, _i, _d, _i, _d], C.c_int),
     "bd3mg_get_x": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_dprev": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_state": ([_dp, _dp, _dp, _dp, _dp, _i], C.c_int),
@@ -209,6 +211,12 @@ class Problem:
 
     def set_params(self, lam, delta, eta, kappa=0.0, xmin=0.0, xmax=1.0):
         _check(load().bd3mg_set_params(self._h, lam, delta, eta, kappa, xmin, xmax))
+
+    def set_method(self, method, lip=0.0, n_inner=1, tol_inner=0.0):
+        """Block step of the ablation study: METHOD_BD3MG, METHOD_ASYNC_GD,
+        METHOD_ASYNC_CG (metric L Id; lip <= 0: the Lipschitz bound) or
+        METHOD_ASYNC_MM (n_inner conjugate-gradient iterations at most)."""
+        _check(load().bd3mg_set_method(self._h, int(method), float(lip), int(n_inner), float(tol_inner)))
 
     def set_inflation(self, mu):
         _check(load().bd3mg_set_inflation(self._h, float(mu)))

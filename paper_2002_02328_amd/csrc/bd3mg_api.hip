@@ -48,7 +48,10 @@ struct bd3mg_problem_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Geom geom{};
     int ntiles = 0;
-    Params prm{0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0};
+    Params prm{0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, M_BD3MG, 0.0};
+    int n_inner = 0;         // Async-MM: inner iterations at most
+    double tol_inner = 0.0;  // Async-MM: relative residual of the inner solve (0: n_inner iterations)
+    double lip_given = 0.0;  // L of the metric L Id as given (<= 0: the Lipschitz bound)
 
     // PSF
     bool psf_set = false;
@@ -108,6 +111,13 @@ struct bd3mg_problem_s {
     };
     Ctl *d_ctl = nullptr;
     int nblocks_alloc = 0;
+
+    // Async-MM's inner solve: r, p, v, A p, XY^T (H p) volumes, partial sums
+    // and per-block scalars
+    void *mmv[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double *d_pma = nullptr, *d_prr = nullptr, *d_cgs = nullptr, *d_u01 = nullptr, *d_u10 = nullptr;
+    size_t mm_slots = 0;
+    int mm_blocks = 0;
 
     double gnorm_ref = 0.0;
     bool gnorm_ref_valid = false;
@@ -355,7 +365,9 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     for (int b : blocks) {
         const int z0 = p->z0[b], n = p->nsl[b];
         BlockRange r{b, (int)gi.size() - grp.g_off, 0, (int)di.size() - grp.d_off, 0};
-        for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n, 0, 0});
+        // gradient items carry the block's first gradient item (in the group)
+        // and its item count: the slots of the block's partial sums
+        for (int k = z0; k < z0 + n; ++k) gi.push_back(Item{k, b, z0, n, r.g0, n});
         const int lo = std::max(0, z0 - rd);
         dfirst.push_back(r.d0);
         dlo.push_back(lo);
@@ -423,6 +435,49 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     grp.bytes[3] = A * (2.0 * np + 5.0 * sl + 2.0 * h);
 }
 
+// Buffers of Async-MM's inner solve for launch groups of at most maxg
+// gradient items (five volumes, two partial-sum arrays, block scalars, and
+// the constant coefficient pairs (0, 1) and (1, 0) of every block).
+bd3mg_status ensure_mm(bd3mg_problem p, int maxg)
+{
+    for (void *&v : p->mmv)
+        if (!v && hipMalloc(&v, p->N * p->esz) != hipSuccess) return fail(BD3MG_ERR_NOMEM, "Async-MM volumes");
+    const size_t slots = (size_t)maxg * p->ntiles;
+    if (slots > p->mm_slots) {
+        if (p->d_pma) HIP_TRY(hipFree(p->d_pma));
+        if (p->d_prr) HIP_TRY(hipFree(p->d_prr));
+        p->d_pma = p->d_prr = nullptr;
+        p->mm_slots = 0;
+        if (hipMalloc(&p->d_pma, slots * sizeof(double)) != hipSuccess ||
+            hipMalloc(&p->d_prr, slots * sizeof(double)) != hipSuccess)
+            return fail(BD3MG_ERR_NOMEM, "Async-MM partial sums");
+        p->mm_slots = slots;
+    }
+    const int nb = (int)p->nsl.size();
+    if (nb > p->mm_blocks) {
+        for (double **d : {&p->d_cgs, &p->d_u01, &p->d_u10}) {
+            if (*d) HIP_TRY(hipFree(*d));
+            *d = nullptr;
+        }
+        p->mm_blocks = 0;
+        if (hipMalloc(&p->d_cgs, (size_t)CG_STRIDE * nb * sizeof(double)) != hipSuccess ||
+            hipMalloc(&p->d_u01, 2 * (size_t)nb * sizeof(double)) != hipSuccess ||
+            hipMalloc(&p->d_u10, 2 * (size_t)nb * sizeof(double)) != hipSuccess)
+            return fail(BD3MG_ERR_NOMEM, "Async-MM block scalars");
+        p->mm_blocks = nb;
+    }
+    std::vector<double> u01(2 * nb), u10(2 * nb);
+    for (int b = 0; b < nb; ++b) {
+        u01[2 * b] = 0.0;
+        u01[2 * b + 1] = 1.0;
+        u10[2 * b] = 1.0;
+        u10[2 * b + 1] = 0.0;
+    }
+    HIP_TRY(hipMemcpy(p->d_u01, u01.data(), u01.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(p->d_u10, u10.data(), u10.size() * sizeof(double), hipMemcpyHostToDevice));
+    return BD3MG_OK;
+}
+
 bd3mg_status build_schedule(bd3mg_problem p)
 {
     if (!p->sched_dirty) return BD3MG_OK;
@@ -487,6 +542,7 @@ bd3mg_status build_schedule(bd3mg_problem p)
     }
     p->maxg = maxg;
     p->maxd = maxd;
+    if (p->prm.method == M_MM) ST_TRY(ensure_mm(p, maxg));
     ST_TRY(realloc_dev((void **)&p->d_pg, &p->pg_cap, (size_t)maxg * p->ntiles * NQG * sizeof(double),
                        "gradient partial sums"));
     ST_TRY(realloc_dev((void **)&p->d_pd, &p->pd_cap,
@@ -603,10 +659,34 @@ bd3mg_status eval_at(bd3mg_problem p, const void *xin, const void *qin, double *
                : eval_t<float>(p, (const float *)xin, (const float *)qin, f, gn, (float *)hbuf);
 }
 
+// The method's settings that depend on the PSF, parameters and schedule:
+// L of the metric L Id (Async-GD, Async-CG) when not given; Async-MM needs
+// the separable PSF and blocks whose S +- r_z are disjoint within a launch
+// group (coloured or sequential schedule).
+bd3mg_status method_ready(bd3mg_problem p)
+{
+    if (p->prm.method == M_GD || p->prm.method == M_CG) {
+        if (p->lip_given > 0.0) {
+            p->prm.lip = p->lip_given;
+        } else {
+            double L = 0.0;
+            ST_TRY(bd3mg_lipschitz_bound(p, &L));
+            p->prm.lip = L;
+        }
+    }
+    if (p->prm.method == M_MM) {
+        if (p->dense) return fail(BD3MG_ERR_STATE, "Async-MM runs with the separable PSF");
+        if (p->schedule == BD3MG_SCHED_ROUND)
+            return fail(BD3MG_ERR_STATE, "Async-MM runs with the coloured or sequential schedule");
+    }
+    return BD3MG_OK;
+}
+
 bd3mg_status ensure_ready(bd3mg_problem p)
 {
     if (!p->psf_set) return fail(BD3MG_ERR_STATE, "the PSF is not set");
     if (!p->data_set) return fail(BD3MG_ERR_STATE, "the data y is not set");
+    ST_TRY(method_ready(p));
     ST_TRY(build_schedule(p));
     if (!p->x_set) {
         HIP_TRY(hipMemcpyAsync(p->x, p->y, p->N * p->esz, hipMemcpyDeviceToDevice, p->stream));
@@ -659,16 +739,47 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
     HIP_TRY(launch_grad<T>(p->geom, p->prm, s, s.q, s.x, nullptr, it + gr.g_off, gr.g_cnt, GM_BLOCK,
                            p->d_pg, p->stream));
     if (prof) ST_TRY(prof_end(p));
-    if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
-    HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, p->d_units + gr.du_off, gr.du_cnt, p->d_pd, p->stream));
-    if (prof) ST_TRY(prof_end(p));
-    if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
-    HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,
-                         tiles_of(p->geom, p->geom.ty_dirs), p->d_pg, p->d_pd, p->d_u, p->d_info, stop,
-                         p->stream));
-    if (prof) ST_TRY(prof_end(p));
+    const double *u = p->d_u;
+    if (p->prm.method == M_MM) {
+        // Async-MM: v = A_S(x)^{-1} (-g_S) by inner conjugate gradients on
+        // every block of the group, then d' = v applied as -g with u = (1, 0)
+        const CgBufs<T> cb{(T *)p->mmv[0], (T *)p->mmv[1], (T *)p->mmv[2], (T *)p->mmv[3], (T *)p->mmv[4],
+                           p->d_pg, p->d_pma, p->d_prr, p->d_cgs, p->d_info};
+        const Item *gi = it + gr.g_off;
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, 0.0, false));
+        HIP_TRY(launch_cg<T>(CG_INIT, p->geom, s, gi, gr.g_cnt, cb, 0, p->tol_inner, p->stream));
+        DevState<T> sp = s;  // H p from the direction pass (d1 = -p, d2 = p)
+        sp.g = cb.p;
+        sp.dp[0] = cb.p;
+        DevState<T> sq = s;  // XY^T (H p) into qt
+        sq.q = cb.qt;
+        for (int i = 0; i < p->n_inner; ++i) {
+            HIP_TRY(launch_dirs<T>(p->geom, p->prm, sp, p->d_units + gr.du_off, gr.du_cnt, p->d_pd, p->stream));
+            HIP_TRY(launch_update<T>(p->geom, sq, it + gr.u_off, gr.u_cnt, p->d_pairs, p->d_u01, false,
+                                     p->stream, 1));
+            HIP_TRY(launch_majapply<T>(p->geom, p->prm, s, cb.qt, s.x, cb.p, cb.ap, gi, gr.g_cnt, p->d_pma,
+                                       p->stream));
+            HIP_TRY(launch_cg<T>(CG_VEC, p->geom, s, gi, gr.g_cnt, cb, i & 1, p->tol_inner, p->stream));
+            HIP_TRY(launch_cg<T>(CG_DIR, p->geom, s, gi, gr.g_cnt, cb, i & 1, p->tol_inner, p->stream));
+        }
+        HIP_TRY(launch_cg<T>(CG_FINAL, p->geom, s, gi, gr.g_cnt, cb, 0, p->tol_inner, p->stream));
+        if (prof) ST_TRY(prof_end(p));
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
+        HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, p->d_units + gr.du_off, gr.du_cnt, p->d_pd, p->stream));
+        if (prof) ST_TRY(prof_end(p));
+        u = p->d_u10;
+    } else {
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
+        HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, p->d_units + gr.du_off, gr.du_cnt, p->d_pd, p->stream));
+        if (prof) ST_TRY(prof_end(p));
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
+        HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,
+                             tiles_of(p->geom, p->geom.ty_dirs), p->d_pg, p->d_pd, p->d_u, p->d_info, stop,
+                             p->stream));
+        if (prof) ST_TRY(prof_end(p));
+    }
     if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
-    HIP_TRY(launch_update<T>(p->geom, s, it + gr.u_off, gr.u_cnt, p->d_pairs, p->d_u, gr.round, p->stream));
+    HIP_TRY(launch_update<T>(p->geom, s, it + gr.u_off, gr.u_cnt, p->d_pairs, u, gr.round, p->stream));
     if (prof) ST_TRY(prof_end(p));
     return BD3MG_OK;
 }
@@ -797,6 +908,8 @@ bd3mg_status ensure_ready_noalloc(bd3mg_problem p)
     if (!p->psf_set) return fail(BD3MG_ERR_STATE, "the PSF is not set");
     if (!p->data_set) return fail(BD3MG_ERR_STATE, "the data y is not set");
     if (p->dense) return fail(BD3MG_ERR_STATE, "bd3mg_run_noalloc takes the separable PSF only");
+    if (p->prm.method == M_MM) return fail(BD3MG_ERR_STATE, "bd3mg_run_noalloc does not run Async-MM");
+    ST_TRY(method_ready(p));
     if (!p->blocks_set) return fail(BD3MG_ERR_STATE, "blocks are not set");
     if (p->sched_dirty)
         return fail(BD3MG_ERR_STATE, "the schedule is not built (bd3mg_get_schedule builds it)");
@@ -1074,6 +1187,10 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
                     p->d_units};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    void *mm[] = {p->mmv[0], p->mmv[1], p->mmv[2], p->mmv[3], p->mmv[4], p->d_pma, p->d_prr, p->d_cgs,
+                  p->d_u01, p->d_u10};
+    for (void *b : mm)
+        if (b) (void)hipFree(b);
     for (auto &q : p->pending) {
         (void)hipEventDestroy(q.a);
         (void)hipEventDestroy(q.b);
@@ -1159,7 +1276,7 @@ bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, doub
         return fail(BD3MG_ERR_ARG, "lambda, eta and kappa must be >= 0");
     if (xmin > xmax) return fail(BD3MG_ERR_ARG, "xmin > xmax");
     const bool kappa_changed = (kappa > 0.0) != (p->prm.kappa > 0.0);
-    p->prm = Params{lambda, delta, eta, kappa, xmin, xmax, p->prm.mu};
+    p->prm = Params{lambda, delta, eta, kappa, xmin, xmax, p->prm.mu, p->prm.method, p->prm.lip};
     p->gnorm_ref_valid = false;
     if (kappa_changed) p->sched_dirty = true;
     return BD3MG_OK;
@@ -1170,6 +1287,26 @@ bd3mg_status bd3mg_set_inflation(bd3mg_problem p, double mu)
     ST_TRY(validate_handle(p));
     if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(BD3MG_ERR_ARG, "mu must be finite and >= 0");
     p->prm.mu = mu;
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_set_method(bd3mg_problem p, int method, double lip, int n_inner, double tol_inner)
+{
+    ST_TRY(validate_handle(p));
+    if (method < BD3MG_METHOD_BD3MG || method > BD3MG_METHOD_ASYNC_MM)
+        return fail(BD3MG_ERR_ARG, "unknown method %d", method);
+    if (!std::isfinite(lip)) return fail(BD3MG_ERR_ARG, "L must be finite");
+    if (method == BD3MG_METHOD_ASYNC_MM && (n_inner < 1 || n_inner > 10000))
+        return fail(BD3MG_ERR_ARG, "Async-MM needs 1 <= n_inner <= 10000, got %d", n_inner);
+    if (!(tol_inner >= 0.0) || !std::isfinite(tol_inner)) return fail(BD3MG_ERR_ARG, "tol_inner must be >= 0");
+    if (method == BD3MG_METHOD_ASYNC_MM && p->dense)
+        return fail(BD3MG_ERR_STATE, "Async-MM runs with the separable PSF");
+    const bool to_mm = method == BD3MG_METHOD_ASYNC_MM && p->prm.method != M_MM;
+    p->prm.method = method;
+    p->lip_given = lip;
+    p->n_inner = n_inner;
+    p->tol_inner = tol_inner;
+    if (to_mm) p->sched_dirty = true;  // the inner solve's buffers are sized with the schedule
     return BD3MG_OK;
 }
 
@@ -1378,7 +1515,7 @@ bd3mg_status bd3mg_run_noalloc(bd3mg_problem p, int max_sweeps, double grad_rtol
                                bd3mg_result *res)
 {
     ST_TRY(validate_handle(p));
-    if (!p->blocks_set || p->sched_dirty || p->dense || !p->psf_set || !p->data_set)
+    if (!p->blocks_set || p->sched_dirty || p->dense || !p->psf_set || !p->data_set || p->prm.method == M_MM)
         return ensure_ready_noalloc(p);  // fails, naming what is missing
     void *base = nullptr;
     HIP_TRY(scratch_base(p->device, &base));

@@ -80,9 +80,16 @@ struct BlockRange {
     int d0, dn;  // direction-pass items [d0, d0 + dn)
 };
 
+// Block step of the ablation study (Sec. 3.2): BD3MG's subspace step with
+// the half-quadratic majorant, or Async-GD / Async-CG (the metric L Id), or
+// Async-MM (d' = -A_S(x)^{-1} grad_S f by an inner linear solve).
+enum Method : int { M_BD3MG = 0, M_GD = 1, M_CG = 2, M_MM = 3 };
+
 struct Params {
     double lambda, delta, eta, kappa, xmin, xmax;
-    double mu;  // curvature inflation of every block majorant (A_S + mu Id)
+    double mu;   // curvature inflation of every block majorant (A_S + mu Id)
+    int method;  // Method
+    double lip;  // L of the metric L Id (M_GD, M_CG)
 };
 
 struct Geom {
@@ -134,9 +141,40 @@ hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, c
 
 // Update pass from the stored H d1, H d2 (pairs: (slot, block) per source;
 // multi: items may have more than one source, as in a round).
+// assign: s.q receives XY^T (H d') on the items' slices (no add, x and dp
+// untouched).
 template <typename T>
 hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
-                         const int2 *pairs, const double *u, bool multi, hipStream_t st);
+                         const int2 *pairs, const double *u, bool multi, hipStream_t st, int assign = 0);
+
+// Async-MM (Sec. 3.2): the block majorant applied to a block vector p,
+//   ap_S = [H^T H p + 2 eta p + lambda V^T Diag(omega(x)) V p + 2 kappa VZ^T VZ p]_S + mu p_S,
+// p zero outside each item's block, the data part from qt = XY^T (H p)
+// (slices S +- r_z); partials: <p, A p> per (item, tile) slot.  Items are
+// the gradient items of a launch group (h0, hn: the block's first item and
+// item count in the group).
+template <typename T>
+hipError_t launch_majapply(const Geom &g, const Params &prm, const DevState<T> &s, const T *qt,
+                           const T *x, const T *pv, T *ap, const Item *items, int nitems,
+                           double *partials, hipStream_t st);
+
+// Async-MM's inner solve on every block of a launch group: conjugate
+// gradients on A_S(x) v = -g_S from v = 0 (for the symmetric A_S the linear
+// biconjugate gradient iterates with the shadow residual started at the
+// residual are these, bitwise).  Per-block scalars in cgs[CG_STRIDE * block].
+enum : int { CG_INIT = 0, CG_VEC = 1, CG_DIR = 2, CG_FINAL = 3 };
+constexpr int CG_STRIDE = 10;  // rho[2], done[2], r0, iterations, ||r||^2 at the end, ||g||^2
+template <typename T>
+struct CgBufs {
+    T *r, *p, *v, *ap, *qt;  // residual, direction, solution, A p, XY^T (H p)
+    double *pg;              // gradient-pass partials (NQG per slot): <g, g>
+    double *pa, *prr;        // <p, A p> and <r, r> per slot
+    double *cgs;             // per-block scalars
+    double *info;            // per-block info of the step (CG_FINAL)
+};
+template <typename T>
+hipError_t launch_cg(int stage, const Geom &g, const DevState<T> &s, const Item *items, int nitems,
+                     const CgBufs<T> &b, int parity, double tol_inner, hipStream_t st);
 
 // qout = XY^T (H src - y) on the items' slices.
 template <typename T>

@@ -611,13 +611,27 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
         const double gg = tot[0], gd = tot[1], dd = tot[2];
         const double *w = tot + 3, *h = tot + NQG, *z = tot + NQG + 3;
         const double e2 = 2.0 * prm.eta + prm.mu, k2 = 2.0 * prm.kappa, lam = prm.lambda;
-        const double b11 = h[0] + e2 * gg + lam * w[0] + k2 * z[0];
-        const double b12 = h[1] - e2 * gd + lam * w[1] + k2 * z[1];
-        const double b22 = h[2] + e2 * dd + lam * w[2] + k2 * z[2];
-        const double c1 = -gg, c2 = gd;
+        double b11 = h[0] + e2 * gg + lam * w[0] + k2 * z[0];
+        double b12 = h[1] - e2 * gd + lam * w[1] + k2 * z[1];
+        double b22 = h[2] + e2 * dd + lam * w[2] + k2 * z[2];
+        const double c1 = -gg;
+        double c2 = gd;
+        if (prm.method == M_GD || prm.method == M_CG) {
+            // the metric L Id (Sec. 3.2): B = L D^T D over D = [-g] (Async-GD)
+            // or D = [-g, dp] (Async-CG)
+            const double lm = prm.lip + prm.mu;
+            b11 = lm * gg;
+            b12 = prm.method == M_CG ? -lm * gd : 0.0;
+            b22 = prm.method == M_CG ? lm * dd : 0.0;
+            if (prm.method == M_GD) c2 = 0.0;
+        }
         const double det = b11 * b22 - b12 * b12, tr = b11 + b22;
         double p11, p12, p22;
-        if (det > 1e-12 * b11 * b22) {
+        if (prm.method == M_GD) {
+            // a single direction: the step -c1 / b11 (zero when g = 0)
+            p11 = b11 > 0.0 ? 1.0 / b11 : 0.0;
+            p12 = p22 = 0.0;
+        } else if (det > 1e-12 * b11 * b22) {
             p11 = b22 / det;
             p12 = -b12 / det;
             p22 = b11 / det;
@@ -629,7 +643,8 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
         } else {
             p11 = p12 = p22 = 0.0;
         }
-        const double u1 = -(p11 * c1 + p12 * c2);
+        // (Async-GD: the quotient itself, -c1 / b11)
+        const double u1 = prm.method == M_GD ? (b11 > 0.0 ? -c1 / b11 : 0.0) : -(p11 * c1 + p12 * c2);
         const double u2 = -(p12 * c1 + p22 * c2);
         u[2 * br.block] = u1;
         u[2 * br.block + 1] = u2;
@@ -835,7 +850,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
 template <typename T, int R, int TYK, bool MULTI>
 __global__ void __launch_bounds__(NT)
 k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ pairs,
-         const double *__restrict__ u)
+         const double *__restrict__ u, int assign)
 {
     constexpr int NRK = TYK / (NT / TX);
     constexpr int K = 2 * R + 1;
@@ -856,7 +871,9 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     // the outputs' q, and on the block x, dp and g, are loaded first so that
     // their latency overlaps the loads of H d' (no pass of this launch writes
     // H d1 or H d2)
-    const bool ins = (m >= it.z0 && m < it.z0 + it.n);
+    // assign: s.q receives XY^T_m (H d')_m itself, and x, dp are left alone
+    // (the majorant applied to a block vector, Async-MM's inner solve)
+    const bool ins = !assign && (m >= it.z0 && m < it.z0 + it.n);
     const __amdgpu_buffer_rsrc_t qs = buf_of(s.q + (size_t)m * S, S), xs = buf_of(s.x + (size_t)m * S, S);
     const __amdgpu_buffer_rsrc_t ds = buf_of(s.dp[0] + (size_t)m * S, S), gs = buf_of(s.g + (size_t)m * S, S);
     T qv[NRK], xv[NRK], dv[NRK], gv[NRK];
@@ -864,7 +881,7 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         const uint32_t o = (i < g.nx && j < g.ny) ? (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T) : 0u;
-        qv[e] = ldbuf<T>(qs, o);
+        qv[e] = assign ? T(0) : ldbuf<T>(qs, o);
         xv[e] = dv[e] = gv[e] = 0;
         if (ins) {
             xv[e] = ldbuf<T>(xs, o);
@@ -1385,6 +1402,244 @@ k_dense_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2
     }
 }
 
+// ---------------------------------------------------------------------------
+// Async-MM (Sec. 3.2, "Ablation study and comparative analysis"): the
+// Worker's direction d' = -A_S(x)^{-1} grad_S f, the half-quadratic block
+// majorant inverted by an inner linear solve.  A_S p for a block vector p
+// (zero outside S) is H^T H p + 2 eta p + lambda V^T Diag(omega(x)) V p +
+// 2 kappa VZ^T VZ p + mu p restricted to S: H p on S +- r_z comes from the
+// direction pass, XY^T (H p) per slice from the update pass (assign mode),
+// and k_majapply adds the z-gather of it to the other terms.
+// ---------------------------------------------------------------------------
+
+// Fixed-order sum of count slots (stride doubles apart) from first, the same
+// total on every thread of the workgroup: each thread in slot order, the
+// wavefronts by DPP moves, then the wavefronts in order.
+__device__ __forceinline__ double slots_sum(const double *__restrict__ base, int stride, int first, int count)
+{
+    __shared__ double red[NT / 64];
+    __shared__ double tot;
+    double v = 0.0;
+    for (int t = threadIdx.x; t < count; t += NT) v += base[(size_t)(first + t) * stride];
+    v = wave_sum_last(v);
+    if ((threadIdx.x & 63) == 63) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0;
+        for (int w = 0; w < NT / 64; ++w) a += red[w];
+        tot = a;
+    }
+    __syncthreads();
+    return tot;
+}
+
+template <typename T, int KZ>
+__global__ void __launch_bounds__(NT)
+k_majapply(Geom g, Params prm, DevState<T> s, const T *__restrict__ qt, const T *__restrict__ x,
+           const T *__restrict__ pv, T *__restrict__ ap, const Item *__restrict__ items,
+           double *__restrict__ partials)
+{
+    constexpr int RZ = KZ / 2;
+    constexpr int XW = TX + 3, XH = TY + 3;  // x and p at (y0-1+jj, x0-1+ii)
+    constexpr int PW = TX + 2, PH = TY + 2;  // w VX p, w VY p at (y0-1+jj, x0-1+ii)
+    __shared__ T X[padded<XW, XH>()];
+    __shared__ T P[padded<XW, XH>()];
+    __shared__ T PX[padded<PW, PH>()];
+    __shared__ T PY[padded<PW, PH>()];
+    __shared__ double red[NT / 64];
+
+    const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;
+    const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int tx = threadIdx.x & (TX - 1);
+    const size_t S = (size_t)g.nx * g.ny;
+    Region<XW, XH, 1, 1> rx(g, x0, y0);
+#pragma unroll
+    for (int qq = 0; qq < rx.E; ++qq) {
+        const size_t o = (size_t)k * S + rx.off[qq];
+        X[threadIdx.x + qq * NT] = rx.inb[qq] ? x[o] : T(0);
+        P[threadIdx.x + qq * NT] = rx.inb[qq] ? pv[o] : T(0);
+    }
+    // data part at the thread's outputs: sum_c gz_{k+c}[c] qt_{k+c}
+    T ht[RPT];
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        ht[e] = 0;
+        const int j = y0 + out_row<RPT>(e), i = x0 + tx;
+        if (i >= g.nx || j >= g.ny) continue;
+        const size_t o = (size_t)j * g.nx + i;
+#pragma unroll
+        for (int c = -RZ; c <= RZ; ++c) {
+            const int m = k + c;
+            if (m < 0 || m >= g.nz) continue;
+            ht[e] += s.gz[(size_t)m * KZ + (c + RZ)] * qt[(size_t)m * S + o];
+        }
+    }
+    __syncthreads();
+    // omega from x, omega VX p and omega VY p; zero outside the slice
+    const T del2 = (T)(prm.delta * prm.delta);
+    {
+        constexpr int N = PW * PH, E = cdiv(N, NT);
+#pragma unroll
+        for (int qq = 0; qq < E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            if (e < N) {
+                const int jj = e / PW, ii = e - jj * PW;
+                const int j = y0 - 1 + jj, i = x0 - 1 + ii;
+                T px = 0, py = 0;
+                if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
+                    const T *xc = X + jj * XW + ii;
+                    const T *pc = P + jj * XW + ii;
+                    const bool hx = i < g.nx - 1, hy = j < g.ny - 1;
+                    const T dxv = hx ? xc[1] - xc[0] : T(0), dyv = hy ? xc[XW] - xc[0] : T(0);
+                    const T w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
+                    px = w * (hx ? pc[1] - pc[0] : T(0));
+                    py = w * (hy ? pc[XW] - pc[0] : T(0));
+                }
+                PX[e] = px;
+                PY[e] = py;
+            }
+        }
+    }
+    __syncthreads();
+    const T lam = (T)prm.lambda, eta2 = (T)(2.0 * prm.eta), kap2 = (T)(2.0 * prm.kappa), mu = (T)prm.mu;
+    double acc = 0.0;
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int lj = out_row<RPT>(e), li = tx;
+        const int j = y0 + lj, i = x0 + li;
+        if (i >= g.nx || j >= g.ny) continue;
+        const int pc = (lj + 1) * PW + (li + 1);
+        const T tv = PX[pc - 1] - PX[pc] + PY[pc - PW] - PY[pc];
+        const T pval = P[(lj + 1) * XW + (li + 1)];
+        T a = ht[e] + eta2 * pval;
+        a += lam * tv;
+        const size_t o = (size_t)k * S + (size_t)j * g.nx + i;
+        if (prm.kappa != 0.0) {
+            // VZ^T VZ p with p zero outside the block
+            const T pm = (k - 1 >= z0) ? pv[o - S] : T(0), pp = (k + 1 < z1) ? pv[o + S] : T(0);
+            T zz = 0;
+            if (k >= 1) zz += pval - pm;
+            if (k < g.nz - 1) zz -= pp - pval;
+            a += kap2 * zz;
+        }
+        a += mu * pval;
+        ap[o] = a;
+        acc += (double)pval * (double)a;
+    }
+    double q1[1] = {acc};
+    wg_reduce_store<1>(q1, red, partials + slot_of());
+}
+
+// Elementwise stages of the inner solve on the gradient items of a launch
+// group (tile TX x TY, four outputs a thread); the first workgroup of a block
+// (its first slice, tile 0) keeps the block's scalars.  Scalars that a stage
+// reads are written by another stage (rho and done are double-buffered by
+// iteration parity), so no launch reads what it writes.
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_cg(int stage, Geom g, DevState<T> s, const Item *__restrict__ items, CgBufs<T> b, int parity, double tol_inner)
+{
+    const Item it = items[blockIdx.z];
+    if (s.stop && *s.stop) return;
+    const int k = it.k, blk = it.block;
+    const int ntiles = gridDim.x * gridDim.y;
+    const bool first = (k == it.z0) && blockIdx.x == 0 && blockIdx.y == 0;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int tx = threadIdx.x & (TX - 1);
+    const size_t S = (size_t)g.nx * g.ny;
+    double *cs = b.cgs + (size_t)CG_STRIDE * blk;
+    size_t o[RPT];
+    bool in[RPT];
+#pragma unroll
+    for (int e = 0; e < RPT; ++e) {
+        const int j = y0 + out_row<RPT>(e), i = x0 + tx;
+        in[e] = i < g.nx && j < g.ny;
+        o[e] = in[e] ? (size_t)k * S + (size_t)j * g.nx + i : 0;
+    }
+    if (stage == CG_INIT) {
+        // r = b - A v = -g with v = 0, p = r
+#pragma unroll
+        for (int e = 0; e < RPT; ++e)
+            if (in[e]) {
+                const T r = -s.g[o[e]];
+                b.r[o[e]] = r;
+                b.p[o[e]] = r;
+                b.v[o[e]] = 0;
+            }
+        if (first) {
+            const double gg = slots_sum(b.pg, NQG, it.h0 * ntiles, it.hn * ntiles);
+            if (threadIdx.x == 0) {
+                cs[0] = cs[1] = gg;  // rho = <r, r>
+                cs[2] = cs[3] = 0.0;  // not done
+                cs[4] = sqrt(gg);     // ||r_0||
+                cs[5] = 0.0;          // iterations
+                cs[6] = gg;           // ||r||^2 at the end
+                cs[7] = gg;           // ||g||^2
+            }
+        }
+        return;
+    }
+    if (stage == CG_FINAL) {
+        // the direction and update passes then apply d' = v (as -g, u = (1, 0))
+#pragma unroll
+        for (int e = 0; e < RPT; ++e)
+            if (in[e]) s.g[o[e]] = -b.v[o[e]];
+        if (first && threadIdx.x == 0) {
+            double *inf = b.info + 8 * (size_t)blk;
+            inf[0] = cs[5];
+            inf[1] = cs[6];
+            inf[2] = 0.0;
+            inf[3] = -cs[7];
+            inf[4] = inf[5] = inf[6] = 0.0;
+            inf[7] = cs[7];
+        }
+        return;
+    }
+    const double rho = cs[parity];
+    const bool done = cs[2 + parity] != 0.0;
+    const double den = slots_sum(b.pa, 1, it.h0 * ntiles, it.hn * ntiles);
+    const bool active = !done && rho != 0.0 && den != 0.0;
+    if (stage == CG_VEC) {
+        // v += alpha p, r -= alpha A p, alpha = <r, r> / <p, A p>; then <r, r>
+        const T alpha = active ? (T)(rho / den) : T(0);
+        double rr = 0.0;
+#pragma unroll
+        for (int e = 0; e < RPT; ++e)
+            if (in[e]) {
+                T r = b.r[o[e]];
+                if (active) {
+                    b.v[o[e]] += alpha * b.p[o[e]];
+                    r -= alpha * b.ap[o[e]];
+                    b.r[o[e]] = r;
+                }
+                rr += (double)r * (double)r;
+            }
+        __shared__ double red[NT / 64];
+        double q1[1] = {rr};
+        wg_reduce_store<1>(q1, red, b.prr + slot_of());
+        return;
+    }
+    // CG_DIR: stop at the tolerance, else p = r + beta p, beta = <r, r>_new / <r, r>
+    const double rr = slots_sum(b.prr, 1, it.h0 * ntiles, it.hn * ntiles);
+    const bool stop = !active || (tol_inner > 0.0 && sqrt(rr) <= tol_inner * cs[4]);
+    if (!stop) {
+        const T beta = (T)(rr / rho);
+#pragma unroll
+        for (int e = 0; e < RPT; ++e)
+            if (in[e]) b.p[o[e]] = b.r[o[e]] + beta * b.p[o[e]];
+    }
+    if (first && threadIdx.x == 0) {
+        cs[2 + (parity ^ 1)] = (done || stop) ? 1.0 : 0.0;
+        cs[parity ^ 1] = rr;
+        if (active) {
+            cs[5] += 1.0;
+            cs[6] = rr;
+        }
+    }
+}
+
 // Streaming copy of n 16-byte words, grid-stride over chunks of U NT words:
 // each lane issues its U loads (coalesced, NT words apart) before its U
 // stores, so U loads per lane are in flight at once.
@@ -1490,18 +1745,38 @@ hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, c
 
 template <typename T>
 hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items, int nitems,
-                         const int2 *pairs, const double *u, bool multi, hipStream_t st)
+                         const int2 *pairs, const double *u, bool multi, hipStream_t st, int assign)
 {
     if (nitems <= 0) return hipSuccess;
     if (multi) {
         BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
                        BD3MG_LAUNCH((k_update<T, R, TYK, true>), grid_of(g, nitems, TYK), dim3(NT), 0,
-                                          st, g, s, items, pairs, u)));
+                                          st, g, s, items, pairs, u, assign)));
     } else {
         BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
                        BD3MG_LAUNCH((k_update<T, R, TYK, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
-                                          st, g, s, items, pairs, u)));
+                                          st, g, s, items, pairs, u, assign)));
     }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_majapply(const Geom &g, const Params &prm, const DevState<T> &s, const T *qt, const T *x,
+                           const T *pv, T *ap, const Item *items, int nitems, double *partials, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_KZ_SWITCH(2 * g.rz + 1,
+                    BD3MG_LAUNCH((k_majapply<T, KZ>), grid_of(g, nitems), dim3(NT), 0, st, g, prm, s, qt, x,
+                                 pv, ap, items, partials));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg(int stage, const Geom &g, const DevState<T> &s, const Item *items, int nitems,
+                     const CgBufs<T> &b, int parity, double tol_inner, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    BD3MG_LAUNCH((k_cg<T>), grid_of(g, nitems), dim3(NT), 0, st, stage, g, s, items, b, parity, tol_inner);
     return hipGetLastError();
 }
 
@@ -1686,7 +1961,12 @@ hipError_t scratch_base(int device, void **ptr)
     template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
                                        const Item *, int, double *, hipStream_t);                 \
     template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Item *, int,      \
-                                         const int2 *, const double *, bool, hipStream_t);        \
+                                         const int2 *, const double *, bool, hipStream_t, int);   \
+    template hipError_t launch_majapply<T>(const Geom &, const Params &, const DevState<T> &,      \
+                                           const T *, const T *, const T *, T *, const Item *, int, \
+                                           double *, hipStream_t);                                \
+    template hipError_t launch_cg<T>(int, const Geom &, const DevState<T> &, const Item *, int,    \
+                                     const CgBufs<T> &, int, double, hipStream_t);                \
     template hipError_t launch_refresh<T>(const Geom &, const DevState<T> &, const T *, T *,       \
                                           const Item *, int, hipStream_t);                        \
     template hipError_t launch_H<T>(const Geom &, const DevState<T> &, const T *, const T *, T *,  \
