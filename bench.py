@@ -31,6 +31,8 @@ Prints one JSON line:
   (stored samples);
 * the same under asynchronous rounds, with the paper's majorant (outside
   Assumption C) and with the inflation that Assumption C asks for;
+* the ablation study of Sec. 3.2: time and sweeps to 1e-4 of BD3MG, Async-GD,
+  Async-CG and Async-MM on the same workload;
 * the FP64 CPU oracle timed on a bounded sample, on all host cores and on one.
 """
 import argparse
@@ -346,6 +348,34 @@ def round_schedule(binding, w, args):
     return out
 
 
+def ablation(binding, w, args):
+    """The ablation study of Sec. 3.2 on the same workload (coloured order,
+    x0 = y): time and sweeps to ||grad f|| <= 1e-4 ||grad f(y)|| for BD3MG,
+    Async-GD and Async-CG (metric L Id, L the Lipschitz bound) and Async-MM
+    (at most n_inner conjugate-gradient iterations on each block majorant,
+    stopping at a relative residual tol_inner), each within a sweep cap."""
+    g = make_problem(binding, w)
+    g.get_schedule()
+    out = {"tol": 1e-4, "lipschitz_bound": g.lipschitz_bound()}
+    runs = [("BD3MG", binding.METHOD_BD3MG, {}, args.ablation_cap),
+            ("Async-GD", binding.METHOD_ASYNC_GD, {}, args.ablation_cap),
+            ("Async-CG", binding.METHOD_ASYNC_CG, {}, args.ablation_cap),
+            ("Async-MM", binding.METHOD_ASYNC_MM, {"n_inner": 20, "tol_inner": 1e-2}, args.ablation_cap_mm)]
+    for name, code, kw, cap in runs:
+        g.set_method(code, **kw)
+        g.set_x0(None)
+        g.run(1, check_every=0)  # warm-up (buffers, caches)
+        g.set_x0(None)
+        t0 = time.perf_counter()
+        res = g.run(cap, grad_rtol=1e-4, check_every=binding.CHECK_ADAPTIVE)
+        secs = time.perf_counter() - t0
+        out[name] = dict({"seconds": secs, "sweeps": res["sweeps"], "converged": bool(res["converged"]),
+                          "grad_rel": res["grad_norm"] / res["grad_norm_ref"], "f": res["f"],
+                          "ms_per_sweep": 1e3 * secs / max(res["sweeps"], 1), "sweep_cap": cap}, **kw)
+    g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +392,9 @@ def main():
     ap.add_argument("--no-round", action="store_true", help="skip the asynchronous-round schedule")
     ap.add_argument("--no-large", action="store_true", help="skip the 512x512x128 sub-line")
     ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--no-ablation", action="store_true", help="skip the ablation methods of Sec. 3.2")
+    ap.add_argument("--ablation-cap", type=int, default=4000, help="sweep cap of BD3MG, Async-GD, Async-CG")
+    ap.add_argument("--ablation-cap-mm", type=int, default=400, help="sweep cap of Async-MM")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -449,6 +482,9 @@ def main():
 
     if not args.no_round:
         out["round_schedule"] = round_schedule(binding, w, args)
+
+    if not args.no_ablation and not is_dense(w):
+        out["ablation"] = ablation(binding, w, args)
 
     if not args.no_large and w.name == "plain-fp32-256x256x64":
         wl = inputs.WORKLOADS["plain-fp32-512x512x128"]()
