@@ -100,6 +100,13 @@ def _seeds(base):
             np.random.default_rng(base + 3))
 
 
+def paper_x0(y, seed):
+    """The paper's starting point (Sec. 3.1, experimental setup): entries drawn
+    uniformly in [0, max(y)], x fastest, from default_rng(seed)."""
+    y = np.asarray(y)
+    return np.random.default_rng(seed).uniform(0.0, float(np.max(y)), size=y.shape)
+
+
 def small_plain_fp64(seed=1000):
     """64x64x16 FP64 volume, 20 ellipsoids, PSF 5x5x5 (sigma_xy 0.5 -> 2.0 over
     z, sigma_z = 1), noise 0.02, lambda 0.01, delta 0.02, eta 0.01, four blocks

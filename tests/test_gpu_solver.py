@@ -133,6 +133,26 @@ def test_adaptive_checks_stop_where_every_sweep_checks_do(orc, prec):
     assert e.value.status == binding.ERR_ARG
 
 
+@pytest.mark.parametrize("prec", [binding.FP64, binding.FP32])
+def test_paper_initial_point(orc, prec):
+    """The paper's start, x0 uniform in [0, max(y)] (drawn once, given to both
+    sides), on the 64x64x16 workload: 30 sweeps against the oracle."""
+    g, o, y, w = _c1(orc, inputs.small_plain_fp64(), _c1_y(orc), prec)
+    nc, order, color = g.get_schedule()
+    x0 = rounded(inputs.paper_x0(y, seed=77), prec)
+    assert x0.min() >= 0.0 and x0.max() <= y.max()
+    g.set_x0(x0)
+    res = g.run(30)
+    x = x0.copy()
+    d = np.zeros(w.shape)
+    o.run(x, d, w.nslices, order, 30, history=False)
+    e = rel(g.get_x(), x)
+    assert e <= (1e-11 if prec == binding.FP64 else 2e-5), e
+    assert abs(res["f"] - o.f(x)) <= (1e-12 if prec == binding.FP64 else 1e-6) * o.f(x)
+    # the reference of the stop test is ||grad f(y)||, whatever x0 is
+    assert abs(res["grad_norm_ref"] - o.grad_norm(y)) <= 1e-6 * o.grad_norm(y)
+
+
 def test_determinism_and_resume(orc):
     g, o, y, w = _c1(orc, inputs.small_plain_fp64(), _c1_y(orc), binding.FP32)
     g.set_option(binding.OPT_REFRESH_EVERY, 4)  # refreshes fall inside the chained runs
