@@ -33,6 +33,8 @@ Prints one JSON line:
   Assumption C) and with the inflation that Assumption C asks for;
 * the ablation study of Sec. 3.2: time and sweeps to 1e-4 of BD3MG, Async-GD,
   Async-CG and Async-MM on the same workload;
+* batches of problems (16 uneven volumes; 48 small ones) with fused launches
+  and with graph branches;
 * the FP64 CPU oracle timed on a bounded sample, on all host cores and on one.
 """
 import argparse
@@ -377,6 +379,43 @@ def ablation(binding, w, args):
     return out
 
 
+def batches(binding, inputs, sweeps=50):
+    """Batched problems advanced together (two sweeps per graph launch): the
+    16-volume batch of uneven sizes (128..256 x 128..256 x 32..96, PSF 7x7x7,
+    4..16 blocks) and 48 small volumes (64x64x32, PSF 7x7x7, 6 blocks), each
+    with fused launches (every pass of a colour index once for all problems)
+    and with the problems as graph branches; the automatic mode's choice is
+    marked."""
+    out = {}
+    sets = [("uneven-16x(128..256)^2x(32..96)", [inputs.batch_member(p) for p in range(16)]),
+            ("small-48x64x64x32", [inputs.tiny((32, 64, 64), 900 + i, kxy=7, kz=7, nblocks=6, n_ellipsoids=6)
+                                   for i in range(48)])]
+    for name, ws in sets:
+        for w in ws:
+            w.fp64 = False
+        probs = [make_problem(binding, w) for w in ws]
+        for q in probs:
+            q.set_x0(None)
+        nvox = sum(int(np.prod(w.shape)) for w in ws)
+        b = binding.Batch(probs)
+        auto = b.set_mode(binding.BATCH_AUTO)
+        rec = {"volumes": len(ws), "voxels": nvox, "sweeps": sweeps,
+               "auto_mode": "fused" if auto else "branches"}
+        for mode, key in ((binding.BATCH_FUSED, "fused"), (binding.BATCH_BRANCHES, "branches")):
+            b.set_mode(mode)
+            b.tune()  # fused launches take one tile height for all problems
+            ran_fused = b.set_mode(mode)
+            b.run(4)  # capture and warm-up
+            r = b.run(sweeps)
+            rec[key] = {"value": nvox * sweeps / r[0]["seconds"], "unit": "voxel-iterations/s",
+                        "ms_per_sweep": 1e3 * r[0]["seconds"] / sweeps, "fused_launches": ran_fused}
+        out[name] = rec
+        b.close()
+        for q in probs:
+            q.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -394,6 +433,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 512x512x128 sub-line")
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-ablation", action="store_true", help="skip the ablation methods of Sec. 3.2")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-problem runs")
     ap.add_argument("--ablation-cap", type=int, default=4000, help="sweep cap of BD3MG, Async-GD, Async-CG")
     ap.add_argument("--ablation-cap-mm", type=int, default=400, help="sweep cap of Async-MM")
     args = ap.parse_args()
@@ -496,6 +536,9 @@ def main():
 
     if not args.no_ablation and not is_dense(w):
         out["ablation"] = ablation(binding, w, args)
+
+    if not args.no_batch and w.name == "plain-fp32-256x256x64":
+        out["batch"] = batches(binding, inputs)
 
     if not args.no_large and w.name == "plain-fp32-256x256x64":
         wl = inputs.WORKLOADS["plain-fp32-512x512x128"]()

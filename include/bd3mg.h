@@ -375,9 +375,17 @@ bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms)
 
 /* ---------------------------------------------------------------------------
  * Batches: many independent problems (own sizes, PSF, data, parameters and
- * block partitions) advanced together.  Each problem's sweep is captured on
- * its own stream into one HIP graph (fork/join), so one graph launch runs two
- * sweeps of every problem with the problems as parallel branches.
+ * block partitions) advanced together, two sweeps per HIP graph launch.
+ * Fused launches (when every problem has the same precision, z extent,
+ * in-slice radius and tile heights, the separable PSF, BD3MG's step and a
+ * coloured or sequential schedule; see bd3mg_batch_set_mode for when they
+ * are used): each pass of a colour index runs
+ * once for all problems, its grid the concatenation of every problem's
+ * work list (each problem as many workgroups as its own launch would have),
+ * so a sweep of the whole batch is 4 x (most colours) launches; results are
+ * bitwise those of the problems run one by one.  Branch mode (or a batch
+ * that cannot be fused): each problem's sweep is captured on its own stream
+ * into the graph (fork/join), problems as parallel branches.
  * ------------------------------------------------------------------------- */
 typedef struct bd3mg_batch_s *bd3mg_batch;
 
@@ -388,8 +396,24 @@ typedef struct bd3mg_batch_s *bd3mg_batch;
 bd3mg_status bd3mg_batch_create(int n, const bd3mg_problem *probs, bd3mg_batch *out);
 bd3mg_status bd3mg_batch_destroy(bd3mg_batch b);
 
-/* Run bd3mg_autotune on every problem of the batch (tile heights per shape). */
+/* Tile heights for the batch: when it runs fused launches, bd3mg_autotune on
+ * the largest problem, whose choice every problem of its precision then
+ * takes (a fused launch has one tile height); with graph branches,
+ * bd3mg_autotune on every problem. */
 bd3mg_status bd3mg_batch_tune(bd3mg_batch b);
+
+/* Batch mode: BD3MG_BATCH_AUTO (default: fused launches when the batch can
+ * be fused and its volumes total at most 64 MiB of storage, graph branches
+ * otherwise), BD3MG_BATCH_FUSED (whenever the batch can be fused) or
+ * BD3MG_BATCH_BRANCHES.  Measured on one MI355X: 48 volumes of 64x64x32 run
+ * 3x faster fused (every problem's launch alone is a few dozen workgroups);
+ * 16 volumes of 128..256 x 128..256 x 32..96 (146 MB) run 1.6x faster as
+ * branches (4 hardware queues run 4 problems at a time, whose data stays in
+ * the caches, where a fused launch streams every problem's colour slab).
+ * *fused (may be NULL) receives 1 when the batch will run fused launches as
+ * it stands.  ERR_ARG: unknown mode. */
+typedef enum { BD3MG_BATCH_AUTO = 0, BD3MG_BATCH_FUSED = 1, BD3MG_BATCH_BRANCHES = 2 } bd3mg_batch_mode;
+bd3mg_status bd3mg_batch_set_mode(bd3mg_batch b, int mode, int *fused);
 
 /* Advance every problem by max_sweeps sweeps (graph launches of two sweeps,
  * then one direct sweep when max_sweeps is odd).  With grad_rtol > 0 the

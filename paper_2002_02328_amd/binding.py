@@ -22,6 +22,7 @@ OP_H, OP_HT, OP_GRAD = 0, 1, 2
 OK, ERR_ARG, ERR_STATE, ERR_NOMEM, ERR_HIP, ERR_NOT_CONVERGED = range(6)
 CHECK_ADAPTIVE = -1  # check_every of run(): checks spaced by the trend of ||grad f||
 METHOD_BD3MG, METHOD_ASYNC_GD, METHOD_ASYNC_CG, METHOD_ASYNC_MM = 0, 1, 2, 3
+BATCH_AUTO, BATCH_FUSED, BATCH_BRANCHES = 0, 1, 2
 OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
 OPT_TILE_ROWS_DIRS, OPT_TILE_ROWS_UPDATE, OPT_TILE_ROWS_AUX, OPT_DIRS_SLICES = 2, 3, 4, 5
 KERNEL_KINDS = ("grad", "dirs", "solve", "update", "eval")
@@ -46,6 +47,7 @@ SIGNATURES = {
     "bd3mg_run": ([_dp, _i, _d, _i, _dp], C.c_int),
     "bd3mg_run_noalloc": ([_dp, _i, _d, _i, _dp], C.c_int),
     "bd3mg_set_method": ([_dp, _i, _d, _i, _d], C.c_int),
+    "bd3mg_batch_set_mode": ([_dp, _i, _dp], C.c_int),
     "bd3mg_get_x": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_dprev": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_state": ([_dp, _dp, _dp, _dp, _dp, _i], C.c_int),
@@ -364,6 +366,13 @@ class Batch:
 
     def tune(self):
         _check(load().bd3mg_batch_tune(self._h))
+
+    def set_mode(self, mode):
+        """BATCH_AUTO, BATCH_FUSED or BATCH_BRANCHES; returns whether fused
+        launches will run."""
+        f = C.c_int()
+        _check(load().bd3mg_batch_set_mode(self._h, int(mode), C.byref(f)))
+        return bool(f.value)
 
     def run(self, max_sweeps, grad_rtol=0.0, check_every=0):
         res = (Result * len(self.problems))()

@@ -1793,6 +1793,14 @@ struct bd3mg_batch_s {
     hipGraphExec_t exec = nullptr;
     std::vector<char> captured;  // problems in the graph
     std::vector<int> cap_cur;    // their previous-step buffer at capture
+    int mode = BD3MG_BATCH_AUTO;
+    bool cap_fused = false;      // the graph holds fused launches
+    // fused launches: the per-problem argument sets and owner tables of
+    // every (sweep of two, colour index, pass)
+    void *d_fa = nullptr;
+    size_t fa_cap = 0;
+    unsigned char *d_owner = nullptr;
+    size_t owner_cap = 0;
 };
 
 namespace {
@@ -1842,9 +1850,158 @@ bd3mg_status batch_capture(bd3mg_batch b, const std::vector<char> &active)
     return BD3MG_OK;
 }
 
+// Whether one fused launch per pass can serve every problem: the same
+// precision, z extent, in-slice radius and tile heights (template
+// parameters), separable PSF, BD3MG's step, a coloured or sequential
+// schedule (one source per update item).
+bool batch_fusable(bd3mg_batch b)
+{
+    const bd3mg_problem p0 = b->probs[0];
+    for (bd3mg_problem p : b->probs) {
+        if (p->prec != p0->prec || p->dense || p->schedule == BD3MG_SCHED_ROUND || p->prm.method != M_BD3MG)
+            return false;
+        if (p->kz != p0->kz || p->geom.R != p0->geom.R || p->geom.ty_dirs != p0->geom.ty_dirs ||
+            p->geom.ty_update != p0->geom.ty_update)
+            return false;
+    }
+    return b->probs.size() <= 255;
+}
+
+// Whether the batch runs fused launches in its mode (see bd3mg_batch_set_mode).
+bool batch_uses_fused(bd3mg_batch b)
+{
+    if (b->mode == BD3MG_BATCH_BRANCHES || !batch_fusable(b)) return false;
+    if (b->mode == BD3MG_BATCH_FUSED) return true;
+    double bytes = 0.0;
+    for (bd3mg_problem p : b->probs) bytes += (double)p->N * p->esz;
+    return bytes <= 64.0 * 1024 * 1024;
+}
+
+// Capture two sweeps of every active problem as fused launches on the batch
+// stream: for each sweep, colour index and pass, one launch whose grid holds
+// the workgroups of that pass of every active problem with that colour.
+template <typename T>
+bd3mg_status batch_capture_fused_t(bd3mg_batch b, const std::vector<char> &active)
+{
+    const int n = (int)b->probs.size();
+    int maxc = 0;
+    for (int i = 0; i < n; ++i)
+        if (active[i]) maxc = std::max(maxc, b->probs[i]->ncolors);
+    struct Set {
+        size_t fa0, ow0;
+        unsigned nwg;
+        int pass;
+    };
+    std::vector<Set> sets;
+    std::vector<FusedArgs<T>> fa;
+    std::vector<unsigned char> owner;
+    for (int sw = 0; sw < 2; ++sw)
+        for (int c = 0; c < maxc; ++c)
+            for (int pass = FP_GRAD; pass <= FP_UPDATE; ++pass) {
+                Set st{fa.size(), owner.size(), 0, pass};
+                unsigned wg = 0;
+                int local = 0;
+                for (int i = 0; i < n; ++i) {
+                    bd3mg_problem p = b->probs[i];
+                    if (!active[i] || c >= p->ncolors) continue;
+                    const auto &gr = p->groups[c];
+                    const int cur = p->cur;
+                    p->cur = cur ^ sw;  // the previous-step buffers of this sweep
+                    FusedArgs<T> a{};
+                    a.g = p->geom;
+                    a.prm = p->prm;
+                    a.s = dev_state<T>(p);
+                    p->cur = cur;
+                    a.pg = p->d_pg;
+                    a.pd = p->d_pd;
+                    a.u = p->d_u;
+                    a.info = p->d_info;
+                    a.gx = (unsigned)p->geom.ntx;
+                    if (pass == FP_GRAD) {
+                        a.items = p->d_items + gr.g_off;
+                        a.nitems = gr.g_cnt;
+                        a.gy = (unsigned)p->geom.nty;
+                    } else if (pass == FP_DIRS) {
+                        a.items = p->d_units + gr.du_off;
+                        a.nitems = gr.du_cnt;
+                        a.gy = (unsigned)((p->ny + p->geom.ty_dirs - 1) / p->geom.ty_dirs);
+                    } else if (pass == FP_SOLVE) {
+                        a.brs = p->d_br + gr.br_off;
+                        a.nitems = gr.br_cnt;
+                        a.gx = a.gy = 1;
+                        a.ntg = p->ntiles;
+                        a.ntd = tiles_of(p->geom, p->geom.ty_dirs);
+                    } else {
+                        a.items = p->d_items + gr.u_off;
+                        a.nitems = gr.u_cnt;
+                        a.gy = (unsigned)((p->ny + p->geom.ty_update - 1) / p->geom.ty_update);
+                        a.pairs = p->d_pairs;
+                    }
+                    a.wg0 = wg;
+                    const unsigned cnt = a.gx * a.gy * (unsigned)a.nitems;
+                    const unsigned end = (wg + cnt + 7) / 8 * 8;
+                    for (unsigned h = wg; h < end; h += 8) owner.push_back((unsigned char)local);
+                    wg = end;
+                    fa.push_back(a);
+                    ++local;
+                }
+                st.nwg = wg;
+                sets.push_back(st);
+            }
+    if (fa.empty()) return fail(BD3MG_ERR_STATE, "no active problem in the batch");
+    ST_TRY(realloc_dev(&b->d_fa, &b->fa_cap, fa.size() * sizeof(FusedArgs<T>), "fused launch arguments"));
+    ST_TRY(realloc_dev((void **)&b->d_owner, &b->owner_cap, std::max<size_t>(owner.size(), 1),
+                       "fused launch owners"));
+    HIP_TRY(hipMemcpy(b->d_fa, fa.data(), fa.size() * sizeof(FusedArgs<T>), hipMemcpyHostToDevice));
+    if (!owner.empty()) HIP_TRY(hipMemcpy(b->d_owner, owner.data(), owner.size(), hipMemcpyHostToDevice));
+    // the problems' earlier work (set-up, checks) is complete before the graph runs
+    for (bd3mg_problem p : b->probs) HIP_TRY(hipStreamSynchronize(p->stream));
+    batch_drop_graph(b);
+    const Geom &g0 = b->probs[0]->geom;
+    HIP_TRY(hipStreamBeginCapture(b->s0, hipStreamCaptureModeRelaxed));
+    hipError_t e = hipSuccess;
+    for (const Set &st : sets) {
+        if (e != hipSuccess) break;
+        e = launch_fused<T>(st.pass, g0, (const FusedArgs<T> *)b->d_fa + st.fa0, b->d_owner + st.ow0, st.nwg,
+                            b->s0);
+    }
+    hipGraph_t gph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(b->s0, &gph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (gph) (void)hipGraphDestroy(gph);
+        return fail(BD3MG_ERR_HIP, "fused graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    b->graph = gph;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->captured = active;
+    for (int i = 0; i < n; ++i) b->cap_cur[i] = b->probs[i]->cur;
+    b->cap_fused = true;
+    return BD3MG_OK;
+}
+
+bd3mg_status batch_capture_any(bd3mg_batch b, const std::vector<char> &active)
+{
+    if (batch_uses_fused(b))
+        return b->probs[0]->prec == BD3MG_FP64 ? batch_capture_fused_t<double>(b, active)
+                                               : batch_capture_fused_t<float>(b, active);
+    b->cap_fused = false;
+    return batch_capture(b, active);
+}
+
 }  // namespace
 
 extern "C" {
+
+bd3mg_status bd3mg_batch_set_mode(bd3mg_batch b, int mode, int *fused)
+{
+    if (!b) return fail(BD3MG_ERR_ARG, "null batch");
+    if (mode != BD3MG_BATCH_AUTO && mode != BD3MG_BATCH_FUSED && mode != BD3MG_BATCH_BRANCHES)
+        return fail(BD3MG_ERR_ARG, "unknown batch mode %d", mode);
+    if (mode != b->mode) batch_drop_graph(b);
+    b->mode = mode;
+    if (fused) *fused = batch_uses_fused(b) ? 1 : 0;
+    return BD3MG_OK;
+}
 
 bd3mg_status bd3mg_batch_create(int n, const bd3mg_problem *probs, bd3mg_batch *out)
 {
@@ -1881,6 +2038,8 @@ bd3mg_status bd3mg_batch_destroy(bd3mg_batch b)
     if (!b) return BD3MG_OK;
     if (b->s0) (void)hipStreamSynchronize(b->s0);
     batch_drop_graph(b);
+    if (b->d_fa) (void)hipFree(b->d_fa);
+    if (b->d_owner) (void)hipFree(b->d_owner);
     for (hipEvent_t e : b->join)
         if (e) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -1894,7 +2053,22 @@ bd3mg_status bd3mg_batch_destroy(bd3mg_batch b)
 bd3mg_status bd3mg_batch_tune(bd3mg_batch b)
 {
     if (!b) return fail(BD3MG_ERR_ARG, "null batch");
-    for (bd3mg_problem p : b->probs) ST_TRY(bd3mg_autotune(p, 3, nullptr, nullptr));
+    if (b->mode != BD3MG_BATCH_BRANCHES && batch_fusable(b) &&
+        (b->mode == BD3MG_BATCH_FUSED || batch_uses_fused(b))) {
+        // fused launches need one set of tile heights: the largest problem's
+        bd3mg_problem big = b->probs[0];
+        for (bd3mg_problem p : b->probs)
+            if (p->N > big->N) big = p;
+        int ch[2] = {0, 0};
+        ST_TRY(bd3mg_autotune(big, 3, ch, nullptr));
+        for (bd3mg_problem p : b->probs)
+            if (p->prec == big->prec && !p->dense) {
+                p->geom.ty_dirs = ch[0];
+                p->geom.ty_update = ch[1];
+            }
+    } else {
+        for (bd3mg_problem p : b->probs) ST_TRY(bd3mg_autotune(p, 3, nullptr, nullptr));
+    }
     batch_drop_graph(b);  // tile heights are baked into the captured launches
     return BD3MG_OK;
 }
@@ -1924,7 +2098,7 @@ bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, in
         bool recapture = !b->exec || b->captured != active;
         for (int i = 0; i < n && !recapture; ++i)
             if (active[i] && b->cap_cur[i] != b->probs[i]->cur) recapture = true;
-        if (recapture) ST_TRY(batch_capture(b, active));
+        if (recapture) ST_TRY(batch_capture_any(b, active));
         HIP_TRY(hipGraphLaunch(b->exec, b->s0));
         bool need_sync = stopping && ((s + 2) % ce == 0);
         for (int i = 0; i < n; ++i) {

@@ -235,6 +235,33 @@ hipError_t launch_sum(const double *partials, int nslot, int nq, double *out, hi
 constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
 hipError_t scratch_base(int device, void **ptr);
 
+// One problem's part of a fused batch pass: every problem's gradient,
+// direction, solve or update pass of the same colour index runs in one
+// launch, its workgroups from wg0 on (a multiple of 8, so a workgroup's XCD
+// is the same as in a launch of its own); owner[h / 8] is the problem of
+// workgroup h.  All problems of a fused launch share the precision, the z
+// extent, the in-slice radius and the tile heights (template parameters).
+template <typename T>
+struct FusedArgs {
+    Geom g;
+    Params prm;
+    DevState<T> s;
+    const Item *items;      // gradient items, direction units or update items of the colour
+    const BlockRange *brs;  // solve: the colour's block ranges
+    const int2 *pairs;      // update: source pairs
+    double *u;              // solve: written; update: read
+    double *pg, *pd;        // gradient and direction partial sums
+    double *info;           // solve: per-block info
+    int nitems;             // work items (solve: block ranges) of this problem in the pass
+    int ntg, ntd;           // solve: tiles per item of the gradient and direction passes
+    unsigned wg0;           // first workgroup of this problem in the fused grid
+    unsigned gx, gy;        // tiles per slice of the pass
+};
+enum : int { FP_GRAD = 0, FP_DIRS = 1, FP_SOLVE = 2, FP_UPDATE = 3 };
+template <typename T>
+hipError_t launch_fused(int pass, const Geom &g, const FusedArgs<T> *fa, const unsigned char *owner, unsigned nwg,
+                        hipStream_t st);
+
 // Start and stop events for the next kernel launch of this host thread (set
 // around a profiled single-kernel pass, null otherwise): the launchers then
 // use hipExtLaunchKernelGGL, which timestamps the kernel's own start and end

@@ -283,20 +283,34 @@ __device__ __forceinline__ void wg_reduce_store(double (&q)[NV], double *red, do
     }
 }
 
+// Block index and grid of a workgroup as a pass sees them: the hardware's
+// own for a pass launched alone, or the part of a fused launch (several
+// problems' passes in one grid) that belongs to one problem.
+struct VB {
+    unsigned x, y, z, gx, gy, gz;
+};
+
+__device__ __forceinline__ VB vb_native()
+{
+    return VB{blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y, gridDim.z};
+}
+
 // Tile (x, y) and item (z) of this workgroup, XCD-aware: the dispatcher
 // hands linear workgroup h to XCD h mod 8, so each XCD's workgroups are
 // mapped here to one contiguous run of the (x, y, z) order (a bijection of
 // the grid). Neighbouring tiles of a slice then run on the same XCD, and the
 // halo rows they share are found in that XCD's L2 (the update pass, whose
-// reads are one source slice per item with its halo).
-__device__ __forceinline__ uint3 xcd_block()
+// reads are one source slice per item with its halo).  (A fused launch
+// starts each problem's part at a multiple of 8, so h mod 8 is still the
+// XCD.)
+__device__ __forceinline__ uint3 xcd_block(const VB &v)
 {
     constexpr unsigned NXCD = 8;
-    const unsigned gx = gridDim.x, gxy = gridDim.x * gridDim.y, n = gxy * gridDim.z;
-    const unsigned h = blockIdx.x + gx * blockIdx.y + gxy * blockIdx.z;
+    const unsigned gx = v.gx, gxy = v.gx * v.gy, n = gxy * v.gz;
+    const unsigned h = v.x + gx * v.y + gxy * v.z;
     const unsigned per = n / NXCD, rem = n % NXCD, c = h % NXCD;
     const unsigned t = c * per + min(c, rem) + h / NXCD;
-    return make_uint3(t % gx, (t / gx) % gridDim.y, t / gxy);
+    return make_uint3(t % gx, (t / gx) % v.gy, t / gxy);
 }
 
 // Tile of this workgroup within its slice, XCD-aware: when a slice has a
@@ -306,17 +320,17 @@ __device__ __forceinline__ uint3 xcd_block()
 // share their halos in its L2, still slice after slice, so the same tile of
 // consecutive slices (which share source slices) stays on one XCD, n/8
 // workgroups apart.
-__device__ __forceinline__ uint2 xcd_slice_tile()
+__device__ __forceinline__ uint2 xcd_slice_tile(const VB &v)
 {
-    const unsigned gx = gridDim.x, n = gridDim.x * gridDim.y;
-    unsigned l = blockIdx.x + gx * blockIdx.y;
+    const unsigned gx = v.gx, n = v.gx * v.gy;
+    unsigned l = v.x + gx * v.y;
     if (n % 8 == 0) l = (l % 8) * (n / 8) + l / 8;
     return make_uint2(l % gx, l / gx);
 }
 
-__device__ __forceinline__ size_t slot_of()
+__device__ __forceinline__ size_t slot_of(const VB &v)
 {
-    return ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    return ((size_t)v.z * v.gy + v.y) * v.gx + v.x;
 }
 
 }  // namespace
@@ -335,10 +349,10 @@ __device__ __forceinline__ size_t slot_of()
 // the z-stencil of q to out.
 // ---------------------------------------------------------------------------
 template <typename T, int KZ>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
-k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
-       T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
-       int nshare)
+__device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevState<T> s, const T *__restrict__ q,
+                                          const T *__restrict__ x, T *__restrict__ out,
+                                          const Item *__restrict__ items, int mode, double *__restrict__ partials,
+                                          int nshare)
 {
     constexpr int RZ = KZ / 2;
     constexpr int XW = TX + 3, XH = TY + 3;  // x at (y0-1+jj, x0-1+ii)
@@ -354,9 +368,9 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
 
     // tiles in the XCD-aware order within the slice (neighbours share their
     // halos in L2; the same tile of consecutive slices stays on one XCD)
-    const uint2 tl = xcd_slice_tile();
-    const size_t slot = ((size_t)blockIdx.z * gridDim.y + tl.y) * gridDim.x + tl.x;
-    const Item it = items[blockIdx.z];
+    const uint2 tl = xcd_slice_tile(vb);
+    const size_t slot = ((size_t)vb.z * vb.gy + tl.y) * vb.gx + tl.x;
+    const Item it = items[vb.z];
     if (s.stop && *s.stop) return;  // read with the item, not before it
     const int k = it.k;
     const int x0 = tl.x * TX, y0 = tl.y * TY;
@@ -393,7 +407,7 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
         // the data term is given as nshare shares per item (the general-kernel
         // adjoint split over workgroups), q = [share][item][ny][nx]: added in order
         for (int p = 0; p < nshare; ++p) {
-            const __amdgpu_buffer_rsrc_t qp = buf_of(q + ((size_t)p * gridDim.z + blockIdx.z) * S, S);
+            const __amdgpu_buffer_rsrc_t qp = buf_of(q + ((size_t)p * vb.gz + vb.z) * S, S);
 #pragma unroll
             for (int qq = 0; qq < rg.E; ++qq) ht[qq] += ldbuf<T>(qp, bo[qq]);
         }
@@ -542,6 +556,15 @@ k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__re
     }
 }
 
+template <typename T, int KZ>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
+k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
+       T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
+       int nshare)
+{
+    grad_body<T, KZ>(vb_native(), g, prm, s, q, x, out, items, mode, partials, nshare);
+}
+
 // ---------------------------------------------------------------------------
 // Per block: fixed-order reduction of its gradient and direction slots, then
 // the 2x2 system of the memory-gradient subspace (Sec. 2.3, eq. "minimizer"):
@@ -679,7 +702,7 @@ template <typename T, int R, int TYK, int E>
 __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, const DevState<T> &s,
                                             const Item &it, int kk, size_t i, const T (&v1)[E],
                                             const T (&v2)[E], const uint32_t (&off)[E], const bool (&inb)[E],
-                                            T *A1, T *A2, T *B1, double *partials, uint2 tl)
+                                            T *A1, T *A2, T *B1, double *partials, uint2 tl, const VB &vb)
 {
     constexpr int NRK = TYK / (NT / TX);
     constexpr int K = 2 * R + 1, W = TX + 2 * R, H = TYK + 2 * R, N = W * H;
@@ -754,13 +777,13 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
         }
     }
     // without the VZ term the last three sums are zero
-    wg_reduce_store<NQD>(qs, red, partials + ((i * gridDim.y + tl.y) * gridDim.x + tl.x) * NQD,
+    wg_reduce_store<NQD>(qs, red, partials + ((i * vb.gy + tl.y) * vb.gx + tl.x) * NQD,
                          prm.kappa != 0.0 ? NQD : 3);
 }
 
 template <typename T, int KZ, int R, int TYK>
-__global__ void __launch_bounds__(NT)
-k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double *__restrict__ partials)
+__device__ __forceinline__ void dirs_body(const VB vb, Geom g, Params prm, DevState<T> s,
+                                          const Item *__restrict__ units, double *__restrict__ partials)
 {
     constexpr int RZ = KZ / 2;
     constexpr int W = TX + 2 * R, H = TYK + 2 * R;
@@ -780,8 +803,8 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
     // which keeps the same tile of consecutive slices (sharing KZ - 1
     // source slices) on one XCD close in time (the whole-grid order of the
     // update pass would spread them out and lose that reuse)
-    const uint2 tl = xcd_slice_tile();
-    const Item it = units[blockIdx.z];
+    const uint2 tl = xcd_slice_tile(vb);
+    const Item it = units[vb.z];
     if (s.stop && *s.stop) return;  // read with the unit, not before it
     const int k = it.k, z0 = it.z0, z1 = it.z0 + it.n;
     const bool two = it.hn > 1;
@@ -824,12 +847,19 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
             }
         }
     }
-    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)it.h0, a1, a2, rg.off, rg.inb, A1, A2, B1, partials, tl);
+    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)it.h0, a1, a2, rg.off, rg.inb, A1, A2, B1, partials, tl, vb);
     if (two) {
         __syncthreads();  // the reduction of slice k read A2
         dirs_finish<T, R, TYK>(g, prm, s, it, k + 1, (size_t)it.h0 + 1, b1, b2, rg.off, rg.inb, A1, A2, B1,
-                               partials, tl);
+                               partials, tl, vb);
     }
+}
+
+template <typename T, int KZ, int R, int TYK>
+__global__ void __launch_bounds__(NT)
+k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double *__restrict__ partials)
+{
+    dirs_body<T, KZ, R, TYK>(vb_native(), g, prm, s, units, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -848,9 +878,8 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
 // dp[1], so a workgroup never sees a half-updated step.
 // ---------------------------------------------------------------------------
 template <typename T, int R, int TYK, bool MULTI>
-__global__ void __launch_bounds__(NT)
-k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ pairs,
-         const double *__restrict__ u, int assign)
+__device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, const Item *__restrict__ items,
+                                            const int2 *__restrict__ pairs, const double *__restrict__ u, int assign)
 {
     constexpr int NRK = TYK / (NT / TX);
     constexpr int K = 2 * R + 1;
@@ -858,7 +887,7 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
     __shared__ __align__(16) T A[padded<WS2, H2>()];
     __shared__ __align__(16) T B[padded<TX, H2>()];
 
-    const uint3 bk = xcd_block();
+    const uint3 bk = xcd_block(vb);
     const Item it = items[bk.z];
     if (s.stop && *s.stop) return;  // read with the item, not before it
     const int m = it.k;
@@ -962,6 +991,14 @@ k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__re
         if (i >= g.nx || j >= g.ny) continue;
         stbuf(qo, (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T), qv[e] + v[e]);
     }
+}
+
+template <typename T, int R, int TYK, bool MULTI>
+__global__ void __launch_bounds__(NT)
+k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ pairs,
+         const double *__restrict__ u, int assign)
+{
+    update_body<T, R, TYK, MULTI>(vb_native(), g, s, items, pairs, u, assign);
 }
 
 // ---------------------------------------------------------------------------
@@ -1113,7 +1150,7 @@ k_H(Geom g, DevState<T> s, const T *__restrict__ in, const T *__restrict__ sub, 
             ss[0] += (double)v * (double)v;
         }
     }
-    if (partials) wg_reduce_store<1>(ss, red, partials + slot_of());
+    if (partials) wg_reduce_store<1>(ss, red, partials + slot_of(vb_native()));
 }
 
 // ---------------------------------------------------------------------------
@@ -1352,7 +1389,7 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
                 qs[5] += z2v * z2v;
             }
         }
-        wg_reduce_store<NQD>(qs, red, partials + slot_of() * NQD);
+        wg_reduce_store<NQD>(qs, red, partials + slot_of(vb_native()) * NQD);
         return;
     }
     const size_t base = nsplit > 1 ? ((size_t)part * (gridDim.z / nsplit) + ii) * S : (size_t)k * S;
@@ -1367,7 +1404,7 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
     }
     if (partials) {
         double q1[1] = {qs[0]};
-        wg_reduce_store<1>(q1, red, partials + slot_of());
+        wg_reduce_store<1>(q1, red, partials + slot_of(vb_native()));
     }
 }
 
@@ -1529,7 +1566,7 @@ k_majapply(Geom g, Params prm, DevState<T> s, const T *__restrict__ qt, const T 
         acc += (double)pval * (double)a;
     }
     double q1[1] = {acc};
-    wg_reduce_store<1>(q1, red, partials + slot_of());
+    wg_reduce_store<1>(q1, red, partials + slot_of(vb_native()));
 }
 
 // Elementwise stages of the inner solve on the gradient items of a launch
@@ -1618,7 +1655,7 @@ k_cg(int stage, Geom g, DevState<T> s, const Item *__restrict__ items, CgBufs<T>
             }
         __shared__ double red[NT / 64];
         double q1[1] = {rr};
-        wg_reduce_store<1>(q1, red, b.prr + slot_of());
+        wg_reduce_store<1>(q1, red, b.prr + slot_of(vb_native()));
         return;
     }
     // CG_DIR: stop at the tolerance, else p = r + beta p, beta = <r, r>_new / <r, r>
@@ -1638,6 +1675,74 @@ k_cg(int stage, Geom g, DevState<T> s, const Item *__restrict__ items, CgBufs<T>
             cs[6] = rr;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Fused batch passes: one launch runs a pass of the same colour index for
+// every problem of a batch, each problem's workgroups a contiguous part of
+// the grid (work lists concatenated; each problem gets as many workgroups as
+// its own launch would have).  The bodies are the single-problem passes', so
+// a fused run is bitwise a run of the problems one by one.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ bool fused_part(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner,
+                                           int *p, VB *vb)
+{
+    // uniform over the workgroup: the argument block is read with scalar loads
+    *p = __builtin_amdgcn_readfirstlane((int)owner[blockIdx.x >> 3]);
+    const FusedArgs<T> &a = fa[*p];
+    const unsigned l = blockIdx.x - a.wg0, per = a.gx * a.gy;
+    if (l >= per * (unsigned)a.nitems) return false;  // padding to the next multiple of 8
+    // the divisions run on the vector unit: their (uniform) results are moved
+    // back to scalar registers, as the hardware block index would be
+    const unsigned bx = l % a.gx, by = (l / a.gx) % a.gy, bz = l / per;
+    *vb = VB{(unsigned)__builtin_amdgcn_readfirstlane((int)bx), (unsigned)__builtin_amdgcn_readfirstlane((int)by),
+             (unsigned)__builtin_amdgcn_readfirstlane((int)bz), a.gx, a.gy, (unsigned)a.nitems};
+    return true;
+}
+
+template <typename T, int KZ>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
+k_grad_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner)
+{
+    int p;
+    VB vb;
+    if (!fused_part(fa, owner, &p, &vb)) return;
+    const FusedArgs<T> &a = fa[p];
+    grad_body<T, KZ>(vb, a.g, a.prm, a.s, a.s.q, a.s.x, nullptr, a.items, GM_BLOCK, a.pg, 0);
+}
+
+template <typename T, int KZ, int R, int TYK>
+__global__ void __launch_bounds__(NT)
+k_dirs_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner)
+{
+    int p;
+    VB vb;
+    if (!fused_part(fa, owner, &p, &vb)) return;
+    const FusedArgs<T> &a = fa[p];
+    dirs_body<T, KZ, R, TYK>(vb, a.g, a.prm, a.s, a.items, a.pd);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT)
+k_solve_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner)
+{
+    int p;
+    VB vb;
+    if (!fused_part(fa, owner, &p, &vb)) return;
+    const FusedArgs<T> &a = fa[p];
+    solve_block(a.prm, a.brs[vb.z], a.ntg, a.ntd, a.pg, a.pd, a.u, a.info, a.s.stop);  // a 1 x 1 x blocks grid
+}
+
+template <typename T, int R, int TYK>
+__global__ void __launch_bounds__(NT)
+k_update_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner)
+{
+    int p;
+    VB vb;
+    if (!fused_part(fa, owner, &p, &vb)) return;
+    const FusedArgs<T> &a = fa[p];
+    update_body<T, R, TYK, false>(vb, a.g, a.s, a.items, a.pairs, a.u, 0);
 }
 
 // Streaming copy of n 16-byte words, grid-stride over chunks of U NT words:
@@ -1756,6 +1861,33 @@ hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items,
         BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
                        BD3MG_LAUNCH((k_update<T, R, TYK, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
                                           st, g, s, items, pairs, u, assign)));
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fused(int pass, const Geom &g, const FusedArgs<T> *fa, const unsigned char *owner, unsigned nwg,
+                        hipStream_t st)
+{
+    if (nwg == 0) return hipSuccess;
+    const dim3 grid(nwg);
+    switch (pass) {
+    case FP_GRAD:
+        BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_LAUNCH((k_grad_fused<T, KZ>), grid, dim3(NT), 0, st, fa, owner));
+        break;
+    case FP_DIRS:
+        BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
+                        BD3MG_LAUNCH((k_dirs_fused<T, KZ, R, TYK>), grid, dim3(NT), 0, st, fa, owner))));
+        break;
+    case FP_SOLVE:
+        BD3MG_LAUNCH((k_solve_fused<T>), grid, dim3(NT), 0, st, fa, owner);
+        break;
+    case FP_UPDATE:
+        BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
+                       BD3MG_LAUNCH((k_update_fused<T, R, TYK>), grid, dim3(NT), 0, st, fa, owner)));
+        break;
+    default:
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
@@ -1967,6 +2099,8 @@ hipError_t scratch_base(int device, void **ptr)
                                            double *, hipStream_t);                                \
     template hipError_t launch_cg<T>(int, const Geom &, const DevState<T> &, const Item *, int,    \
                                      const CgBufs<T> &, int, double, hipStream_t);                \
+    template hipError_t launch_fused<T>(int, const Geom &, const FusedArgs<T> *,                   \
+                                        const unsigned char *, unsigned, hipStream_t);            \
     template hipError_t launch_refresh<T>(const Geom &, const DevState<T> &, const T *, T *,       \
                                           const Item *, int, hipStream_t);                        \
     template hipError_t launch_H<T>(const Geom &, const DevState<T> &, const T *, const T *, T *,  \

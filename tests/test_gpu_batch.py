@@ -55,6 +55,59 @@ def test_batch_equals_single_runs_bitwise(orc, sweeps):
     assert all(g.get_state()[3] == sweeps + 2 for g in probs)
 
 
+def fusable_members():
+    """Problems of different shapes and partitions with one kernel shape
+    (PSF 5x5x5), so that one fused launch per pass serves them all."""
+    return [inputs.tiny((9, 40, 70), 41, kxy=5, kz=5, nblocks=3),
+            inputs.tiny((6, 70, 33), 42, kxy=5, kz=5, nblocks=2),
+            inputs.tiny((12, 17, 130), 43, kxy=5, kz=5, nblocks=4),
+            inputs.tiny((5, 64, 64), 44, kxy=5, kz=5, nblocks=5),
+            inputs.tiny((16, 23, 91), 45, kxy=5, kz=5, nblocks=7)]
+
+
+@pytest.mark.parametrize("prec", [binding.FP32, binding.FP64])
+@pytest.mark.parametrize("sweeps", [6, 7])
+def test_fused_batch_equals_single_runs_bitwise(orc, prec, sweeps):
+    ws = fusable_members()
+    single = []
+    for w in ws:
+        g, o, y = setup(orc, w, prec)
+        g.run(sweeps, check_every=0)
+        single.append((g.get_x(), g.get_dprev()))
+    probs = [setup(orc, w, prec)[0] for w in ws]
+    b = binding.Batch(probs)
+    assert b.set_mode(binding.BATCH_FUSED)
+    res = b.run(sweeps)
+    for g, (xs, ds), r in zip(probs, single, res):
+        assert r["sweeps"] == sweeps
+        assert np.array_equal(g.get_x(), xs) and np.array_equal(g.get_dprev(), ds)
+    # and the branch mode gives the same again
+    probs2 = [setup(orc, w, prec)[0] for w in ws]
+    b2 = binding.Batch(probs2)
+    assert not b2.set_mode(binding.BATCH_BRANCHES)
+    b2.run(sweeps)
+    for g, g2 in zip(probs, probs2):
+        assert np.array_equal(g.get_x(), g2.get_x())
+
+
+def test_fused_batch_with_a_tolerance_and_fallback(orc):
+    ws = fusable_members()[:3]
+    made = [setup(orc, w, binding.FP64) for w in ws]
+    b = binding.Batch([m[0] for m in made])
+    assert b.set_mode(binding.BATCH_FUSED)
+    res = b.run(400, grad_rtol=1e-3, check_every=4)
+    for (g, o, y), w, r in zip(made, ws, res):
+        assert r["converged"] == 1 and r["sweeps"] % 4 == 0
+        g2 = setup(orc, w, binding.FP64)[0]
+        g2.run(r["sweeps"], check_every=0)
+        assert np.array_equal(g2.get_x(), g.get_x())
+    # problems of different kernel shapes cannot share a launch: branch mode
+    mixed = binding.Batch([setup(orc, w, binding.FP32)[0] for w in small_members()])
+    assert not mixed.set_mode(binding.BATCH_FUSED)
+    # a few small volumes: the automatic mode fuses
+    assert b.set_mode(binding.BATCH_AUTO)
+
+
 def test_batch_fp64_matches_oracle(orc):
     ws = small_members()[:3]
     made = [setup(orc, w, binding.FP64) for w in ws]
@@ -91,12 +144,15 @@ def test_batched_uneven_volumes_full_size(orc):
     made = [setup(orc, w, binding.FP32) for w in ws]
     probs = [m[0] for m in made]
     b = binding.Batch(probs)
+    assert b.set_mode(binding.BATCH_FUSED)  # this batch can share launches
     b.tune()
     res = b.run(50)
     assert all(r["sweeps"] == 50 for r in res)
     nvox = sum(int(np.prod(w.shape)) for w in ws)
-    print("batch: %d volumes, %d voxels, 50 sweeps in %.4f s: %.3e voxel-iterations/s"
+    print("fused batch: %d volumes, %d voxels, 50 sweeps in %.4f s: %.3e voxel-iterations/s"
           % (len(ws), nvox, res[0]["seconds"], nvox * 50 / res[0]["seconds"]))
+    # 146 MB of volumes: the automatic mode takes graph branches
+    assert not b.set_mode(binding.BATCH_AUTO)
     # single runs (tile heights as tuned) give the same iterates
     for i in (0, 7, 15):
         g = probs[i]
