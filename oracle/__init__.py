@@ -35,6 +35,7 @@ class _Problem(C.Structure):
         ("lip", C.c_double),
         ("n_inner", C.c_int),
         ("tol_inner", C.c_double),
+        ("tv3d", C.c_int),
     ]
 
 # Block steps of the ablation study (Sec. 3.2): BD3MG and its variants.
@@ -152,8 +153,9 @@ class Problem:
         return o
 
     def __init__(self, y, gx, gy, gz, lam=0.0, delta=1.0, eta=0.0, kappa=0.0,
-                 xmin=0.0, xmax=1.0, dense=False, mu=0.0):
-        """method etc.: see set_method (BD3MG unless changed)."""
+                 xmin=0.0, xmax=1.0, dense=False, mu=0.0, tv3d=False):
+        """method etc.: see set_method (BD3MG unless changed).  tv3d: V^Z inside
+        the root of the TV term with V^X and V^Y."""
         self.y = _f64(y)
         assert self.y.ndim == 3
         self.nz, self.ny, self.nx = self.y.shape
@@ -169,7 +171,8 @@ class Problem:
                            self.gx.ctypes.data, self.gy.ctypes.data, self.gz.ctypes.data,
                            self.y.ctypes.data, self.lam, self.delta, self.eta, self.kappa,
                            self.xmin, self.xmax, int(self.dense), self.mu, None,
-                           BD3MG, 0.0, 0, 0.0)
+                           BD3MG, 0.0, 0, 0.0, int(bool(tv3d)))
+        self.tv3d = bool(tv3d)
         self.pk = None
 
     def set_method(self, method, lip=None, n_inner=10, tol_inner=0.0):

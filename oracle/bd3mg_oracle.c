@@ -65,6 +65,10 @@ typedef struct {
     double lip;                  /* L of the metric L Id (methods 1 and 2) */
     int n_inner;                 /* Async-MM: BiCG iterations at most */
     double tol_inner;            /* Async-MM: stop when ||r_k|| <= tol_inner ||r_0|| (0: never) */
+    /* 1: three-dimensional total variation, V^Z inside the root with V^X and
+     * V^Y (the generic ||(D x)_n|| form of the TV term); 0: V^X, V^Y only, as
+     * in the criterion of Sec. 3.1 */
+    int tv3d;
 } orc_problem;
 
 #define VOX(p, k, j, i) (((size_t)(k) * (size_t)(p)->ny + (size_t)(j)) * (size_t)(p)->nx + (size_t)(i))
@@ -386,7 +390,8 @@ void orc_V(const orc_problem *p, int op, int adjoint, const double *in, double *
 static double omega_at(const orc_problem *p, const double *x, int k, int j, int i)
 {
     double gxv = dX(p, x, k, j, i), gyv = dY(p, x, k, j, i);
-    return 1.0 / sqrt(gxv * gxv + gyv * gyv + p->delta * p->delta);
+    double gzv = p->tv3d ? dZ(p, x, k, j, i) : 0.0;
+    return 1.0 / sqrt(gxv * gxv + gyv * gyv + gzv * gzv + p->delta * p->delta);
 }
 
 static double clipd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -413,8 +418,9 @@ double orc_f_terms(const orc_problem *p, const double *x, double *terms)
                 double e = x[v] - clipd(x[v], p->xmin, p->xmax);
                 s1 += e * e;
                 double gxv = dX(p, x, k, j, i), gyv = dY(p, x, k, j, i);
-                s2 += sqrt(gxv * gxv + gyv * gyv + p->delta * p->delta);
                 double gzv = dZ(p, x, k, j, i);
+                double g3 = p->tv3d ? gzv : 0.0;
+                s2 += sqrt(gxv * gxv + gyv * gyv + g3 * g3 + p->delta * p->delta);
                 s3 += gzv * gzv;
             }
         part[4 * k + 0] = s0; part[4 * k + 1] = s1; part[4 * k + 2] = s2; part[4 * k + 3] = s3;
@@ -463,6 +469,10 @@ void orc_grad_slices(const orc_problem *p, const double *x, double *g, int k0, i
                 if (i < p->nx - 1) tv -= omega_at(p, x, k, j, i) * dX(p, x, k, j, i);
                 if (j >= 1) tv += omega_at(p, x, k, j - 1, i) * dY(p, x, k, j - 1, i);
                 if (j < p->ny - 1) tv -= omega_at(p, x, k, j, i) * dY(p, x, k, j, i);
+                if (p->tv3d) {  /* V^Z^T (w V^Z x) */
+                    if (k >= 1) tv += omega_at(p, x, k - 1, j, i) * dZ(p, x, k - 1, j, i);
+                    if (k < p->nz - 1) tv -= omega_at(p, x, k, j, i) * dZ(p, x, k, j, i);
+                }
                 acc += p->lambda * tv;
                 if (p->kappa != 0.0) {
                     double zz = 0.0;
@@ -523,20 +533,24 @@ double orc_majorant_form(const orc_problem *p, const double *x, const double *u,
     scratch_clear(hu, h0, h1, nslice(p));
     scratch_clear(hv, h0, h1, nslice(p));
     double box = dot_slices(p, u, v, z0, z1);
-    int nzs = z1 - z0;
+    /* with 3D TV the difference along z of u, v reaches slice z0 - 1 */
+    int t0 = (p->tv3d && z0 >= 1) ? z0 - 1 : z0;
+    int nzs = z1 - t0;
     double *part = (double *)calloc((size_t)(nzs > 0 ? nzs : 1), sizeof(double));
 #pragma omp parallel for schedule(static)
-    for (int k = z0; k < z1; ++k) {
+    for (int k = t0; k < z1; ++k) {
         double s = 0.0;
         for (int j = 0; j < p->ny; ++j)
             for (int i = 0; i < p->nx; ++i) {
                 double w = omega_at(p, x, k, j, i);
-                s += w * (dX(p, u, k, j, i) * dX(p, v, k, j, i) + dY(p, u, k, j, i) * dY(p, v, k, j, i));
+                double d = dX(p, u, k, j, i) * dX(p, v, k, j, i) + dY(p, u, k, j, i) * dY(p, v, k, j, i);
+                if (p->tv3d) d += dZ(p, u, k, j, i) * dZ(p, v, k, j, i);
+                s += w * d;
             }
-        part[k - z0] = s;
+        part[k - t0] = s;
     }
     double tv = 0.0;
-    for (int k = z0; k < z1; ++k) tv += part[k - z0];
+    for (int k = t0; k < z1; ++k) tv += part[k - t0];
     free(part);
     double zz = 0.0;
     if (p->kappa != 0.0) {
@@ -579,6 +593,10 @@ void orc_majorant_apply(const orc_problem *p, const double *x, const double *u, 
                 if (i < p->nx - 1) tv -= omega_at(p, x, k, j, i) * dX(p, u, k, j, i);
                 if (j >= 1) tv += omega_at(p, x, k, j - 1, i) * dY(p, u, k, j - 1, i);
                 if (j < p->ny - 1) tv -= omega_at(p, x, k, j, i) * dY(p, u, k, j, i);
+                if (p->tv3d) {
+                    if (k >= 1) tv += omega_at(p, x, k - 1, j, i) * dZ(p, u, k - 1, j, i);
+                    if (k < p->nz - 1) tv -= omega_at(p, x, k, j, i) * dZ(p, u, k, j, i);
+                }
                 acc += p->lambda * tv;
                 if (p->kappa != 0.0) {
                     double zz = 0.0;

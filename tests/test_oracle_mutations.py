@@ -58,6 +58,11 @@ MUTATIONS = {
     "async-cg-metric-offdiagonal-sign": ("B[1] = -lm * gd;", "B[1] = lm * gd;"),
     "dense-lipschitz-column-sums": ("if (k + t >= 0 && k + t < p->nz) c += fabs(p->pk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);",
                                     "if (k + t >= 0 && k + t < p->nz) c += 0.5 * fabs(p->pk[((size_t)(k + t) * p->kz + t + rz) * kk + q]);"),
+    "tv3d-omega-drops-z": ("double gzv = p->tv3d ? dZ(p, x, k, j, i) : 0.0;", "double gzv = 0.0;"),
+    "tv3d-f-drops-z": ("double g3 = p->tv3d ? gzv : 0.0;", "double g3 = 0.0;"),
+    "tv3d-adjoint-z-sign": ("if (k >= 1) tv += omega_at(p, x, k - 1, j, i) * dZ(p, x, k - 1, j, i);",
+                            "if (k >= 1) tv -= omega_at(p, x, k - 1, j, i) * dZ(p, x, k - 1, j, i);"),
+    "tv3d-form-misses-the-slice-below": ("int t0 = (p->tv3d && z0 >= 1) ? z0 - 1 : z0;", "int t0 = z0;"),
 }
 
 NET_MUTATIONS = {
@@ -78,7 +83,7 @@ NET_MUTATIONS = {
 }
 
 PIN_FILES = {SRC: ["test_oracle_pins.py", "test_oracle_round.py", "test_oracle_dense.py",
-                   "test_oracle_ablation.py"],
+                   "test_oracle_ablation.py", "test_oracle_tv3d.py"],
              NET_SRC: ["test_oracle_convnet.py"]}
 
 
