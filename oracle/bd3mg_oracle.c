@@ -898,6 +898,9 @@ int orc_run_round(const orc_problem *p, double *x, double *dprev, int nblocks, c
 double orc_lipschitz_bound(const orc_problem *p)
 {
     int rz = p->kz / 2;
+    /* ||[V^X; V^Y]||^2 <= 8, and 12 with V^Z inside the root as well (each
+     * forward difference has norm <= 2); omega <= 1 / delta */
+    double tvc = p->tv3d ? 12.0 : 8.0;
     double rmax = 0.0, cmax = 0.0;
     if (p->pk) {
         /* general kernels: row sums of |H| are bounded by sum |P_k| of the
@@ -914,7 +917,7 @@ double orc_lipschitz_bound(const orc_problem *p)
             if (r > rmax) rmax = r;
             if (c > cmax) cmax = c;
         }
-        return rmax * cmax + 2.0 * p->eta + 8.0 * p->lambda / p->delta + 8.0 * p->kappa;
+        return rmax * cmax + 2.0 * p->eta + tvc * p->lambda / p->delta + 8.0 * p->kappa;
     }
     for (int k = 0; k < p->nz; ++k) {
         double r = 0.0, c = 0.0;
@@ -934,7 +937,7 @@ double orc_lipschitz_bound(const orc_problem *p)
         if (ay > sy) sy = ay;
     }
     double hh = rmax * cmax * sx * sx * sy * sy;
-    return hh + 2.0 * p->eta + 8.0 * p->lambda / p->delta + 8.0 * p->kappa;
+    return hh + 2.0 * p->eta + tvc * p->lambda / p->delta + 8.0 * p->kappa;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -63,6 +63,7 @@ MUTATIONS = {
     "tv3d-adjoint-z-sign": ("if (k >= 1) tv += omega_at(p, x, k - 1, j, i) * dZ(p, x, k - 1, j, i);",
                             "if (k >= 1) tv -= omega_at(p, x, k - 1, j, i) * dZ(p, x, k - 1, j, i);"),
     "tv3d-form-misses-the-slice-below": ("int t0 = (p->tv3d && z0 >= 1) ? z0 - 1 : z0;", "int t0 = z0;"),
+    "tv3d-lipschitz-keeps-8": ("double tvc = p->tv3d ? 12.0 : 8.0;", "double tvc = 8.0;"),
 }
 
 NET_MUTATIONS = {

@@ -129,3 +129,29 @@ def test_sweeps_decrease_f_and_agree_on_the_minimiser(orc):
         p.run(x, d, nsl, order, 1500, history=False)
         xs.append(x)
     assert np.linalg.norm(xs[0] - xs[1]) <= 1e-7 * np.linalg.norm(xs[0])
+
+
+def test_lipschitz_bound_covers_the_z_difference(orc):
+    """With no blur, box or z penalty the curvature of f at a flat volume is
+    lambda / delta V^T V; on the 3D checkerboard v = (-1)^(i+j+k) its Rayleigh
+    quotient is 4 times the share of forward differences per voxel along each
+    axis (10.33 on 6x8x8), above the 8 of the in-slice operators alone, so
+    the bound must take 12 lambda / delta (each forward difference has norm at
+    most 2)."""
+    shape = (6, 8, 8)
+    nz, ny, nx = shape
+    lam, delta = 0.3, 0.05
+    zero = np.zeros((nz, 3))
+    p = orc.Problem(np.zeros(shape), zero, zero, np.zeros((nz, 3)), lam=lam, delta=delta, tv3d=True)
+    k, j, i = np.indices(shape)
+    v = (-1.0) ** (i + j + k)
+    x = np.full(shape, 0.5)
+    t = 1e-6 * delta
+    q = float((v * (p.grad(x + t * v) - p.grad(x))).sum() / (t * (v * v).sum()))
+    share = ((nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)) / (nx * ny * nz)
+    assert abs(q - 4 * share * lam / delta) <= 1e-6 * q
+    L = p.lipschitz_bound()
+    assert abs(L - 12 * lam / delta) <= 1e-12 * L
+    assert 8 * lam / delta < q <= L
+    p2 = orc.Problem(np.zeros(shape), zero, zero, np.zeros((nz, 3)), lam=lam, delta=delta)
+    assert abs(p2.lipschitz_bound() - 8 * lam / delta) <= 1e-12 * L
