@@ -61,10 +61,11 @@ typedef enum {
 } bd3mg_precision;
 
 typedef enum {
-    /* Blocks at least max(2*r_z, kappa > 0) slices apart share a colour and are
-     * updated together; colours run in order.  Same-colour blocks read and
-     * write disjoint data, so this equals the sequential (delay-free) rule of
-     * Sec. 3.1 applied in colour-major order (Sec. 2.4, delta_k = 0). */
+    /* Blocks at least max(2*r_z, kappa > 0 or bd3mg_set_tv3d) slices apart
+     * share a colour and are updated together; colours run in order.
+     * Same-colour blocks read and write disjoint data, so this equals the
+     * sequential (delay-free) rule of Sec. 3.1 applied in colour-major order
+     * (Sec. 2.4, delta_k = 0). */
     BD3MG_SCHED_COLORED = 0,
     /* One block at a time in z order (the natural sequential rule). */
     BD3MG_SCHED_SEQUENTIAL = 1,
@@ -155,6 +156,20 @@ bd3mg_status bd3mg_set_psf_dense(bd3mg_problem p, int kx, int ky, int kz, const 
 bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, double eta,
                               double kappa, double xmin, double xmax);
 
+/* Total variation over the volume instead of per slice, an option beside the
+ * criterion of Sec. 3.1 (eq. "eq_crit"), whose total variation takes only the
+ * in-slice differences V^X, V^Y inside the root and leaves z to the separate
+ * kappa ||V^Z x||^2.  on = 1 puts V^Z inside the root as well:
+ *   lambda sum sqrt((V^X x)^2 + (V^Y x)^2 + (V^Z x)^2 + delta^2),
+ * with the same forward differences (zero at the last slice), its gradient
+ * term lambda V^Z^T(omega V^Z x) and the matching half-quadratic majorant
+ * term lambda V^Z^T Diag(omega) V^Z; kappa still adds its own term.  on = 0
+ * (the default) is the paper's criterion.  A block's gradient then reads x
+ * on the slices next to the block, and same-colour blocks keep at least one
+ * slice apart.  Async-MM and the fused launches of a batch do not take it.
+ * ERR_ARG: on not 0 or 1.  ERR_STATE: the method is Async-MM. */
+bd3mg_status bd3mg_set_tv3d(bd3mg_problem p, int on);
+
 /* Curvature inflation (Sec. 2.5, Assumption C): every block step uses the
  * majorant A_S(x) + mu Id instead of A_S(x), for every schedule.  mu = 0
  * (the default) is the paper's majorant.  ERR_ARG: mu < 0 or not finite. */
@@ -174,8 +189,9 @@ bd3mg_status bd3mg_set_inflation(bd3mg_problem p, double mu);
  *   0 (for the symmetric A_S these are the linear biconjugate gradient
  *   iterates with the shadow residual started at the residual), stopping
  *   early once ||r|| <= tol_inner ||r_0|| (tol_inner = 0: n_inner
- *   iterations) or when a step is undefined; needs the separable PSF and the
- *   coloured or sequential schedule (ERR_STATE at run otherwise).
+ *   iterations) or when a step is undefined; needs the separable PSF, the
+ *   total variation of the slices (not bd3mg_set_tv3d) and the coloured or
+ *   sequential schedule (ERR_STATE at run otherwise).
  * lip: L of the metric L Id (GD, CG); lip <= 0 takes bd3mg_lipschitz_bound
  * at each run.  The inflation mu (bd3mg_set_inflation) adds to every metric.
  * bd3mg_block_step's info for Async-MM is {iterations, ||r_end||^2, 0,
@@ -193,7 +209,8 @@ bd3mg_status bd3mg_set_method(bd3mg_problem p, int method, double lip, int n_inn
 /* An upper bound L of the Lipschitz constant of grad f (Assumption A) from
  * the PSF tables and parameters: ||H||_1 ||H||_inf + 2 eta + 8 lambda / delta
  * + 8 kappa (the in-slice difference operators have ||D||^2 <= 8 and
- * omega <= 1 / delta).  With tau = nblocks - 1, mu = L (2 sqrt(tau) + 1)
+ * omega <= 1 / delta; 12 lambda / delta with the total variation along z,
+ * bd3mg_set_tv3d).  With tau = nblocks - 1, mu = L (2 sqrt(tau) + 1)
  * satisfies Assumption C for BD3MG_SCHED_ROUND whatever the point (a
  * sufficient, conservative reading).  ERR_STATE: PSF not set. */
 bd3mg_status bd3mg_lipschitz_bound(bd3mg_problem p, double *L);

@@ -47,6 +47,7 @@ SIGNATURES = {
     "bd3mg_run": ([_dp, _i, _d, _i, _dp], C.c_int),
     "bd3mg_run_noalloc": ([_dp, _i, _d, _i, _dp], C.c_int),
     "bd3mg_set_method": ([_dp, _i, _d, _i, _d], C.c_int),
+    "bd3mg_set_tv3d": ([_dp, _i], C.c_int),
     "bd3mg_batch_set_mode": ([_dp, _i, _dp], C.c_int),
     "bd3mg_get_x": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_dprev": ([_dp, _dp, _i], C.c_int),
@@ -219,6 +220,11 @@ class Problem:
         METHOD_ASYNC_CG (metric L Id; lip <= 0: the Lipschitz bound) or
         METHOD_ASYNC_MM (n_inner conjugate-gradient iterations at most)."""
         _check(load().bd3mg_set_method(self._h, int(method), float(lip), int(n_inner), float(tol_inner)))
+
+    def set_tv3d(self, on=True):
+        """Total variation over (V^X, V^Y, V^Z) inside the root instead of the
+        slices' (V^X, V^Y); kappa ||V^Z x||^2 stays a term of its own."""
+        _check(load().bd3mg_set_tv3d(self._h, int(on)))
 
     def set_inflation(self, mu):
         _check(load().bd3mg_set_inflation(self._h, float(mu)))

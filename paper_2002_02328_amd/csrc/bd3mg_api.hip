@@ -48,7 +48,7 @@ struct bd3mg_problem_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     Geom geom{};
     int ntiles = 0;
-    Params prm{0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, M_BD3MG, 0.0};
+    Params prm{0.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0, M_BD3MG, 0.0, 0};
     int n_inner = 0;         // Async-MM: inner iterations at most
     double tol_inner = 0.0;  // Async-MM: relative residual of the inner solve (0: n_inner iterations)
     double lip_given = 0.0;  // L of the metric L Id as given (<= 0: the Lipschitz bound)
@@ -304,10 +304,15 @@ bd3mg_status zero_steps(bd3mg_problem p)
     return BD3MG_OK;
 }
 
+// Whether the criterion couples neighbouring slices outside H: the z
+// penalty, or the total variation taken along z.
+static bool z_coupled(bd3mg_problem p) { return p->prm.kappa > 0.0 || p->prm.tv3d; }
+
 // Greedy colouring in z order: block b takes the smallest colour none of whose
 // earlier members is closer than min_gap slices.  Same-colour blocks then read
 // and write disjoint data (the residual on S +- r_z, the iterate on S +- 1 when
-// kappa > 0), so updating them together equals updating them in sequence.
+// kappa > 0 or the TV is taken along z), so updating them together equals
+// updating them in sequence.
 void color_blocks(bd3mg_problem p)
 {
     const int nb = (int)p->nsl.size();
@@ -320,7 +325,7 @@ void color_blocks(bd3mg_problem p)
         p->ncolors = 1;  // every block in one round, all from the same snapshot
     } else {
         const int rz = p->kz / 2;
-        const int min_gap = std::max(2 * rz, p->prm.kappa > 0.0 ? 1 : 0);
+        const int min_gap = std::max(2 * rz, z_coupled(p) ? 1 : 0);
         int nc = 0;
         for (int b = 0; b < nb; ++b) {
             int c = 0;
@@ -342,7 +347,8 @@ void color_blocks(bd3mg_problem p)
 
 // Work items of a launch group (a set of blocks updated together):
 //   gradient pass: the blocks' own slices S;
-//   direction pass: S +- r_z (and slice z0 - 1 when kappa > 0, for VZ);
+//   direction pass: S +- r_z (and slice z0 - 1 when kappa > 0 or the TV is
+//   taken along z, for VZ);
 //   update pass: S +- r_z (a round: every slice of the volume once),
 // all clipped to the volume, block by block in z order.  Each update item
 // lists its sources: the (direction slot, block) pairs whose stored H d1,
@@ -353,7 +359,7 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
                  bool round = false)
 {
     const int rz = p->kz / 2;
-    const int rd = std::max(rz, p->prm.kappa > 0.0 ? 1 : 0);
+    const int rd = std::max(rz, z_coupled(p) ? 1 : 0);
     grp.g_off = (int)gi.size();
     grp.d_off = (int)di.size();
     grp.u_off = (int)ui.size();
@@ -1276,7 +1282,7 @@ bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, doub
         return fail(BD3MG_ERR_ARG, "lambda, eta and kappa must be >= 0");
     if (xmin > xmax) return fail(BD3MG_ERR_ARG, "xmin > xmax");
     const bool kappa_changed = (kappa > 0.0) != (p->prm.kappa > 0.0);
-    p->prm = Params{lambda, delta, eta, kappa, xmin, xmax, p->prm.mu, p->prm.method, p->prm.lip};
+    p->prm = Params{lambda, delta, eta, kappa, xmin, xmax, p->prm.mu, p->prm.method, p->prm.lip, p->prm.tv3d};
     p->gnorm_ref_valid = false;
     if (kappa_changed) p->sched_dirty = true;
     return BD3MG_OK;
@@ -1287,6 +1293,20 @@ bd3mg_status bd3mg_set_inflation(bd3mg_problem p, double mu)
     ST_TRY(validate_handle(p));
     if (!(mu >= 0.0) || !std::isfinite(mu)) return fail(BD3MG_ERR_ARG, "mu must be finite and >= 0");
     p->prm.mu = mu;
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_set_tv3d(bd3mg_problem p, int on)
+{
+    ST_TRY(validate_handle(p));
+    if (on != 0 && on != 1) return fail(BD3MG_ERR_ARG, "on must be 0 or 1, got %d", on);
+    if (on && p->prm.method == M_MM)
+        return fail(BD3MG_ERR_STATE, "Async-MM runs with the total variation of the slices");
+    if (on != p->prm.tv3d) {
+        p->prm.tv3d = on;
+        p->gnorm_ref_valid = false;
+        p->sched_dirty = true;  // the colouring gap and the direction items depend on it
+    }
     return BD3MG_OK;
 }
 
@@ -1301,6 +1321,8 @@ bd3mg_status bd3mg_set_method(bd3mg_problem p, int method, double lip, int n_inn
     if (!(tol_inner >= 0.0) || !std::isfinite(tol_inner)) return fail(BD3MG_ERR_ARG, "tol_inner must be >= 0");
     if (method == BD3MG_METHOD_ASYNC_MM && p->dense)
         return fail(BD3MG_ERR_STATE, "Async-MM runs with the separable PSF");
+    if (method == BD3MG_METHOD_ASYNC_MM && p->prm.tv3d)
+        return fail(BD3MG_ERR_STATE, "Async-MM runs with the total variation of the slices");
     const bool to_mm = method == BD3MG_METHOD_ASYNC_MM && p->prm.method != M_MM;
     p->prm.method = method;
     p->lip_given = lip;
@@ -1416,7 +1438,7 @@ bd3mg_status bd3mg_lipschitz_bound(bd3mg_problem p, double *L)
             cmax = std::max(cmax, c);
         }
         const Params &q = p->prm;
-        *L = rmax * cmax + 2.0 * q.eta + 8.0 * q.lambda / q.delta + 8.0 * q.kappa;
+        *L = rmax * cmax + 2.0 * q.eta + (q.tv3d ? 12.0 : 8.0) * q.lambda / q.delta + 8.0 * q.kappa;
         return BD3MG_OK;
     }
     double rmax = 0.0, cmax = 0.0, sx = 0.0, sy = 0.0;
@@ -1434,7 +1456,8 @@ bd3mg_status bd3mg_lipschitz_bound(bd3mg_problem p, double *L)
         sy = std::max(sy, ay);
     }
     const Params &q = p->prm;
-    *L = rmax * cmax * sx * sx * sy * sy + 2.0 * q.eta + 8.0 * q.lambda / q.delta + 8.0 * q.kappa;
+    *L = rmax * cmax * sx * sx * sy * sy + 2.0 * q.eta + (q.tv3d ? 12.0 : 8.0) * q.lambda / q.delta +
+         8.0 * q.kappa;
     return BD3MG_OK;
 }
 
@@ -1858,7 +1881,8 @@ bool batch_fusable(bd3mg_batch b)
 {
     const bd3mg_problem p0 = b->probs[0];
     for (bd3mg_problem p : b->probs) {
-        if (p->prec != p0->prec || p->dense || p->schedule == BD3MG_SCHED_ROUND || p->prm.method != M_BD3MG)
+        if (p->prec != p0->prec || p->dense || p->schedule == BD3MG_SCHED_ROUND || p->prm.method != M_BD3MG ||
+            p->prm.tv3d)
             return false;
         if (p->kz != p0->kz || p->geom.R != p0->geom.R || p->geom.ty_dirs != p0->geom.ty_dirs ||
             p->geom.ty_update != p0->geom.ty_update)

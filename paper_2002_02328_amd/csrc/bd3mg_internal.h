@@ -90,6 +90,7 @@ struct Params {
     double mu;   // curvature inflation of every block majorant (A_S + mu Id)
     int method;  // Method
     double lip;  // L of the metric L Id (M_GD, M_CG)
+    int tv3d;    // total variation over (VX, VY, VZ) instead of (VX, VY) per slice
 };
 
 struct Geom {

@@ -340,6 +340,9 @@ __device__ __forceinline__ size_t slot_of(const VB &v)
 //   (H^T r)_k = sum_c gz_{k+c}[c] q_{k+c}
 //   g = H^T r + lambda (VX^T(w VX x) + VY^T(w VY x)) + 2 eta (x - clip x)
 //       + 2 kappa VZ^T VZ x,     w = 1 / sqrt((VX x)^2 + (VY x)^2 + delta^2)
+// and with the total variation taken along z too (TV3), w = 1 / sqrt((VX x)^2
+// + (VY x)^2 + (VZ x)^2 + delta^2) and lambda VZ^T(w VZ x) added, which needs
+// x on slices k - 1 and k + 1 as well.
 // g is formed on the tile plus one column and one row beyond it, so the
 // curvature sums of the block's total-variation majorant, which need the
 // forward differences of g and dp, come out of the same workgroup.
@@ -348,7 +351,7 @@ __device__ __forceinline__ size_t slot_of(const VB &v)
 // GM_EVAL sums ||g||^2 and the TV, box and z terms of f; GM_ZCOMB writes only
 // the z-stencil of q to out.
 // ---------------------------------------------------------------------------
-template <typename T, int KZ>
+template <typename T, int KZ, bool TV3 = false>
 __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevState<T> s, const T *__restrict__ q,
                                           const T *__restrict__ x, T *__restrict__ out,
                                           const Item *__restrict__ items, int mode, double *__restrict__ partials,
@@ -365,6 +368,10 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     __shared__ T G[padded<GW, GH>()];
     __shared__ T D[padded<GW, GH>()];
     __shared__ double red[(NT / 64) * NQG];
+    // TV3: x on slice k - 1 (same positions as X), and at the positions of w
+    // the z part w_{k-1} VZ x_{k-1} - w_k VZ x_k of VZ^T(w VZ x)
+    __shared__ T XM[TV3 ? padded<XW, XH>() : 1];
+    __shared__ T PT[TV3 ? padded<PW, PH>() : 1];
 
     // tiles in the XCD-aware order within the slice (neighbours share their
     // halos in L2; the same tile of consecutive slices stays on one XCD)
@@ -387,6 +394,27 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
         for (int qq = 0; qq < rx.E; ++qq) {
             const T v = ldbuf<T>(xs, rx.off[qq] * (uint32_t)sizeof(T));
             xr[qq] = rx.inb[qq] ? v : T(0);
+        }
+    }
+    constexpr int PE = cdiv(PW * PH, NT);
+    T xm[TV3 ? rx.E : 1], xn[TV3 ? PE : 1];
+    if constexpr (TV3) {
+        if (mode != GM_ZCOMB) {
+            // x on slice k - 1 (zero at k = 0) and on slice k + 1 at the
+            // positions of w (zero at k = nz - 1)
+            const __amdgpu_buffer_rsrc_t xa = buf_of(x + (size_t)max(k - 1, 0) * S, S);
+#pragma unroll
+            for (int qq = 0; qq < rx.E; ++qq) {
+                const T v = ldbuf<T>(xa, rx.off[qq] * (uint32_t)sizeof(T));
+                xm[qq] = (rx.inb[qq] && k >= 1) ? v : T(0);
+            }
+            const Region<PW, PH, 1, 1> rp(g, x0, y0);
+            const __amdgpu_buffer_rsrc_t xb = buf_of(x + (size_t)min(k + 1, g.nz - 1) * S, S);
+#pragma unroll
+            for (int qq = 0; qq < PE; ++qq) {
+                const T v = ldbuf<T>(xb, rp.off[qq] * (uint32_t)sizeof(T));
+                xn[qq] = (rp.inb[qq] && k < g.nz - 1) ? v : T(0);
+            }
         }
     }
     uint32_t bo[rg.E];
@@ -445,6 +473,10 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     }
 #pragma unroll
     for (int qq = 0; qq < rx.E; ++qq) X[threadIdx.x + qq * NT] = xr[qq];
+    if constexpr (TV3) {
+#pragma unroll
+        for (int qq = 0; qq < rx.E; ++qq) XM[threadIdx.x + qq * NT] = xm[qq];
+    }
     __syncthreads();
     // w, w VX x and w VY x once per position; zero outside the slice
     const T del2 = (T)(prm.delta * prm.delta);
@@ -456,18 +488,34 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
             if (e < N) {
                 const int jj = e / PW, ii = e - jj * PW;
                 const int j = y0 - 1 + jj, i = x0 - 1 + ii;
-                T px = 0, py = 0, w = 0;
+                T px = 0, py = 0, w = 0, pt = 0;
                 if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
                     const T *xc = X + jj * XW + ii;
                     const T dxv = (i < g.nx - 1) ? xc[1] - xc[0] : T(0);
                     const T dyv = (j < g.ny - 1) ? xc[XW] - xc[0] : T(0);
-                    w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
+                    if constexpr (TV3) {
+                        const T dzv = (k < g.nz - 1) ? xn[qq] - xc[0] : T(0);
+                        w = inv_sqrt(dxv * dxv + dyv * dyv + dzv * dzv + del2);
+                        // w VZ x on slice k - 1 at the same position
+                        T zm = 0;
+                        if (k >= 1) {
+                            const T *mc = XM + jj * XW + ii;
+                            const T dxm = (i < g.nx - 1) ? mc[1] - mc[0] : T(0);
+                            const T dym = (j < g.ny - 1) ? mc[XW] - mc[0] : T(0);
+                            const T dzm = xc[0] - mc[0];
+                            zm = inv_sqrt(dxm * dxm + dym * dym + dzm * dzm + del2) * dzm;
+                        }
+                        pt = zm - w * dzv;
+                    } else {
+                        w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
+                    }
                     px = w * dxv;
                     py = w * dyv;
                 }
                 PX[e] = px;
                 PY[e] = py;
                 WW[e] = w;
+                if constexpr (TV3) PT[e] = pt;
             }
         }
     }
@@ -489,7 +537,8 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
             const T xv = xc[0];
             // VX^T(w VX x) + VY^T(w VY x) at (j, i); P is zero outside the slice
             const int pc = (lj + 1) * PW + (li + 1);
-            const T tv = PX[pc - 1] - PX[pc] + PY[pc - PW] - PY[pc];
+            T tv = PX[pc - 1] - PX[pc] + PY[pc - PW] - PY[pc];
+            if constexpr (TV3) tv += PT[pc];
             const T box = xv - clampv(xv, lo, hi);
             gv = ht[qq] + lam * tv + eta2 * box;
             const size_t o = (size_t)k * S + rg.off[qq];
@@ -502,6 +551,8 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
                     zz -= dz;
                 }
                 gv += kap2 * zz;
+            } else if (TV3 && mode == GM_EVAL && k < g.nz - 1) {
+                dz = x[o + S] - xv;
             }
             if (interior) {
                 if (block) {
@@ -520,7 +571,8 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
                     const double bx = xd - (xd < prm.xmin ? prm.xmin : (xd > prm.xmax ? prm.xmax : xd));
                     const double gd = (double)gv;
                     qs[0] += gd * gd;
-                    qs[1] += sqrt(dxd * dxd + dyd * dyd + prm.delta * prm.delta);
+                    const double tz = TV3 ? dzd * dzd : 0.0;
+                    qs[1] += sqrt(dxd * dxd + dyd * dyd + tz + prm.delta * prm.delta);
                     qs[2] += bx * bx;
                     qs[3] += dzd * dzd;
                 }
@@ -556,13 +608,13 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     }
 }
 
-template <typename T, int KZ>
+template <typename T, int KZ, bool TV3>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
        int nshare)
 {
-    grad_body<T, KZ>(vb_native(), g, prm, s, q, x, out, items, mode, partials, nshare);
+    grad_body<T, KZ, TV3>(vb_native(), g, prm, s, q, x, out, items, mode, partials, nshare);
 }
 
 // ---------------------------------------------------------------------------
@@ -630,10 +682,11 @@ __device__ __forceinline__ void solve_block(const Params &prm, const BlockRange 
     // not at entry, so that its load overlaps those of the slots)
     if (threadIdx.x == 0 && !(stop && *stop)) {
         // gradient pass: <g,g>, <g,dp>, <dp,dp>, then the TV curvature sums;
-        // direction pass: <Hd_a,Hd_b>, then <VZ d_a, VZ d_b>
+        // direction pass: <Hd_a,Hd_b>, then <VZ d_a, VZ d_b> (weighted by
+        // 2 kappa + lambda w already when the TV is taken along z)
         const double gg = tot[0], gd = tot[1], dd = tot[2];
         const double *w = tot + 3, *h = tot + NQG, *z = tot + NQG + 3;
-        const double e2 = 2.0 * prm.eta + prm.mu, k2 = 2.0 * prm.kappa, lam = prm.lambda;
+        const double e2 = 2.0 * prm.eta + prm.mu, k2 = prm.tv3d ? 1.0 : 2.0 * prm.kappa, lam = prm.lambda;
         double b11 = h[0] + e2 * gg + lam * w[0] + k2 * z[0];
         double b12 = h[1] - e2 * gd + lam * w[1] + k2 * z[1];
         double b22 = h[2] + e2 * dd + lam * w[2] + k2 * z[2];
@@ -696,6 +749,24 @@ k_solve(Params prm, const BlockRange *__restrict__ brs, int ntg, int ntd, const 
 // (a unit): their z-combines share KZ - 1 source slices, which are read once.
 // ---------------------------------------------------------------------------
 
+// Weight of the products of z differences of a block step at voxel o =
+// (k, j, i): with the total variation taken along z as well (TV3) it is
+// 2 kappa + lambda w, w of the current x there computed as the gradient pass
+// does; otherwise 1 (the solve multiplies the plain sums by 2 kappa).
+template <typename T>
+__device__ __forceinline__ double zweight(const Geom &g, const Params &prm, const T *__restrict__ x, int k,
+                                          int j, int i, size_t o)
+{
+    if (!prm.tv3d) return 1.0;
+    const size_t S = (size_t)g.nx * g.ny;
+    const T xv = x[o];
+    const T dxv = (i < g.nx - 1) ? x[o + 1] - xv : T(0);
+    const T dyv = (j < g.ny - 1) ? x[o + g.nx] - xv : T(0);
+    const T dzv = (k < g.nz - 1) ? x[o + S] - xv : T(0);
+    const T w = inv_sqrt(dxv * dxv + dyv * dyv + dzv * dzv + (T)(prm.delta * prm.delta));
+    return 2.0 * prm.kappa + prm.lambda * (double)w;
+}
+
 // LDS passes, stores and sums of one output slice kk (direction item i) from
 // its z-combined d1, d2 on the tile plus an R halo.
 template <typename T, int R, int TYK, int E>
@@ -748,7 +819,8 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
 #pragma unroll
     for (int v = 0; v < NQD; ++v) qs[v] = 0.0;
     const bool ink = (kk >= z0 && kk < z1);
-    const bool zterm = (prm.kappa != 0.0) && kk >= z0 - 1 && kk < z1 && kk < g.nz - 1;
+    const bool zsums = prm.kappa != 0.0 || prm.tv3d;
+    const bool zterm = zsums && kk >= z0 - 1 && kk < z1 && kk < g.nz - 1;
     const T *__restrict__ gg = s.g;
     const T *__restrict__ dpv = s.dp[0];
 #pragma unroll
@@ -771,14 +843,15 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
                 z1v += (double)gg[o];
                 z2v -= (double)dpv[o];
             }
-            qs[3] += z1v * z1v;
-            qs[4] += z1v * z2v;
-            qs[5] += z2v * z2v;
+            const double c = zweight(g, prm, s.x, kk, j, ii, o);
+            qs[3] += c * z1v * z1v;
+            qs[4] += c * z1v * z2v;
+            qs[5] += c * z2v * z2v;
         }
     }
-    // without the VZ term the last three sums are zero
+    // without a VZ term the last three sums are zero
     wg_reduce_store<NQD>(qs, red, partials + ((i * vb.gy + tl.y) * vb.gx + tl.x) * NQD,
-                         prm.kappa != 0.0 ? NQD : 3);
+                         zsums ? NQD : 3);
 }
 
 template <typename T, int KZ, int R, int TYK>
@@ -1360,7 +1433,7 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
         T *o1 = s.hd[0] + (size_t)blockIdx.z * S, *o2 = s.hd[1] + (size_t)blockIdx.z * S;
         const int z0 = it.z0, z1 = it.z0 + it.n;
         const bool ink = (k >= z0 && k < z1);
-        const bool zterm = (prm.kappa != 0.0) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
+        const bool zterm = (prm.kappa != 0.0 || prm.tv3d) && k >= z0 - 1 && k < z1 && k < g.nz - 1;
 #pragma unroll
         for (int e = 0; e < NRD; ++e) {
             const int j = y0 + r0 + e, i = x0 + tx;
@@ -1384,9 +1457,10 @@ k_dense(Geom g, Params prm, DevState<T> s, const T *__restrict__ pk, const T *__
                     z1v += (double)s.g[ov];
                     z2v -= (double)s.dp[0][ov];
                 }
-                qs[3] += z1v * z1v;
-                qs[4] += z1v * z2v;
-                qs[5] += z2v * z2v;
+                const double c = zweight(g, prm, s.x, k, j, i, ov);
+                qs[3] += c * z1v * z1v;
+                qs[4] += c * z1v * z2v;
+                qs[5] += c * z2v * z2v;
             }
         }
         wg_reduce_store<NQD>(qs, red, partials + slot_of(vb_native()) * NQD);
@@ -1831,9 +1905,15 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
 {
     if (nitems <= 0) return hipSuccess;
     if (nshare > 0 && g.rz != 0) return hipErrorInvalidValue;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                    BD3MG_LAUNCH((k_grad<T, KZ>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
-                                       s, q, x, out, items, mode, partials, nshare));
+    if (prm.tv3d) {
+        BD3MG_KZ_SWITCH(2 * g.rz + 1,
+                        BD3MG_LAUNCH((k_grad<T, KZ, true>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
+                                           s, q, x, out, items, mode, partials, nshare));
+    } else {
+        BD3MG_KZ_SWITCH(2 * g.rz + 1,
+                        BD3MG_LAUNCH((k_grad<T, KZ, false>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
+                                           s, q, x, out, items, mode, partials, nshare));
+    }
     return hipGetLastError();
 }
 

@@ -13,9 +13,9 @@ def rounded(a, prec):
 
 
 def pair(orc, shape, prec, seed, kx=5, ky=5, kz=5, tables="gauss", lam=0.01, delta=0.02, eta=0.01,
-         kappa=0.0, nslices=None, schedule=binding.SCHED_COLORED, y=None, mu=0.0):
+         kappa=0.0, nslices=None, schedule=binding.SCHED_COLORED, y=None, mu=0.0, tv3d=False):
     """(gpu problem, oracle problem, y) with identical rounded inputs (mu: the
-    curvature inflation of both)."""
+    curvature inflation of both; tv3d: the total variation along z too)."""
     nz, ny, nx = shape
     rng = np.random.default_rng(seed)
     if tables == "gauss":
@@ -32,10 +32,12 @@ def pair(orc, shape, prec, seed, kx=5, ky=5, kz=5, tables="gauss", lam=0.01, del
         p0 = orc.Problem(np.zeros(shape), gx, gy, gz)
         y = p0.H(w.xbar) + w.noise
     y = rounded(y, prec)
-    o = orc.Problem(y, gx, gy, gz, lam=lam, delta=delta, eta=eta, kappa=kappa, mu=mu)
+    o = orc.Problem(y, gx, gy, gz, lam=lam, delta=delta, eta=eta, kappa=kappa, mu=mu, tv3d=tv3d)
     g = binding.Problem(nx, ny, nz, prec)
     if mu:
         g.set_inflation(mu)
+    if tv3d:
+        g.set_tv3d(True)
     g.set_psf_separable(gx, gy, gz)
     g.set_params(lam, delta, eta, kappa)
     g.set_data(y)
