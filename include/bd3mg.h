@@ -284,9 +284,11 @@ bd3mg_status bd3mg_run(bd3mg_problem p, int max_sweeps, double grad_rtol, int ch
  * that overlap in time on one GPU (any problems, any streams) race and must
  * be ordered by the caller.  The stop-test control block is cleared at the
  * start of every call; every other part is written before it is read.
- * Differences from bd3mg_run: a passing check is confirmed on q rebuilt in
- * place from x (then kept), and res->f is formed from q rebuilt in place;
- * profiling is not recorded.  Needs the separable PSF and a built schedule
+ * Differences from bd3mg_run: both directions are blurred every sweep (no
+ * H dp is kept, as with BD3MG_OPT_HDP_EVERY = 0, whose bd3mg_run it equals
+ * bitwise); a passing check is confirmed on q rebuilt in place from x (then
+ * kept), and res->f is formed from q rebuilt in place; profiling is not
+ * recorded.  Needs the separable PSF and a built schedule
  * (bd3mg_get_schedule, bd3mg_run or bd3mg_eval after the last change of
  * blocks or PSF): ERR_STATE otherwise, as for a missing PSF, data or
  * blocks.  x^0 = y, the reference norm ||grad f(y)|| and q are formed in
@@ -308,7 +310,10 @@ bd3mg_status bd3mg_get_state(bd3mg_problem p, void *x, void *dprev, void *q, lon
                              int on_device);
 
 /* Resume: restore a state saved with bd3mg_get_state.  With q == NULL the
- * blurred residual is recomputed from x (equal up to rounding, not bitwise). */
+ * blurred residual is recomputed from x (equal up to rounding, not bitwise).
+ * H dp (BD3MG_OPT_HDP_EVERY) is not part of the state: the first sweep after
+ * a resume blurs both directions, so the resumed run equals the uninterrupted
+ * one bitwise only with BD3MG_OPT_HDP_EVERY = 0 (else up to rounding). */
 bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, const void *q,
                              long long sweeps, int on_device);
 
@@ -347,7 +352,20 @@ typedef enum {
      * slices of a block share the reads of their common source slices), or 0
      * (the default: 2 for a launch group with at least 2^20 direction output
      * voxels, else 1).  Results are bitwise the same for every setting. */
-    BD3MG_OPT_DIRS_SLICES = 5
+    BD3MG_OPT_DIRS_SLICES = 5,
+    /* Keeping H dp (Sec. 2.3, Worker: the subspace is [-grad, d_prev], so its
+     * second image H d2 = H d_prev is the H d' the block's previous visit
+     * formed).  n >= 1 (default 64): the update pass stores each block's
+     * H d' = u1 H d1 + u2 H d2 for the block's next visit, whose direction
+     * pass then blurs d1 = -grad only; every n-th sweep blurs both directions
+     * again, bounding the rounding the recurrence carries (n = 1: always).
+     * 0: both directions every sweep, nothing kept.  Applies to bd3mg_run
+     * with the separable PSF and a method other than Async-MM; batches,
+     * bd3mg_run_noalloc and bd3mg_block_step blur both directions.  Costs two
+     * volumes of sum over blocks of |S +- r_z| slices, allocated at the first
+     * run (without them, both directions are blurred).  Results differ from
+     * n = 0 by rounding only. */
+    BD3MG_OPT_HDP_EVERY = 6
 } bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
 
@@ -400,7 +418,8 @@ bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms)
  * once for all problems, its grid the concatenation of every problem's
  * work list (each problem as many workgroups as its own launch would have),
  * so a sweep of the whole batch is 4 x (most colours) launches; results are
- * bitwise those of the problems run one by one.  Branch mode (or a batch
+ * bitwise those of the problems run one by one with BD3MG_OPT_HDP_EVERY = 0
+ * (batch sweeps blur both directions and keep no H dp).  Branch mode (or a batch
  * that cannot be fused): each problem's sweep is captured on its own stream
  * into the graph (fork/join), problems as parallel branches.
  * ------------------------------------------------------------------------- */

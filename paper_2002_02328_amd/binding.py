@@ -25,6 +25,7 @@ METHOD_BD3MG, METHOD_ASYNC_GD, METHOD_ASYNC_CG, METHOD_ASYNC_MM = 0, 1, 2, 3
 BATCH_AUTO, BATCH_FUSED, BATCH_BRANCHES = 0, 1, 2
 OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
 OPT_TILE_ROWS_DIRS, OPT_TILE_ROWS_UPDATE, OPT_TILE_ROWS_AUX, OPT_DIRS_SLICES = 2, 3, 4, 5
+OPT_HDP_EVERY = 6
 KERNEL_KINDS = ("grad", "dirs", "solve", "update", "eval")
 
 # Every function the header declares, with its C signature.

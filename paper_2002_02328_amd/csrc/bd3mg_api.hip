@@ -82,6 +82,9 @@ struct bd3mg_problem_s {
         int du_off, du_cnt;  // direction units: one or two consecutive slices of a block
         double bytes[4];  // algorithmic bytes of the gradient, direction, solve and update passes
         bool round;       // update pass over every slice with per-slice block coefficients
+        int dbase;        // colour groups: first direction item among all colour groups' items
+        double bytes_one; // direction pass blurring d1 only (H dp read)
+        double bytes_hdw; // update pass: the stores of every pair's H d'
     };
     std::vector<Group> groups;  // ncolors colour groups, then one group per block
     Item *d_items = nullptr;
@@ -97,6 +100,13 @@ struct bd3mg_problem_s {
     int dirs_slices = 0;      // slices per direction workgroup (0: by group size)
     void *d_hd = nullptr;     // H d1 then H d2 of a launch group's direction items
     size_t hd_alloc = 0, hd_slots = 0;
+    // H dp of every colour group's direction items, the update pass's H d'
+    // kept for the block's next visit: two buffers of hdp_slots slots, the
+    // one read selected by the parity of cur (as dpb)
+    void *d_hdp = nullptr;
+    size_t hdp_alloc = 0, hdp_slots = 0;
+    long long hdp_every = 64;  // sweeps 0, n, 2n, ... (counted from x^0) blur both directions (0: H dp never kept)
+    bool hdp_valid = false;    // the buffer cur selects holds H dp of every block
     int maxg = 1, maxd = 1;   // most gradient and direction items of a launch group
 
     // reductions
@@ -160,6 +170,7 @@ DevState<T> dev_state(bd3mg_problem p)
     s.sblk = p->d_sblk;
     s.hd[0] = (T *)p->d_hd;
     s.hd[1] = s.hd[0] ? s.hd[0] + p->hd_slots * p->nx * p->ny : nullptr;
+    s.hdw = nullptr;
     s.stop = nullptr;
     return s;
 }
@@ -301,6 +312,7 @@ bd3mg_status zero_steps(bd3mg_problem p)
     HIP_TRY(hipMemsetAsync(p->dpb[0], 0, p->N * p->esz, p->stream));
     HIP_TRY(hipMemsetAsync(p->dpb[1], 0, p->N * p->esz, p->stream));
     p->cur = 0;
+    p->hdp_valid = false;
     return BD3MG_OK;
 }
 
@@ -362,6 +374,7 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     const int rd = std::max(rz, z_coupled(p) ? 1 : 0);
     grp.g_off = (int)gi.size();
     grp.d_off = (int)di.size();
+    grp.dbase = (int)di.size();
     grp.u_off = (int)ui.size();
     grp.br_off = (int)br.size();
     grp.du_off = (int)units.size();
@@ -439,6 +452,10 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
     grp.bytes[1] = A * (2.0 * sl + 2.0 * grp.d_cnt);
     grp.bytes[2] = (double)(grp.g_cnt * NQG + grp.d_cnt * NQD) * p->ntiles * sizeof(double);
     grp.bytes[3] = A * (2.0 * np + 5.0 * sl + 2.0 * h);
+    // reading H dp instead of dp and blurring d1 only: g on S and H dp of
+    // the items read, H d1 written; the update pass then also writes H d'
+    grp.bytes_one = A * (sl + 2.0 * grp.d_cnt);
+    grp.bytes_hdw = A * np;
 }
 
 // Buffers of Async-MM's inner solve for launch groups of at most maxg
@@ -502,6 +519,7 @@ bd3mg_status build_schedule(bd3mg_problem p)
             if (p->color[b] == c) blocks.push_back(b);
         group_items(p, blocks, gi, di, ui, pairs, units, br, p->groups[c], p->schedule == BD3MG_SCHED_ROUND);
     }
+    const size_t ndc = di.size();  // direction items of the colour groups
     for (int b = 0; b < nb; ++b) group_items(p, {b}, gi, di, ui, pairs, units, br, p->groups[p->ncolors + b]);
     // one device array: gradient items, then direction items, then update items
     const int ng = (int)gi.size(), nd = (int)di.size();
@@ -558,6 +576,8 @@ bd3mg_status build_schedule(bd3mg_problem p)
     ST_TRY(realloc_dev(&p->d_hd, &p->hd_alloc, 2 * (size_t)maxd * p->nx * p->ny * p->esz,
                        "stored directions H d1, H d2"));
     p->hd_slots = (size_t)maxd;
+    p->hdp_slots = ndc;
+    p->hdp_valid = false;
     if (p->dense) {
         ST_TRY(ensure_tmp(p, 4));  // H^T r of the gradient pass
         size_t sl = 1;
@@ -688,12 +708,47 @@ bd3mg_status method_ready(bd3mg_problem p)
     return BD3MG_OK;
 }
 
+// The two H dp buffers, when H dp is kept (separable PSF, not Async-MM).
+// Not having the memory is not an error: the direction pass then blurs both
+// directions every sweep.
+bd3mg_status ensure_hdp(bd3mg_problem p)
+{
+    if (p->hdp_every <= 0 || p->dense || p->prm.method == M_MM) return BD3MG_OK;
+    const size_t need = 2 * p->hdp_slots * p->nx * p->ny * p->esz;
+    if (need <= p->hdp_alloc) return BD3MG_OK;
+    if (p->d_hdp) HIP_TRY(hipFree(p->d_hdp));
+    p->d_hdp = nullptr;
+    p->hdp_alloc = 0;
+    p->hdp_valid = false;
+    if (hipMalloc(&p->d_hdp, need) != hipSuccess) {
+        p->d_hdp = nullptr;
+        (void)hipGetLastError();
+        return BD3MG_OK;
+    }
+    p->hdp_alloc = need;
+    return BD3MG_OK;
+}
+
+// Direction-pass mode of sweep sw (counted from x^0): 0 blurs d1 and d2 and
+// keeps no H dp; 1 blurs both and the update pass stores every block's H d'
+// as the H dp of its next visit; 2 blurs d1 only and reads H dp.  Both
+// directions are blurred again on every hdp_every-th sweep, so that the
+// rounding the recurrence H dp' = u1 H d1 + u2 H dp carries does not build
+// up; the choice depends on the sweep count only, so runs split into several
+// calls, or checked at other sweeps, take the same modes.
+int hdp_mode(bd3mg_problem p, bool noalloc, long long sw)
+{
+    if (noalloc || p->dense || p->prm.method == M_MM || p->hdp_every <= 0 || !p->d_hdp) return 0;
+    return (p->hdp_valid && sw % p->hdp_every != 0) ? 2 : 1;
+}
+
 bd3mg_status ensure_ready(bd3mg_problem p)
 {
     if (!p->psf_set) return fail(BD3MG_ERR_STATE, "the PSF is not set");
     if (!p->data_set) return fail(BD3MG_ERR_STATE, "the data y is not set");
     ST_TRY(method_ready(p));
     ST_TRY(build_schedule(p));
+    ST_TRY(ensure_hdp(p));
     if (!p->x_set) {
         HIP_TRY(hipMemcpyAsync(p->x, p->y, p->N * p->esz, hipMemcpyDeviceToDevice, p->stream));
         ST_TRY(zero_steps(p));
@@ -714,12 +769,22 @@ bd3mg_status ensure_ready(bd3mg_problem p)
     return BD3MG_OK;
 }
 
-// Enqueue the passes of one launch group: gradient, direction, solve, update.
+// Enqueue the passes of one launch group: gradient, direction, solve, update
+// (hdp: the direction-pass mode of hdp_mode; colour groups only).
 template <typename T>
-bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof, const int *stop)
+bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof, const int *stop, int hdp)
 {
     DevState<T> s = dev_state<T>(p);
     s.stop = stop;
+    if (hdp) {
+        // H d2 of the group's items (H dp, or blurred and stored by the
+        // direction pass) in the buffer of this sweep, the pairs' H d' into
+        // the other one
+        const size_t S = (size_t)p->nx * p->ny, span = p->hdp_slots * S;
+        T *hb = (T *)p->d_hdp;
+        s.hd[1] = hb + p->cur * span + (size_t)gr.dbase * S;
+        s.hdw = hb + (p->cur ^ 1) * span + (size_t)gr.dbase * S;
+    }
     const Item *it = p->d_items;
     if (p->dense) {
         // general kernels: H^T r and grad f on S, H d1 and H d2 on S +- r_z by
@@ -775,8 +840,9 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
         if (prof) ST_TRY(prof_end(p));
         u = p->d_u10;
     } else {
-        if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, gr.bytes[1]));
-        HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, p->d_units + gr.du_off, gr.du_cnt, p->d_pd, p->stream));
+        if (prof) ST_TRY(prof_begin(p, BD3MG_K_DIRS, hdp == 2 ? gr.bytes_one : gr.bytes[1]));
+        HIP_TRY(launch_dirs<T>(p->geom, p->prm, s, p->d_units + gr.du_off, gr.du_cnt, p->d_pd, p->stream,
+                               hdp == 2));
         if (prof) ST_TRY(prof_end(p));
         if (prof) ST_TRY(prof_begin(p, BD3MG_K_SOLVE, gr.bytes[2]));
         HIP_TRY(launch_solve(p->prm, p->d_br + gr.br_off, gr.br_cnt, p->ntiles,
@@ -784,17 +850,17 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
                              p->stream));
         if (prof) ST_TRY(prof_end(p));
     }
-    if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3]));
+    if (prof) ST_TRY(prof_begin(p, BD3MG_K_UPDATE, gr.bytes[3] + (hdp ? gr.bytes_hdw : 0.0)));
     HIP_TRY(launch_update<T>(p->geom, s, it + gr.u_off, gr.u_cnt, p->d_pairs, u, gr.round, p->stream));
     if (prof) ST_TRY(prof_end(p));
     return BD3MG_OK;
 }
 
 bd3mg_status phase(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool prof,
-                   const int *stop = nullptr)
+                   const int *stop = nullptr, int hdp = 0)
 {
-    return p->prec == BD3MG_FP64 ? phase_t<double>(p, gr, prof, stop)
-                                 : phase_t<float>(p, gr, prof, stop);
+    return p->prec == BD3MG_FP64 ? phase_t<double>(p, gr, prof, stop, hdp)
+                                 : phase_t<float>(p, gr, prof, stop, hdp);
 }
 
 // One operator of the criterion on ti into to (tr, tr2: scratch volumes;
@@ -994,7 +1060,9 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
             }
         }
         for (; s < end; ++s) {
-            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile, stop));
+            const int hm = hdp_mode(p, noalloc, sweeps0 + s);
+            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile, stop, hm));
+            p->hdp_valid = hm != 0;
             p->cur ^= 1;
             const long long sw = sweeps0 + s + 1;
             if (p->refresh_every > 0 && (sw % p->refresh_every) == 0) {
@@ -1190,7 +1258,7 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
                     p->d_pk, p->d_ones, p->d_hts,
                     p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_sblk, p->d_pg, p->d_pd,
                     p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_pairs, p->d_hd,
-                    p->d_units};
+                    p->d_units, p->d_hdp};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     void *mm[] = {p->mmv[0], p->mmv[1], p->mmv[2], p->mmv[3], p->mmv[4], p->d_pma, p->d_prr, p->d_cgs,
@@ -1593,6 +1661,7 @@ bd3mg_status bd3mg_set_state(bd3mg_problem p, const void *x, const void *dprev, 
     if (sweeps < 0) return fail(BD3MG_ERR_ARG, "sweeps < 0");
     ST_TRY(upload(p, p->x, x, on_device));
     ST_TRY(upload(p, p->dpb[p->cur], dprev, on_device));
+    p->hdp_valid = false;
     p->x_set = true;
     if (q) {
         ST_TRY(upload(p, p->q, q, on_device));
@@ -1615,6 +1684,11 @@ bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value)
     case BD3MG_OPT_PROFILE:
         ST_TRY(prof_collect(p));
         p->profile = value != 0;
+        return BD3MG_OK;
+    case BD3MG_OPT_HDP_EVERY:
+        if (value < 0) return fail(BD3MG_ERR_ARG, "H dp interval < 0");
+        p->hdp_every = value;
+        p->hdp_valid = false;
         return BD3MG_OK;
     case BD3MG_OPT_TILE_ROWS_DIRS:
     case BD3MG_OPT_TILE_ROWS_UPDATE:
@@ -1683,8 +1757,9 @@ bd3mg_status bd3mg_autotune(bd3mg_problem p, int sweeps, int *chosen, double *ms
     p->geom.ty_dirs = bd;
     p->geom.ty_update = bu;
     p->profile = prof0;
-    // restore the state
+    // restore the state (H dp is blurred afresh on the next sweep)
     p->cur = cur0;
+    p->hdp_valid = false;
     HIP_TRY(hipMemcpyAsync(p->x, p->tmp[0], vb, hipMemcpyDeviceToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->dpb[p->cur], p->tmp[1], vb, hipMemcpyDeviceToDevice, p->stream));
     HIP_TRY(hipMemcpyAsync(p->q, p->tmp[2], vb, hipMemcpyDeviceToDevice, p->stream));
@@ -1749,6 +1824,7 @@ bd3mg_status bd3mg_block_step(bd3mg_problem p, int block, double *info)
     const int nb = (int)p->nsl.size();
     if (block < 0 || block >= nb) return fail(BD3MG_ERR_ARG, "block %d out of range", block);
     ST_TRY(phase(p, p->groups[p->ncolors + block], false));
+    p->hdp_valid = false;  // this block's step changed outside the sweep order
     // keep every block's step in one buffer: copy this block's new step back
     const size_t off = (size_t)p->z0[block] * p->nx * p->ny * p->esz;
     const size_t len = (size_t)p->nsl[block] * p->nx * p->ny * p->esz;
@@ -2103,7 +2179,10 @@ bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, in
     if (!b) return fail(BD3MG_ERR_ARG, "null batch");
     if (max_sweeps < 0 || check_every < 0) return fail(BD3MG_ERR_ARG, "negative sweep count");
     const int n = (int)b->probs.size();
-    for (bd3mg_problem p : b->probs) ST_TRY(ensure_ready(p));
+    for (bd3mg_problem p : b->probs) {
+        ST_TRY(ensure_ready(p));
+        p->hdp_valid = false;  // batch sweeps blur both directions and keep no H dp
+    }
     const bool stopping = grad_rtol > 0.0;
     int ce = check_every > 0 ? check_every : 16;
     ce += ce & 1;  // checks fall between graph launches of two sweeps

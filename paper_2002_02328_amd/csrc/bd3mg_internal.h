@@ -117,6 +117,7 @@ struct DevState {
     const T *gz;               // z PSF table [nz][kz]
     const int *sblk;           // block of every slice
     T *hd[2];                  // H d1, H d2 of the launch group's direction items [slot][ny][nx]
+    T *hdw;                    // when set: H d' of each update pair written here by slot (H dp of the next visit)
 };
 
 enum GradMode : int {
@@ -135,10 +136,11 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
 
 // Direction pass over nunits units (slice k of a block with the block's z0,
 // n; first direction item h0 and hn = 1 or 2 consecutive slices); stores
-// H d1, H d2 of item i at slot i of s.hd.
+// H d1, H d2 of item i at slot i of s.hd (one: only H d1; H d2 = H dp is read
+// from slot i of s.hd[1], where the update pass of the previous visit stored it).
 template <typename T>
 hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *units,
-                       int nunits, double *partials, hipStream_t st);
+                       int nunits, double *partials, hipStream_t st, bool one = false);
 
 // Update pass from the stored H d1, H d2 (pairs: (slot, block) per source;
 // multi: items may have more than one source, as in a round).

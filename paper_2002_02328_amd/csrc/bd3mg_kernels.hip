@@ -768,12 +768,18 @@ __device__ __forceinline__ double zweight(const Geom &g, const Params &prm, cons
 }
 
 // LDS passes, stores and sums of one output slice kk (direction item i) from
-// its z-combined d1, d2 on the tile plus an R halo.
-template <typename T, int R, int TYK, int E>
+// its z-combined d1, d2 on the tile plus an R halo.  ONE: only d1 was
+// z-combined; H d2 = H dp is the one the update pass of the block's previous
+// visit formed and stored (slot i of s.hd[1]), read here for the sums, on
+// the slices S +- r_z it reaches (live); the direction items below them (the
+// slice under the block that the VZ sums need when r_z = 0) have H dp = 0 and
+// no update item that would store it.
+template <typename T, int R, int TYK, bool ONE, int E>
 __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, const DevState<T> &s,
                                             const Item &it, int kk, size_t i, const T (&v1)[E],
                                             const T (&v2)[E], const uint32_t (&off)[E], const bool (&inb)[E],
-                                            T *A1, T *A2, T *B1, double *partials, uint2 tl, const VB &vb)
+                                            T *A1, T *A2, T *B1, double *partials, uint2 tl, const VB &vb,
+                                            bool live)
 {
     constexpr int NRK = TYK / (NT / TX);
     constexpr int K = 2 * R + 1, W = TX + 2 * R, H = TYK + 2 * R, N = W * H;
@@ -787,32 +793,44 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
     T wx[K], wy[K];
     load_taps<T, R>(wx, s.gx + (size_t)kk * K);
     load_taps<T, R>(wy, s.gy + (size_t)kk * K);
+    const __amdgpu_buffer_rsrc_t o1 = buf_of(s.hd[0] + i * S, S), o2 = buf_of(s.hd[1] + i * S, S);
+    T h1[NRK], h2[NRK];
+    if constexpr (ONE) {
+        // H dp of the outputs, loaded first so that the LDS passes hide it
+#pragma unroll
+        for (int e = 0; e < NRK; ++e) {
+            const int j = y0 + out_row<NRK>(e), ii = x0 + tx;
+            const uint32_t o = (ii < g.nx && j < g.ny) ? (uint32_t)(j * g.nx + ii) * (uint32_t)sizeof(T) : 0u;
+            const T v = ldbuf<T>(o2, o);
+            h2[e] = live ? v : T(0);
+        }
+    }
 #pragma unroll
     for (int qq = 0; qq < E; ++qq) {
         const int e = threadIdx.x + qq * NT;
         if (N % NT != 0 && e >= N) break;
         A1[lds_at<W, WS>(e)] = inb[qq] ? v1[qq] : T(0);
-        A2[lds_at<W, WS>(e)] = inb[qq] ? v2[qq] : T(0);
+        if constexpr (!ONE) A2[lds_at<W, WS>(e)] = inb[qq] ? v2[qq] : T(0);
     }
     __syncthreads();
     xpass4<T, R, H, false>(A1, B1, wx);
     __syncthreads();
-    xpass4<T, R, H, false>(A2, B2, wx);
-    __syncthreads();
-    T h1[NRK], h2[NRK];
+    if constexpr (!ONE) {
+        xpass4<T, R, H, false>(A2, B2, wx);
+        __syncthreads();
+    }
     ypass_out<T, R, TX, R, false, NRK>(B1, h1, wy);
-    ypass_out<T, R, TX, R, false, NRK>(B2, h2, wy);
+    if constexpr (!ONE) ypass_out<T, R, TX, R, false, NRK>(B2, h2, wy);
     {
         // stored for the update pass, which combines them with the step
         // coefficients instead of blurring the new step again
-        const __amdgpu_buffer_rsrc_t o1 = buf_of(s.hd[0] + i * S, S), o2 = buf_of(s.hd[1] + i * S, S);
 #pragma unroll
         for (int e = 0; e < NRK; ++e) {
             const int j = y0 + out_row<NRK>(e), ii = x0 + tx;
             if (ii >= g.nx || j >= g.ny) continue;
             const uint32_t o = (uint32_t)(j * g.nx + ii) * (uint32_t)sizeof(T);
             stbuf(o1, o, h1[e]);
-            stbuf(o2, o, h2[e]);
+            if constexpr (!ONE) stbuf(o2, o, h2[e]);
         }
     }
     double qs[NQD];
@@ -854,7 +872,7 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
                          zsums ? NQD : 3);
 }
 
-template <typename T, int KZ, int R, int TYK>
+template <typename T, int KZ, int R, int TYK, bool ONE = false>
 __device__ __forceinline__ void dirs_body(const VB vb, Geom g, Params prm, DevState<T> s,
                                           const Item *__restrict__ units, double *__restrict__ partials)
 {
@@ -862,13 +880,15 @@ __device__ __forceinline__ void dirs_body(const VB vb, Geom g, Params prm, DevSt
     constexpr int W = TX + 2 * R, H = TYK + 2 * R;
     // the x pass of d2 is written over the z-combine of d1, and the
     // reduction of the inner products over the z-combine of d2 (three tiles,
-    // not four: more workgroups fit a compute unit's LDS)
+    // not four: more workgroups fit a compute unit's LDS); ONE has no d2
+    // tile, only room for the reduction
     constexpr int WS = vstride<T, W>();
+    constexpr int NRED = (NT / 64) * NQD * (int)(sizeof(double) / sizeof(T));
     __shared__ __align__(16) T A1[padded<WS, H>()];
-    __shared__ __align__(16) T A2[padded<WS, H>()];
+    __shared__ __align__(16) T A2[ONE ? NRED : padded<WS, H>()];
     __shared__ __align__(16) T B1[padded<TX, H>()];
     static_assert(padded<TX, H>() <= padded<WS, H>(), "x pass of d2 must fit the d1 tile");
-    static_assert((NT / 64) * NQD * sizeof(double) <= padded<WS, H>() * sizeof(T), "reduction must fit");
+    static_assert(NRED <= padded<WS, H>(), "reduction must fit");
 
     // slice k of the block [z0, z0 + n): direction items h0 and, when hn is
     // 2, h0 + 1 (slice k + 1)
@@ -909,30 +929,32 @@ __device__ __forceinline__ void dirs_body(const VB vb, Geom g, Params prm, DevSt
         const __amdgpu_buffer_rsrc_t gs = buf_of(gg + (size_t)sl * S, S), ds = buf_of(dpv + (size_t)sl * S, S);
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
-            const T gv = ldbuf<T>(gs, bo[qq]), dv = ldbuf<T>(ds, bo[qq]);
+            const T gv = ldbuf<T>(gs, bo[qq]);
+            const T dv = ONE ? T(0) : ldbuf<T>(ds, bo[qq]);
             if (t < KZ) {
                 a1[qq] -= wa * gv;
-                a2[qq] += wa * dv;
+                if constexpr (!ONE) a2[qq] += wa * dv;
             }
             if (t > 0) {
                 b1[qq] -= wb * gv;
-                b2[qq] += wb * dv;
+                if constexpr (!ONE) b2[qq] += wb * dv;
             }
         }
     }
-    dirs_finish<T, R, TYK>(g, prm, s, it, k, (size_t)it.h0, a1, a2, rg.off, rg.inb, A1, A2, B1, partials, tl, vb);
+    dirs_finish<T, R, TYK, ONE>(g, prm, s, it, k, (size_t)it.h0, a1, a2, rg.off, rg.inb, A1, A2, B1, partials, tl,
+                                vb, k >= z0 - RZ);
     if (two) {
         __syncthreads();  // the reduction of slice k read A2
-        dirs_finish<T, R, TYK>(g, prm, s, it, k + 1, (size_t)it.h0 + 1, b1, b2, rg.off, rg.inb, A1, A2, B1,
-                               partials, tl, vb);
+        dirs_finish<T, R, TYK, ONE>(g, prm, s, it, k + 1, (size_t)it.h0 + 1, b1, b2, rg.off, rg.inb, A1, A2, B1,
+                                    partials, tl, vb, k + 1 >= z0 - RZ);
     }
 }
 
-template <typename T, int KZ, int R, int TYK>
+template <typename T, int KZ, int R, int TYK, bool ONE>
 __global__ void __launch_bounds__(NT)
 k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double *__restrict__ partials)
 {
-    dirs_body<T, KZ, R, TYK>(vb_native(), g, prm, s, units, partials);
+    dirs_body<T, KZ, R, TYK, ONE>(vb_native(), g, prm, s, units, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -948,7 +970,9 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
 // H d' is read on the tile plus an R halo (zero outside the slice: the
 // adjoint blur sees zero padding), then blurred back by the adjoint x and y
 // passes of slice m.  Previous steps are read from dp[0] and written to
-// dp[1], so a workgroup never sees a half-updated step.
+// dp[1], so a workgroup never sees a half-updated step.  When s.hdw is set,
+// each pair's H d' on the tile is also stored in its slot there: the H dp of
+// the block's next visit, so that its direction pass blurs only d1.
 // ---------------------------------------------------------------------------
 template <typename T, int R, int TYK, bool MULTI>
 __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, const Item *__restrict__ items,
@@ -1000,6 +1024,15 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
             v[qq] = 0;
             bo[qq] = rg.off[qq] * (uint32_t)sizeof(T);
         }
+        // the tile's own elements of the region (not its halo), where a
+        // pair's H d' is stored for the next visit
+        bool own[rg.E];
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            const int jj = e / W2, ii = e - jj * W2;
+            own[qq] = rg.inb[qq] && jj >= R && jj < R + TYK && ii >= R && ii < R + TX;
+        }
         // sources two at a time, so that the loads of both are in flight
         // together (a round has several per slice; a colour has one, and
         // its instance carries no code for more)
@@ -1016,8 +1049,13 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
             for (int qq = 0; qq < rg.E; ++qq) {
                 const T xa1 = ldbuf<T>(ha1, bo[qq]), xa2 = ldbuf<T>(ha2, bo[qq]);
                 const T xb1 = ldbuf<T>(hb1, bo[qq]), xb2 = ldbuf<T>(hb2, bo[qq]);
-                v[qq] += a1 * xa1 + a2 * xa2;
-                v[qq] += b1 * xb1 + b2 * xb2;
+                const T wa = a1 * xa1 + a2 * xa2, wb = b1 * xb1 + b2 * xb2;
+                v[qq] += wa;
+                v[qq] += wb;
+                if (s.hdw && own[qq]) {
+                    stbuf(buf_of(s.hdw + (size_t)pa.x * S, S), bo[qq], wa);
+                    stbuf(buf_of(s.hdw + (size_t)pb.x * S, S), bo[qq], wb);
+                }
             }
         }
         if (p < it.hn) {
@@ -1027,8 +1065,11 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
             const __amdgpu_buffer_rsrc_t h1 = buf_of(s.hd[0] + (size_t)pr.x * S, S);
             const __amdgpu_buffer_rsrc_t h2 = buf_of(s.hd[1] + (size_t)pr.x * S, S);
 #pragma unroll
-            for (int qq = 0; qq < rg.E; ++qq)
-                v[qq] += c1 * ldbuf<T>(h1, bo[qq]) + c2 * ldbuf<T>(h2, bo[qq]);
+            for (int qq = 0; qq < rg.E; ++qq) {
+                const T w = c1 * ldbuf<T>(h1, bo[qq]) + c2 * ldbuf<T>(h2, bo[qq]);
+                v[qq] += w;
+                if (s.hdw && own[qq]) stbuf(buf_of(s.hdw + (size_t)pr.x * S, S), bo[qq], w);
+            }
         }
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
@@ -1919,12 +1960,18 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
 
 template <typename T>
 hipError_t launch_dirs(const Geom &g, const Params &prm, const DevState<T> &s, const Item *units,
-                       int nunits, double *partials, hipStream_t st)
+                       int nunits, double *partials, hipStream_t st, bool one)
 {
     if (nunits <= 0) return hipSuccess;
-    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
-                    BD3MG_LAUNCH((k_dirs<T, KZ, R, TYK>), grid_of(g, nunits, TYK), dim3(NT), 0,
-                                       st, g, prm, s, units, partials))));
+    if (one) {
+        BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
+                        BD3MG_LAUNCH((k_dirs<T, KZ, R, TYK, true>), grid_of(g, nunits, TYK), dim3(NT), 0,
+                                           st, g, prm, s, units, partials))));
+    } else {
+        BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
+                        BD3MG_LAUNCH((k_dirs<T, KZ, R, TYK, false>), grid_of(g, nunits, TYK), dim3(NT), 0,
+                                           st, g, prm, s, units, partials))));
+    }
     return hipGetLastError();
 }
 
@@ -2171,7 +2218,7 @@ hipError_t scratch_base(int device, void **ptr)
                                        const T *, const T *, T *, const Item *, int, int,         \
                                        double *, hipStream_t, int);                               \
     template hipError_t launch_dirs<T>(const Geom &, const Params &, const DevState<T> &,          \
-                                       const Item *, int, double *, hipStream_t);                 \
+                                       const Item *, int, double *, hipStream_t, bool);           \
     template hipError_t launch_update<T>(const Geom &, const DevState<T> &, const Item *, int,      \
                                          const int2 *, const double *, bool, hipStream_t, int);   \
     template hipError_t launch_majapply<T>(const Geom &, const Params &, const DevState<T> &,      \

@@ -1,9 +1,10 @@
 """GPU parity of batched BD3MG: many problems of uneven sizes advanced together
 through one graph launch per two sweeps.
 
-The batch runs the same kernels with the same arguments as single-problem runs,
-so a batched run must equal the single runs bitwise; against the FP64 oracle
-the usual FP64 / FP32 bounds apply (see test_gpu_solver).
+The batch runs the same kernels with the same arguments as single-problem runs
+that blur both directions every sweep (BD3MG_OPT_HDP_EVERY = 0: a batch keeps
+no H dp), so a batched run must equal those single runs bitwise; against the
+FP64 oracle the usual FP64 / FP32 bounds apply (see test_gpu_solver).
 """
 import numpy as np
 import pytest
@@ -25,6 +26,7 @@ def setup(orc, w, prec):
     g.set_data(y)
     g.set_blocks(w.nslices)
     g.set_x0(None)
+    g.set_option(binding.OPT_HDP_EVERY, 0)  # single runs as a batch runs them
     o = orc.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
     return g, o, y
 

@@ -153,9 +153,16 @@ def test_paper_initial_point(orc, prec):
     assert abs(res["grad_norm_ref"] - o.grad_norm(y)) <= 1e-6 * o.grad_norm(y)
 
 
-def test_determinism_and_resume(orc):
+@pytest.mark.parametrize("hdp_every", [0, 4])
+def test_determinism_and_resume(orc, hdp_every):
+    """Chained runs equal one run bitwise, with or without H dp kept (4: both
+    directions blurred on sweeps 0, 4, 8, ..., so both kinds of sweep fall
+    inside the chained runs).  A resume from a checkpoint with its residual is
+    bitwise when no H dp is kept; with H dp kept the resumed run blurs both
+    directions first and equals the uninterrupted one up to rounding."""
     g, o, y, w = _c1(orc, inputs.small_plain_fp64(), _c1_y(orc), binding.FP32)
     g.set_option(binding.OPT_REFRESH_EVERY, 4)  # refreshes fall inside the chained runs
+    g.set_option(binding.OPT_HDP_EVERY, hdp_every)
     g.set_x0(None)
     g.run(12)
     xa, da = g.get_x(), g.get_dprev()
@@ -170,7 +177,10 @@ def test_determinism_and_resume(orc):
     g.run(1)
     g.set_state(*st5)
     g.run(7)
-    assert np.array_equal(g.get_x(), xa) and np.array_equal(g.get_dprev(), da)
+    if hdp_every == 0:
+        assert np.array_equal(g.get_x(), xa) and np.array_equal(g.get_dprev(), da)
+    else:
+        assert rel(g.get_x(), xa) <= 1e-5 and rel(g.get_dprev(), da) <= 1e-3
     # without the residual the resume is equal up to rounding only
     g.set_state(st5[0], st5[1], None, st5[3])
     g.run(7)
@@ -189,11 +199,20 @@ def test_profile_counts_launches(orc):
         n, ms, by = prof[k]
         assert n == 3 * nc and ms > 0 and by > 0
     assert prof["eval"][0] == 0
-    # per sweep, the direction pass reads g and dp on every block slice and
-    # writes H d1, H d2 on S +- r_z of every block (6 + 8 + 8 + 6 slices);
-    # the update pass reads H d1, H d2 there, reads g, dp, x and writes x, dp
-    # on the block slices, and reads and writes q on S +- r_z
+    # the direction pass of sweep 0 reads g and dp on every block slice and
+    # writes H d1, H d2 on S +- r_z of every block (6 + 8 + 8 + 6 slices); on
+    # sweeps 1 and 2 (H dp kept) it reads g on the block slices and H dp on
+    # S +- r_z and writes H d1 there.  The update pass reads H d1, H d2 on
+    # S +- r_z, reads g, dp, x and writes x, dp on the block slices, reads and
+    # writes q on S +- r_z, and writes H d' there (the next visit's H dp)
     A = 64 * 64 * 8
+    assert prof["dirs"][2] == ((2 * 16 + 2 * 28) + 2 * (16 + 2 * 28)) * A
+    assert prof["update"][2] == 3 * (2 * 28 + 5 * 16 + 2 * 28 + 28) * A
+    # without H dp kept every sweep blurs both directions
+    g.set_option(binding.OPT_HDP_EVERY, 0)
+    g.set_x0(None)
+    g.run(3, check_every=0)
+    prof = g.get_profile(reset=True)
     assert prof["dirs"][2] == 3 * (2 * 16 + 2 * 28) * A
     assert prof["update"][2] == 3 * (2 * 28 + 5 * 16 + 2 * 28) * A
     assert g.get_profile()["grad"][0] == 0

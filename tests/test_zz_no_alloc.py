@@ -1,9 +1,11 @@
 """bd3mg_run_noalloc, the entry point that allocates nothing (for callers that
 cannot allocate device memory), against bd3mg_run on the same problem.
 
-It runs the same kernels in the same order with its scratch buffers taken
-from the library's fixed per-device array, so iterates, previous steps, stop
-sweeps, f and ||grad f|| are expected bitwise equal to bd3mg_run's.  Two
+It runs the same kernels in the same order as bd3mg_run blurring both
+directions every sweep (BD3MG_OPT_HDP_EVERY = 0: the entry point keeps no
+H dp), with its scratch buffers taken from the library's fixed per-device
+array, so iterates, previous steps, stop sweeps, f and ||grad f|| are
+expected bitwise equal to that bd3mg_run's.  Two
 calls in a row on different problems, the second smaller, check that nothing
 left in the shared array by the first call is read by the second."""
 import numpy as np
@@ -25,6 +27,7 @@ def _twin(orc, shape, nsl, seed, kz, prec):
     for p in (a, b):
         p.get_schedule()  # builds the schedule (the entry point that allocates nothing needs it)
         p.set_x0(None)
+        p.set_option(binding.OPT_HDP_EVERY, 0)
     return a, b
 
 
