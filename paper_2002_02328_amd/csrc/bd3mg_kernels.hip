@@ -1024,14 +1024,17 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
             v[qq] = 0;
             bo[qq] = rg.off[qq] * (uint32_t)sizeof(T);
         }
-        // the tile's own elements of the region (not its halo), where a
-        // pair's H d' is stored for the next visit
-        bool own[rg.E];
+        // a round: the tile's own elements of the region (not its halo),
+        // where each pair's H d' is stored for the next visit (a colour has
+        // one pair, whose H d' is stored from the LDS tile below)
+        bool own[MULTI ? rg.E : 1];
+        if constexpr (MULTI) {
 #pragma unroll
-        for (int qq = 0; qq < rg.E; ++qq) {
-            const int e = threadIdx.x + qq * NT;
-            const int jj = e / W2, ii = e - jj * W2;
-            own[qq] = rg.inb[qq] && jj >= R && jj < R + TYK && ii >= R && ii < R + TX;
+            for (int qq = 0; qq < rg.E; ++qq) {
+                const int e = threadIdx.x + qq * NT;
+                const int jj = e / W2, ii = e - jj * W2;
+                own[qq] = rg.inb[qq] && jj >= R && jj < R + TYK && ii >= R && ii < R + TX;
+            }
         }
         // sources two at a time, so that the loads of both are in flight
         // together (a round has several per slice; a colour has one, and
@@ -1068,7 +1071,9 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
             for (int qq = 0; qq < rg.E; ++qq) {
                 const T w = c1 * ldbuf<T>(h1, bo[qq]) + c2 * ldbuf<T>(h2, bo[qq]);
                 v[qq] += w;
-                if (s.hdw && own[qq]) stbuf(buf_of(s.hdw + (size_t)pr.x * S, S), bo[qq], w);
+                if constexpr (MULTI) {
+                    if (s.hdw && own[qq]) stbuf(buf_of(s.hdw + (size_t)pr.x * S, S), bo[qq], w);
+                }
             }
         }
 #pragma unroll
@@ -1094,6 +1099,17 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
         }
     }
     __syncthreads();
+    if (!MULTI && s.hdw) {
+        // the pair's H d' on the tile (the next visit's H dp), from the LDS
+        // tile in rows of 64 lanes
+        const __amdgpu_buffer_rsrc_t ho = buf_of(s.hdw + (size_t)it.ps * S, S);
+#pragma unroll
+        for (int e = 0; e < NRK; ++e) {
+            const int j = y0 + out_row<NRK>(e), i = x0 + tx;
+            if (i >= g.nx || j >= g.ny) continue;
+            stbuf(ho, (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T), A[(out_row<NRK>(e) + R) * WS2 + tx + R]);
+        }
+    }
     xpass4<T, R, H2, true>(A, B, wx);
     __syncthreads();
     T v[NRK];
