@@ -21,10 +21,10 @@ MUTATIONS = {
                         "if (i >= 1) tv -= omega_at(p, x, k, j, i - 1) * dX(p, x, k, j, i - 1);"),
     "tv-adjoint-weight-index": ("if (j >= 1) tv += omega_at(p, x, k, j - 1, i) * dY(p, x, k, j - 1, i);",
                                 "if (j >= 1) tv += omega_at(p, x, k, j, i) * dY(p, x, k, j - 1, i);"),
-    "tv-curvature-drops-y": ("s += w * (dX(p, u, k, j, i) * dX(p, v, k, j, i) + dY(p, u, k, j, i) * dY(p, v, k, j, i));",
-                             "s += w * (dX(p, u, k, j, i) * dX(p, v, k, j, i));"),
-    "omega-delta-not-squared": ("return 1.0 / sqrt(gxv * gxv + gyv * gyv + p->delta * p->delta);",
-                                "return 1.0 / sqrt(gxv * gxv + gyv * gyv + p->delta);"),
+    "tv-curvature-drops-y": ("double d = dX(p, u, k, j, i) * dX(p, v, k, j, i) + dY(p, u, k, j, i) * dY(p, v, k, j, i);",
+                             "double d = dX(p, u, k, j, i) * dX(p, v, k, j, i);"),
+    "omega-delta-not-squared": ("return 1.0 / sqrt(gxv * gxv + gyv * gyv + gzv * gzv + p->delta * p->delta);",
+                                "return 1.0 / sqrt(gxv * gxv + gyv * gyv + gzv * gzv + p->delta);"),
     "blur-transposed": ("int sg = transpose ? 1 : -1;", "int sg = transpose ? -1 : 1;"),
     "adjoint-z-weight-of-output-slice": ("acc += p->gz[(size_t)m * p->kz + (c + rz)]",
                                          "acc += p->gz[(size_t)k * p->kz + (c + rz)]"),
@@ -40,7 +40,7 @@ MUTATIONS = {
                                   "            block_direction(p, x, dprev, z0, nslices[b], dn, NULL);\n"
                                   "            for (size_t q = (size_t)z0 * nslice(p); q < (size_t)(z0 + nslices[b]) * nslice(p); ++q)"
                                   " { x[q] += dn[q]; dprev[q] = dn[q]; dn[q] = 0.0; }\n"),
-    "lipschitz-tv-term": ("return hh + 2.0 * p->eta + 8.0 * p->lambda / p->delta",
+    "lipschitz-tv-term": ("return hh + 2.0 * p->eta + tvc * p->lambda / p->delta",
                           "return hh + 2.0 * p->eta + p->lambda / p->delta"),
     "dense-kernel-of-input-slice": ("double w = psf_w(p, k, c, b, a);", "double w = psf_w(p, kk, c, b, a);"),
     "dense-adjoint-kernel-of-output-slice": ("double w = psf_w(p, kk, c, b, a);", "double w = psf_w(p, k, c, b, a);"),
