@@ -299,9 +299,10 @@ def round_schedule(binding, w, args):
     snapshot; one gradient, direction, solve and update launch per sweep):
     sweep throughput and per-kernel device time with the paper's majorant
     (mu = 0, outside Assumption C: nothing guarantees descent), time to the
-    tolerance from x0 = y and from the warm start, and the run with the
-    curvature inflation mu = L (2 sqrt(tau) + 1), tau = B - 1, under which
-    Assumption C holds."""
+    tolerance from x0 = y, from the warm start and with the guard of the
+    rounds (f checked every 16 sweeps), and the run with the curvature
+    inflation mu = L (2 sqrt(tau) + 1), tau = B - 1, under which Assumption C
+    holds."""
     nvox = int(np.prod(w.shape))
     r = make_problem(binding, w)
     r.set_blocks(w.nslices, binding.SCHED_ROUND)
@@ -341,6 +342,15 @@ def round_schedule(binding, w, args):
             tt["warm_started"] = to_tol(net, args.tol, args.max_sweeps_to_tol)
             net.close()
         out["time_to_tol"] = tt
+        # the same run with the guard (f checked every 16 sweeps; a rise
+        # restores the last accepted state and raises mu)
+        r.set_option(binding.OPT_ROUND_GUARD, 16)
+        gd = to_tol(None, args.tol, args.max_sweeps_to_tol)
+        trips, mu_end = r.round_guard_info()
+        gd.update({"guard_every": 16, "restores": trips, "mu_end": mu_end})
+        tt["guarded"] = gd
+        r.set_option(binding.OPT_ROUND_GUARD, 0)
+        r.set_inflation(0.0)
         # Assumption C: inflation mu >= L (2 sqrt(tau) + 1) with tau = B - 1
         tau = len(w.nslices) - 1
         mu = L * (2.0 * np.sqrt(tau) + 1.0)

@@ -170,6 +170,11 @@ bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, doub
  * ERR_ARG: on not 0 or 1.  ERR_STATE: the method is Async-MM. */
 bd3mg_status bd3mg_set_tv3d(bd3mg_problem p, int on);
 
+/* Restores the last run's guard of the asynchronous rounds made
+ * (BD3MG_OPT_ROUND_GUARD), and the inflation mu now in use.  Either pointer
+ * may be NULL. */
+bd3mg_status bd3mg_round_guard_info(bd3mg_problem p, int *trips, double *mu);
+
 /* Curvature inflation (Sec. 2.5, Assumption C): every block step uses the
  * majorant A_S(x) + mu Id instead of A_S(x), for every schedule.  mu = 0
  * (the default) is the paper's majorant.  ERR_ARG: mu < 0 or not finite. */
@@ -365,7 +370,25 @@ typedef enum {
      * volumes of sum over blocks of |S +- r_z| slices, allocated at the first
      * run (without them, both directions are blurred).  Results differ from
      * n = 0 by rounding only. */
-    BD3MG_OPT_HDP_EVERY = 6
+    BD3MG_OPT_HDP_EVERY = 6,
+    /* Guard of the asynchronous rounds (BD3MG_SCHED_ROUND), m >= 1 sweeps
+     * (0, the default: none).  Rounds below the inflation of Assumption C
+     * (Sec. 2.5) are not guaranteed to converge.  With the guard, bd3mg_run
+     * evaluates f at its start and after every m sweeps (at the end of a
+     * run's chunk of sweeps); when f rose above the last accepted value by
+     * more than the storage precision's rounding (4e-9 relative in FP32,
+     * 1e-13 in FP64), x, every block's previous step and q go back to the
+     * last accepted state and the inflation mu is raised (doubled, at least
+     * L / 16, at most L (2 sqrt(tau) + 1) with L from bd3mg_lipschitz_bound
+     * and tau = nblocks - 1, where Assumption C holds); otherwise the state
+     * is accepted.  At the largest inflation every state is accepted.  The
+     * raised mu stays with the problem (bd3mg_round_guard_info,
+     * bd3mg_set_inflation).  res->sweeps counts every sweep run, discarded
+     * ones included; the state's sweep count (bd3mg_get_state) only those
+     * kept.  Costs three volumes, an evaluation of f (the blur of x and an
+     * evaluation pass) and a copy of the state every m sweeps.  Other
+     * schedules and bd3mg_run_noalloc ignore it. */
+    BD3MG_OPT_ROUND_GUARD = 7
 } bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
 

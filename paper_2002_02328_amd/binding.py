@@ -26,6 +26,7 @@ BATCH_AUTO, BATCH_FUSED, BATCH_BRANCHES = 0, 1, 2
 OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
 OPT_TILE_ROWS_DIRS, OPT_TILE_ROWS_UPDATE, OPT_TILE_ROWS_AUX, OPT_DIRS_SLICES = 2, 3, 4, 5
 OPT_HDP_EVERY = 6
+OPT_ROUND_GUARD = 7
 KERNEL_KINDS = ("grad", "dirs", "solve", "update", "eval")
 
 # Every function the header declares, with its C signature.
@@ -49,6 +50,7 @@ SIGNATURES = {
     "bd3mg_run_noalloc": ([_dp, _i, _d, _i, _dp], C.c_int),
     "bd3mg_set_method": ([_dp, _i, _d, _i, _d], C.c_int),
     "bd3mg_set_tv3d": ([_dp, _i], C.c_int),
+    "bd3mg_round_guard_info": ([_dp, C.POINTER(C.c_int), C.POINTER(C.c_double)], C.c_int),
     "bd3mg_batch_set_mode": ([_dp, _i, _dp], C.c_int),
     "bd3mg_get_x": ([_dp, _dp, _i], C.c_int),
     "bd3mg_get_dprev": ([_dp, _dp, _i], C.c_int),
@@ -226,6 +228,12 @@ class Problem:
         """Total variation over (V^X, V^Y, V^Z) inside the root instead of the
         slices' (V^X, V^Y); kappa ||V^Z x||^2 stays a term of its own."""
         _check(load().bd3mg_set_tv3d(self._h, int(on)))
+
+    def round_guard_info(self):
+        """(restores by the last run's guard of the rounds, inflation mu now)."""
+        t, mu = C.c_int(), C.c_double()
+        _check(load().bd3mg_round_guard_info(self._h, C.byref(t), C.byref(mu)))
+        return t.value, mu.value
 
     def set_inflation(self, mu):
         _check(load().bd3mg_set_inflation(self._h, float(mu)))

@@ -69,6 +69,11 @@ struct bd3mg_problem_s {
     // volumes (storage type); q is the in-slice adjoint-blurred residual
     void *x = nullptr, *y = nullptr, *q = nullptr, *g = nullptr, *dpb[2] = {nullptr, nullptr};
     void *tmp[4] = {nullptr, nullptr, nullptr, nullptr};  // tmp[3]: H^T r of the dense mode
+    // guard of the round schedule: f checked every round_guard sweeps, the last
+    // accepted state (x, previous steps, q) kept in gsave
+    long long round_guard = 0;
+    void *gsave[3] = {nullptr, nullptr, nullptr};
+    int guard_trips = 0;  // restores of the last run
     int cur = 0;  // dpb[cur] holds every block's last step
     bool data_set = false, x_set = false, q_stale = true;
 
@@ -1005,6 +1010,39 @@ bd3mg_status ensure_ready_noalloc(bd3mg_problem p)
     return BD3MG_OK;
 }
 
+// Guard of the asynchronous rounds: the accepted state (x, every block's
+// previous step, q) is copied to gsave, and back on a restore.
+bd3mg_status guard_copy(bd3mg_problem p, bool save)
+{
+    for (int i = 0; i < 3; ++i)
+        if (!p->gsave[i] && hipMalloc(&p->gsave[i], p->N * p->esz) != hipSuccess)
+            return fail(BD3MG_ERR_NOMEM, "guard state volume of %zu bytes", p->N * p->esz);
+    void *live[3] = {p->x, p->dpb[p->cur], p->q};
+    for (int i = 0; i < 3; ++i)
+        HIP_TRY(hipMemcpyAsync(save ? p->gsave[i] : live[i], save ? live[i] : p->gsave[i], p->N * p->esz,
+                               hipMemcpyDeviceToDevice, p->stream));
+    return BD3MG_OK;
+}
+
+// Inflation after the guard saw f increase: doubled, at least L / 16, at
+// most the value mu = L (2 sqrt(tau) + 1), tau = nblocks - 1, under which
+// Assumption C holds whatever the point.
+bd3mg_status guard_raise(bd3mg_problem p)
+{
+    double L = 0.0;
+    ST_TRY(bd3mg_lipschitz_bound(p, &L));
+    const double cap = L * (2.0 * std::sqrt((double)p->nsl.size() - 1.0) + 1.0);
+    p->prm.mu = std::min(cap, std::max(2.0 * p->prm.mu, L / 16.0));
+    return BD3MG_OK;
+}
+
+double guard_cap(bd3mg_problem p)
+{
+    double L = 0.0;
+    if (bd3mg_lipschitz_bound(p, &L) != BD3MG_OK) return 0.0;
+    return L * (2.0 * std::sqrt((double)p->nsl.size() - 1.0) + 1.0);
+}
+
 // The run loop of bd3mg_run and bd3mg_run_noalloc.  noalloc: the set-up is
 // done in place (no scratch volume is taken), a stop is confirmed on q
 // rebuilt in place from x, and f at the end is formed in g (not read again
@@ -1034,6 +1072,20 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
     const long long sweeps0 = p->sweeps_done;
     int done = max_sweeps;
     bool conv = false;
+    // Guard of the asynchronous rounds (BD3MG_OPT_ROUND_GUARD): every
+    // round_guard sweeps f is evaluated; when it rose above the last accepted
+    // value the state goes back to the accepted one and the inflation is
+    // raised.  lost counts the sweeps run and then discarded, so the state's
+    // own sweep count is s - lost.
+    const bool guard = !noalloc && p->schedule == BD3MG_SCHED_ROUND && p->round_guard > 0;
+    const double slack = p->prec == BD3MG_FP32 ? 4e-9 : 1e-13;
+    int lost = 0, s_acc = 0, g_cur = p->cur;
+    double f_acc = 0.0;
+    p->guard_trips = 0;
+    if (guard) {
+        ST_TRY(eval_at(p, p->x, p->q, &f_acc, nullptr));
+        ST_TRY(guard_copy(p, true));
+    }
     bd3mg_problem_s::Ctl ctl{0, 0, NAN};
     // adaptive checks: the last two checks (sweep, ||grad f||)
     int sa = -1, sb = -1;
@@ -1090,7 +1142,7 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
                 // if the rebuilt gradient is still above the threshold, take
                 // the rebuilt residual as q and continue from the stop sweep.
                 const int ss = ctl.stop_sweep;
-                p->cur = cur0 ^ (ss & 1);
+                p->cur = cur0 ^ ((ss - lost) & 1);
                 double gfresh = 0.0;
                 void *qf = p->q;  // rebuilt in place when nothing may be allocated
                 if (!noalloc) {
@@ -1118,10 +1170,32 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
                 gb = ctl.gnorm;
             }
         }
+        if (guard && s - s_acc >= p->round_guard) {
+            double fs = 0.0;
+            ST_TRY(eval_at(p, p->x, p->q, &fs, nullptr));
+            if (fs <= f_acc + slack * std::fabs(f_acc) || p->prm.mu >= guard_cap(p)) {
+                ST_TRY(guard_copy(p, true));
+                f_acc = fs;
+                s_acc = s;
+                g_cur = p->cur;
+            } else {
+                // back to the accepted state, with more curvature
+                p->cur = g_cur;
+                ST_TRY(guard_copy(p, false));
+                lost += s - s_acc;
+                s_acc = s;
+                p->hdp_valid = false;
+                ST_TRY(guard_raise(p));
+                ++p->guard_trips;
+                sa = sb = -1;
+                HIP_TRY(hipMemsetAsync(p->d_ctl, 0, sizeof(bd3mg_problem_s::Ctl), p->stream));
+                ctl = bd3mg_problem_s::Ctl{0, 0, NAN};
+            }
+        }
         if (p->pending.size() > 4096) ST_TRY(prof_collect(p));
     }
-    p->cur = cur0 ^ (done & 1);
-    p->sweeps_done = sweeps0 + done;
+    p->cur = cur0 ^ ((done - lost) & 1);
+    p->sweeps_done = sweeps0 + done - lost;
     HIP_TRY(hipEventRecord(p->ev1, p->stream));
     double gn = ctl.gnorm, f = NAN;
     if (checking) {
@@ -1258,7 +1332,7 @@ bd3mg_status bd3mg_destroy(bd3mg_problem p)
                     p->d_pk, p->d_ones, p->d_hts,
                     p->d_gx, p->d_gy, p->d_gz, p->d_items, p->d_br, p->d_vol, p->d_sblk, p->d_pg, p->d_pd,
                     p->d_pe, p->d_pr, p->d_u, p->d_info, p->d_sum, p->d_ctl, p->d_pairs, p->d_hd,
-                    p->d_units, p->d_hdp};
+                    p->d_units, p->d_hdp, p->gsave[0], p->gsave[1], p->gsave[2]};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     void *mm[] = {p->mmv[0], p->mmv[1], p->mmv[2], p->mmv[3], p->mmv[4], p->d_pma, p->d_prr, p->d_cgs,
@@ -1353,6 +1427,14 @@ bd3mg_status bd3mg_set_params(bd3mg_problem p, double lambda, double delta, doub
     p->prm = Params{lambda, delta, eta, kappa, xmin, xmax, p->prm.mu, p->prm.method, p->prm.lip, p->prm.tv3d};
     p->gnorm_ref_valid = false;
     if (kappa_changed) p->sched_dirty = true;
+    return BD3MG_OK;
+}
+
+bd3mg_status bd3mg_round_guard_info(bd3mg_problem p, int *trips, double *mu)
+{
+    ST_TRY(validate_handle(p));
+    if (trips) *trips = p->guard_trips;
+    if (mu) *mu = p->prm.mu;
     return BD3MG_OK;
 }
 
@@ -1684,6 +1766,10 @@ bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value)
     case BD3MG_OPT_PROFILE:
         ST_TRY(prof_collect(p));
         p->profile = value != 0;
+        return BD3MG_OK;
+    case BD3MG_OPT_ROUND_GUARD:
+        if (value < 0) return fail(BD3MG_ERR_ARG, "guard interval < 0");
+        p->round_guard = value;
         return BD3MG_OK;
     case BD3MG_OPT_HDP_EVERY:
         if (value < 0) return fail(BD3MG_ERR_ARG, "H dp interval < 0");

@@ -153,3 +153,45 @@ def test_direction_slices_per_workgroup_bitwise(orc, schedule, prec, kz):
             nc, order, color = g.get_schedule()
             o.run(x, d, nslices, order, 6, history=False)
         assert rel(runs[1][0], x) <= 1e-9
+
+
+def test_guard_restores_and_raises_the_inflation(orc):
+    """The divergent case above (thin blocks, wide z blur, mu = 0) with the
+    guard every 4 sweeps: the guard restores the last accepted state at
+    least once and raises mu within (0, L (2 sqrt(tau) + 1)]; f after every
+    guarded call is at most f before it (up to the guard's FP64 slack); the
+    run ends below f(y); discarded sweeps are counted in the call's sweeps
+    but not in the state's sweep count."""
+    nslices = [2] * 8
+    g, o, y = setup((16, 24, 24), 5, binding.FP64, 3, 7, nslices, binding.SCHED_ROUND)
+    f0 = o.f(y)
+    g.set_option(binding.OPT_ROUND_GUARD, 4)
+    prev, trips_total = f0, 0
+    for _ in range(10):
+        r = g.run(8)
+        trips, mu = g.round_guard_info()
+        trips_total += trips
+        assert r["sweeps"] == 8
+        assert r["f"] <= prev * (1 + 1e-13)
+        prev = r["f"]
+    L = g.lipschitz_bound()
+    print("guard: %d restores, mu = %.4g (cap %.4g), f %.6g -> %.6g, state sweeps %d of 80"
+          % (trips_total, mu, L * (2 * np.sqrt(7) + 1), f0, prev, g.get_state()[3]))
+    assert trips_total >= 1
+    assert 0 < mu <= L * (2 * np.sqrt(len(nslices) - 1) + 1) * (1 + 1e-12)
+    assert prev < f0
+    assert g.get_state()[3] < 80
+
+
+def test_guard_leaves_a_converging_round_unchanged(orc):
+    """Where the rounds descend, the guard accepts every check: the iterate
+    is bitwise that of the unguarded run and mu is untouched."""
+    out = []
+    for m in (0, 4):
+        g, o, y = setup((9, 21, 70), 21, binding.FP32, 5, 7, [1, 3, 2, 3], binding.SCHED_ROUND, mu=0.3)
+        g.set_option(binding.OPT_ROUND_GUARD, m)
+        r = g.run(24, check_every=0)
+        trips, mu = g.round_guard_info()
+        assert trips == 0 and mu == 0.3 and r["sweeps"] == 24 and g.get_state()[3] == 24
+        out.append((g.get_x(), g.get_dprev()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
