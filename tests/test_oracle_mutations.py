@@ -7,6 +7,7 @@ and runs the pin suite against it in a subprocess: the suite has to fail.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -93,19 +94,44 @@ def _cases():
            [(NET_SRC, n, NET_MUTATIONS[n]) for n in sorted(NET_MUTATIONS)]
 
 
-@pytest.mark.parametrize("path,name,edit", _cases(), ids=[c[1] for c in _cases()])
-def test_pins_catch_planted_mistake(path, name, edit, tmp_path):
+def _run_case(path, name, edit, work):
+    """Build the oracle with one planted mistake and run its pins; returns
+    (pins' exit status, the tail of their output), or None when the pattern
+    does not occur exactly once."""
     old, new = edit
     src = open(path).read()
-    assert src.count(old) == 1, name
-    mut = tmp_path / "mut.c"
-    mut.write_text(src.replace(old, new))
+    if src.count(old) != 1:
+        return None
+    d = os.path.join(work, name)
+    os.makedirs(d)
+    mut = os.path.join(d, "mut.c")
+    with open(mut, "w") as fh:
+        fh.write(src.replace(old, new))
     others = [s for s in PIN_FILES if s != path]
-    lib = tmp_path / "libmut.so"
+    lib = os.path.join(d, "libmut.so")
     subprocess.run(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                    "-o", str(lib), str(mut)] + others + ["-lm"], check=True)
-    env = dict(os.environ, ORACLE_LIB=str(lib), OMP_NUM_THREADS="2")
+                    "-o", lib, mut] + others + ["-lm"], check=True)
+    env = dict(os.environ, ORACLE_LIB=lib, OMP_NUM_THREADS="1")
     res = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"] +
                          [os.path.join(ROOT, "tests", f) for f in PIN_FILES[path]],
-                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
-    assert res.returncode != 0, "pins did not catch mutation %s\n%s" % (name, res.stdout[-2000:])
+                         cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
+    return res.returncode, res.stdout[-2000:]
+
+
+@pytest.fixture(scope="module")
+def outcomes(tmp_path_factory):
+    """Every case at once, a few processes at a time (the pins of one case
+    run single-threaded), so the module takes minutes rather than the sum."""
+    work = str(tmp_path_factory.mktemp("mutations"))
+    workers = max(1, min(6, (os.cpu_count() or 2) - 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = {c[1]: ex.submit(_run_case, c[0], c[1], c[2], work) for c in _cases()}
+        return {n: f.result() for n, f in futs.items()}
+
+
+@pytest.mark.parametrize("path,name,edit", _cases(), ids=[c[1] for c in _cases()])
+def test_pins_catch_planted_mistake(path, name, edit, outcomes):
+    out = outcomes[name]
+    assert out is not None, "pattern of %s does not occur exactly once" % name
+    rc, tail = out
+    assert rc != 0, "pins did not catch mutation %s\n%s" % (name, tail)
