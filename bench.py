@@ -135,7 +135,7 @@ def kernel_variant(w, kernel, tile_rows):
         return {"grad": "k_dense<%s, %d, 1, true, %d>" % (t, r, ty), "dirs": "k_dense<%s, %d, 2, false, %d>" % (t, r, ty),
                 "solve": "k_solve", "update": "k_dense_update<%s>" % t}[kernel]
     # the direction pass blurs d1 only (H dp kept) on all sweeps but one in 64
-    return {"grad": "k_grad<%s, %d, false>" % (t, kz),
+    return {"grad": "k_grad<%s, %d, false, true>" % (t, kz),
             "dirs": "k_dirs<%s, %d, %d, %d, true>" % (t, kz, r, tile_rows["dirs"]),
             "solve": "k_solve",
             "update": "k_update<%s, %d, %d, false>" % (t, r, tile_rows["update"])}[kernel]

@@ -351,12 +351,15 @@ __device__ __forceinline__ size_t slot_of(const VB &v)
 // GM_EVAL sums ||g||^2 and the TV, box and z terms of f; GM_ZCOMB writes only
 // the z-stencil of q to out.
 // ---------------------------------------------------------------------------
-template <typename T, int KZ, bool TV3 = false>
+// BLK: the sweep's mode GM_BLOCK fixed at compile time (its instance carries
+// no code of the other modes and no copies of their sums); otherwise mode_in.
+template <typename T, int KZ, bool TV3, bool BLK>
 __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevState<T> s, const T *__restrict__ q,
                                           const T *__restrict__ x, T *__restrict__ out,
-                                          const Item *__restrict__ items, int mode, double *__restrict__ partials,
-                                          int nshare)
+                                          const Item *__restrict__ items, int mode_in,
+                                          double *__restrict__ partials, int nshare)
 {
+    const int mode = BLK ? (int)GM_BLOCK : mode_in;
     constexpr int RZ = KZ / 2;
     constexpr int XW = TX + 3, XH = TY + 3;  // x at (y0-1+jj, x0-1+ii)
     constexpr int PW = TX + 2, PH = TY + 2;  // w VX x, w VY x, w at (y0-1+jj, x0-1+ii)
@@ -608,13 +611,13 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     }
 }
 
-template <typename T, int KZ, bool TV3>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
+template <typename T, int KZ, bool TV3, bool BLK>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BLK ? 4 : 5)))
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
        int nshare)
 {
-    grad_body<T, KZ, TV3>(vb_native(), g, prm, s, q, x, out, items, mode, partials, nshare);
+    grad_body<T, KZ, TV3, BLK>(vb_native(), g, prm, s, q, x, out, items, mode, partials, nshare);
 }
 
 // ---------------------------------------------------------------------------
@@ -1840,7 +1843,7 @@ k_grad_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restric
     VB vb;
     if (!fused_part(fa, owner, &p, &vb)) return;
     const FusedArgs<T> &a = fa[p];
-    grad_body<T, KZ>(vb, a.g, a.prm, a.s, a.s.q, a.s.x, nullptr, a.items, GM_BLOCK, a.pg, 0);
+    grad_body<T, KZ, false, true>(vb, a.g, a.prm, a.s, a.s.q, a.s.x, nullptr, a.items, GM_BLOCK, a.pg, 0);
 }
 
 template <typename T, int KZ, int R, int TYK>
@@ -1962,15 +1965,24 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
 {
     if (nitems <= 0) return hipSuccess;
     if (nshare > 0 && g.rz != 0) return hipErrorInvalidValue;
+#define BD3MG_GRAD_LAUNCH(TV, BL)                                                                  \
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_LAUNCH((k_grad<T, KZ, TV, BL>), grid_of(g, nitems), dim3(NT), 0, st, \
+                                               g, prm, s, q, x, out, items, mode, partials, nshare))
+    const bool blk = mode == GM_BLOCK;
     if (prm.tv3d) {
-        BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                        BD3MG_LAUNCH((k_grad<T, KZ, true>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
-                                           s, q, x, out, items, mode, partials, nshare));
+        if (blk) {
+            BD3MG_GRAD_LAUNCH(true, true);
+        } else {
+            BD3MG_GRAD_LAUNCH(true, false);
+        }
     } else {
-        BD3MG_KZ_SWITCH(2 * g.rz + 1,
-                        BD3MG_LAUNCH((k_grad<T, KZ, false>), grid_of(g, nitems), dim3(NT), 0, st, g, prm,
-                                           s, q, x, out, items, mode, partials, nshare));
+        if (blk) {
+            BD3MG_GRAD_LAUNCH(false, true);
+        } else {
+            BD3MG_GRAD_LAUNCH(false, false);
+        }
     }
+#undef BD3MG_GRAD_LAUNCH
     return hipGetLastError();
 }
 
