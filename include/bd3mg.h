@@ -365,7 +365,7 @@ typedef enum {
      * pass then blurs d1 = -grad only; every n-th sweep blurs both directions
      * again, bounding the rounding the recurrence carries (n = 1: always).
      * 0: both directions every sweep, nothing kept.  Applies to bd3mg_run
-     * with the separable PSF and a method other than Async-MM; batches,
+     * and batches with the separable PSF and a method other than Async-MM;
      * bd3mg_run_noalloc and bd3mg_block_step blur both directions.  Costs two
      * volumes of sum over blocks of |S +- r_z| slices, allocated at the first
      * run (without them, both directions are blurred).  Results differ from
@@ -441,8 +441,8 @@ bd3mg_status bd3mg_probe_copy(size_t bytes, int iters, double *gbps, double *ms)
  * once for all problems, its grid the concatenation of every problem's
  * work list (each problem as many workgroups as its own launch would have),
  * so a sweep of the whole batch is 4 x (most colours) launches; results are
- * bitwise those of the problems run one by one with BD3MG_OPT_HDP_EVERY = 0
- * (batch sweeps blur both directions and keep no H dp).  Branch mode (or a batch
+ * bitwise those of the problems run one by one (each problem's direction
+ * pass keeps H dp, or not, on the same sweeps as its single run).  Branch mode (or a batch
  * that cannot be fused): each problem's sweep is captured on its own stream
  * into the graph (fork/join), problems as parallel branches.
  * ------------------------------------------------------------------------- */

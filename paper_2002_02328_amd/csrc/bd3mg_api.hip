@@ -741,10 +741,22 @@ bd3mg_status ensure_hdp(bd3mg_problem p)
 // rounding the recurrence H dp' = u1 H d1 + u2 H dp carries does not build
 // up; the choice depends on the sweep count only, so runs split into several
 // calls, or checked at other sweeps, take the same modes.
-int hdp_mode(bd3mg_problem p, bool noalloc, long long sw)
+int hdp_mode(bd3mg_problem p, bool noalloc, long long sw, bool valid)
 {
     if (noalloc || p->dense || p->prm.method == M_MM || p->hdp_every <= 0 || !p->d_hdp) return 0;
-    return (p->hdp_valid && sw % p->hdp_every != 0) ? 2 : 1;
+    return (valid && sw % p->hdp_every != 0) ? 2 : 1;
+}
+
+// H d2 of a colour group's items in the H dp buffer of this sweep (the parity
+// of cur) and the update's H d' into the other one, for modes 1 and 2.
+template <typename T>
+void hdp_state(bd3mg_problem p, DevState<T> &s, const bd3mg_problem_s::Group &gr, int mode)
+{
+    if (!mode) return;
+    const size_t S = (size_t)p->nx * p->ny, span = p->hdp_slots * S;
+    T *hb = (T *)p->d_hdp;
+    s.hd[1] = hb + p->cur * span + (size_t)gr.dbase * S;
+    s.hdw = hb + (p->cur ^ 1) * span + (size_t)gr.dbase * S;
 }
 
 bd3mg_status ensure_ready(bd3mg_problem p)
@@ -781,15 +793,9 @@ bd3mg_status phase_t(bd3mg_problem p, const bd3mg_problem_s::Group &gr, bool pro
 {
     DevState<T> s = dev_state<T>(p);
     s.stop = stop;
-    if (hdp) {
-        // H d2 of the group's items (H dp, or blurred and stored by the
-        // direction pass) in the buffer of this sweep, the pairs' H d' into
-        // the other one
-        const size_t S = (size_t)p->nx * p->ny, span = p->hdp_slots * S;
-        T *hb = (T *)p->d_hdp;
-        s.hd[1] = hb + p->cur * span + (size_t)gr.dbase * S;
-        s.hdw = hb + (p->cur ^ 1) * span + (size_t)gr.dbase * S;
-    }
+    // H d2 of the group's items (H dp, or blurred and stored by the direction
+    // pass) in the buffer of this sweep, the pairs' H d' into the other one
+    hdp_state<T>(p, s, gr, hdp);
     const Item *it = p->d_items;
     if (p->dense) {
         // general kernels: H^T r and grad f on S, H d1 and H d2 on S +- r_z by
@@ -1112,7 +1118,7 @@ bd3mg_status run_impl(bd3mg_problem p, int max_sweeps, double grad_rtol, int che
             }
         }
         for (; s < end; ++s) {
-            const int hm = hdp_mode(p, noalloc, sweeps0 + s);
+            const int hm = hdp_mode(p, noalloc, sweeps0 + s, p->hdp_valid);
             for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], p->profile, stop, hm));
             p->hdp_valid = hm != 0;
             p->cur ^= 1;
@@ -1974,35 +1980,67 @@ struct bd3mg_batch_s {
     hipStream_t s0 = nullptr;
     hipEvent_t fork = nullptr, ev0 = nullptr, ev1 = nullptr;
     std::vector<hipEvent_t> join;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    std::vector<char> captured;  // problems in the graph
-    std::vector<int> cap_cur;    // their previous-step buffer at capture
+    // Graphs of two sweeps, kept for the states they were captured in: per
+    // problem -1 when inactive, else its previous-step buffer (cur) and the
+    // direction-pass modes of the two sweeps (H dp kept or not).  A batch
+    // whose problems advance together needs two: the pair that blurs both
+    // directions again and the others.
+    struct Graph {
+        std::vector<int> key;
+        bool fused = false;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        // fused launches: the per-problem argument sets and owner tables of
+        // every (sweep of two, colour index, pass)
+        void *d_fa = nullptr;
+        unsigned char *d_owner = nullptr;
+        unsigned long long used = 0;
+    };
+    std::vector<Graph> graphs;
+    unsigned long long tick = 0;
     int mode = BD3MG_BATCH_AUTO;
-    bool cap_fused = false;      // the graph holds fused launches
-    // fused launches: the per-problem argument sets and owner tables of
-    // every (sweep of two, colour index, pass)
-    void *d_fa = nullptr;
-    size_t fa_cap = 0;
-    unsigned char *d_owner = nullptr;
-    size_t owner_cap = 0;
 };
 
 namespace {
 
+void graph_free(bd3mg_batch_s::Graph &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.d_fa) (void)hipFree(g.d_fa);
+    if (g.d_owner) (void)hipFree(g.d_owner);
+    g = bd3mg_batch_s::Graph{};
+}
+
 void batch_drop_graph(bd3mg_batch b)
 {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+    for (auto &g : b->graphs) graph_free(g);
+    b->graphs.clear();
+}
+
+// Direction-pass modes of a problem's next two sweeps (see hdp_mode).
+void pair_modes(bd3mg_problem p, int m[2])
+{
+    m[0] = hdp_mode(p, false, p->sweeps_done, p->hdp_valid);
+    m[1] = hdp_mode(p, false, p->sweeps_done + 1, m[0] != 0);
+}
+
+std::vector<int> graph_key(bd3mg_batch b, const std::vector<char> &active)
+{
+    std::vector<int> key(b->probs.size(), -1);
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+        if (!active[i]) continue;
+        int m[2];
+        pair_modes(b->probs[i], m);
+        key[i] = b->probs[i]->cur | (m[0] << 1) | (m[1] << 3);
+    }
+    return key;
 }
 
 // Capture two sweeps of every active problem, each problem on its own stream
 // between a fork and a join event of the batch stream, into one graph.
-bd3mg_status batch_capture(bd3mg_batch b, const std::vector<char> &active)
+bd3mg_status batch_capture(bd3mg_batch b, const std::vector<char> &active, bd3mg_batch_s::Graph &out)
 {
-    batch_drop_graph(b);
     HIP_TRY(hipStreamBeginCapture(b->s0, hipStreamCaptureModeRelaxed));
     bd3mg_status st = BD3MG_OK;
     if (hipEventRecord(b->fork, b->s0) != hipSuccess) st = fail(BD3MG_ERR_HIP, "fork record failed");
@@ -2013,8 +2051,11 @@ bd3mg_status batch_capture(bd3mg_batch b, const std::vector<char> &active)
             st = fail(BD3MG_ERR_HIP, "fork wait failed");
             break;
         }
+        int m[2];
+        pair_modes(p, m);
         for (int sw = 0; sw < 2 && st == BD3MG_OK; ++sw) {
-            for (int c = 0; c < p->ncolors && st == BD3MG_OK; ++c) st = phase(p, p->groups[c], false);
+            for (int c = 0; c < p->ncolors && st == BD3MG_OK; ++c)
+                st = phase(p, p->groups[c], false, nullptr, m[sw]);
             p->cur ^= 1;
         }
         if (st == BD3MG_OK && (hipEventRecord(b->join[i], p->stream) != hipSuccess ||
@@ -2028,10 +2069,9 @@ bd3mg_status batch_capture(bd3mg_batch b, const std::vector<char> &active)
         return st;
     }
     if (e != hipSuccess) return fail(BD3MG_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
-    b->graph = g;
-    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    b->captured = active;
-    for (size_t i = 0; i < b->probs.size(); ++i) b->cap_cur[i] = b->probs[i]->cur;
+    out.graph = g;
+    HIP_TRY(hipGraphInstantiate(&out.exec, out.graph, nullptr, nullptr, 0));
+    out.fused = false;
     return BD3MG_OK;
 }
 
@@ -2067,29 +2107,39 @@ bool batch_uses_fused(bd3mg_batch b)
 // stream: for each sweep, colour index and pass, one launch whose grid holds
 // the workgroups of that pass of every active problem with that colour.
 template <typename T>
-bd3mg_status batch_capture_fused_t(bd3mg_batch b, const std::vector<char> &active)
+bd3mg_status batch_capture_fused_t(bd3mg_batch b, const std::vector<char> &active, bd3mg_batch_s::Graph &out)
 {
     const int n = (int)b->probs.size();
     int maxc = 0;
+    std::vector<int> modes(2 * n, 0);
     for (int i = 0; i < n; ++i)
-        if (active[i]) maxc = std::max(maxc, b->probs[i]->ncolors);
+        if (active[i]) {
+            maxc = std::max(maxc, b->probs[i]->ncolors);
+            pair_modes(b->probs[i], &modes[2 * i]);
+        }
     struct Set {
         size_t fa0, ow0;
         unsigned nwg;
         int pass;
+        bool one;
     };
     std::vector<Set> sets;
     std::vector<FusedArgs<T>> fa;
     std::vector<unsigned char> owner;
+    // the direction pass runs in two launches when some problems blur d1 only
+    // (H dp kept) and others both directions in the same sweep
     for (int sw = 0; sw < 2; ++sw)
         for (int c = 0; c < maxc; ++c)
-            for (int pass = FP_GRAD; pass <= FP_UPDATE; ++pass) {
-                Set st{fa.size(), owner.size(), 0, pass};
+            for (int pass = FP_GRAD; pass <= FP_UPDATE; ++pass)
+                for (int one = 0; one < (pass == FP_DIRS ? 2 : 1); ++one) {
+                Set st{fa.size(), owner.size(), 0, pass, one != 0};
                 unsigned wg = 0;
                 int local = 0;
                 for (int i = 0; i < n; ++i) {
                     bd3mg_problem p = b->probs[i];
                     if (!active[i] || c >= p->ncolors) continue;
+                    const int hm = modes[2 * i + sw];
+                    if (pass == FP_DIRS && (hm == 2) != (one != 0)) continue;
                     const auto &gr = p->groups[c];
                     const int cur = p->cur;
                     p->cur = cur ^ sw;  // the previous-step buffers of this sweep
@@ -2097,6 +2147,7 @@ bd3mg_status batch_capture_fused_t(bd3mg_batch b, const std::vector<char> &activ
                     a.g = p->geom;
                     a.prm = p->prm;
                     a.s = dev_state<T>(p);
+                    hdp_state<T>(p, a.s, gr, hm);
                     p->cur = cur;
                     a.pg = p->d_pg;
                     a.pd = p->d_pd;
@@ -2132,24 +2183,23 @@ bd3mg_status batch_capture_fused_t(bd3mg_batch b, const std::vector<char> &activ
                     ++local;
                 }
                 st.nwg = wg;
-                sets.push_back(st);
-            }
+                if (wg > 0) sets.push_back(st);
+                }
     if (fa.empty()) return fail(BD3MG_ERR_STATE, "no active problem in the batch");
-    ST_TRY(realloc_dev(&b->d_fa, &b->fa_cap, fa.size() * sizeof(FusedArgs<T>), "fused launch arguments"));
-    ST_TRY(realloc_dev((void **)&b->d_owner, &b->owner_cap, std::max<size_t>(owner.size(), 1),
-                       "fused launch owners"));
-    HIP_TRY(hipMemcpy(b->d_fa, fa.data(), fa.size() * sizeof(FusedArgs<T>), hipMemcpyHostToDevice));
-    if (!owner.empty()) HIP_TRY(hipMemcpy(b->d_owner, owner.data(), owner.size(), hipMemcpyHostToDevice));
+    if (hipMalloc(&out.d_fa, fa.size() * sizeof(FusedArgs<T>)) != hipSuccess ||
+        hipMalloc((void **)&out.d_owner, std::max<size_t>(owner.size(), 1)) != hipSuccess)
+        return fail(BD3MG_ERR_NOMEM, "fused launch arguments");
+    HIP_TRY(hipMemcpy(out.d_fa, fa.data(), fa.size() * sizeof(FusedArgs<T>), hipMemcpyHostToDevice));
+    if (!owner.empty()) HIP_TRY(hipMemcpy(out.d_owner, owner.data(), owner.size(), hipMemcpyHostToDevice));
     // the problems' earlier work (set-up, checks) is complete before the graph runs
     for (bd3mg_problem p : b->probs) HIP_TRY(hipStreamSynchronize(p->stream));
-    batch_drop_graph(b);
     const Geom &g0 = b->probs[0]->geom;
     HIP_TRY(hipStreamBeginCapture(b->s0, hipStreamCaptureModeRelaxed));
     hipError_t e = hipSuccess;
     for (const Set &st : sets) {
         if (e != hipSuccess) break;
-        e = launch_fused<T>(st.pass, g0, (const FusedArgs<T> *)b->d_fa + st.fa0, b->d_owner + st.ow0, st.nwg,
-                            b->s0);
+        e = launch_fused<T>(st.pass, g0, (const FusedArgs<T> *)out.d_fa + st.fa0, out.d_owner + st.ow0, st.nwg,
+                            b->s0, st.one);
     }
     hipGraph_t gph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->s0, &gph);
@@ -2157,21 +2207,46 @@ bd3mg_status batch_capture_fused_t(bd3mg_batch b, const std::vector<char> &activ
         if (gph) (void)hipGraphDestroy(gph);
         return fail(BD3MG_ERR_HIP, "fused graph capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
     }
-    b->graph = gph;
-    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-    b->captured = active;
-    for (int i = 0; i < n; ++i) b->cap_cur[i] = b->probs[i]->cur;
-    b->cap_fused = true;
+    out.graph = gph;
+    HIP_TRY(hipGraphInstantiate(&out.exec, out.graph, nullptr, nullptr, 0));
+    out.fused = true;
     return BD3MG_OK;
 }
 
-bd3mg_status batch_capture_any(bd3mg_batch b, const std::vector<char> &active)
+// The graph of the batch's next two sweeps in its current state: a kept one,
+// or captured now (the least recently used of four dropped to make room).
+bd3mg_status batch_graph(bd3mg_batch b, const std::vector<char> &active, hipGraphExec_t *exec)
 {
+    const std::vector<int> key = graph_key(b, active);
+    for (auto &g : b->graphs)
+        if (g.key == key) {
+            g.used = ++b->tick;
+            *exec = g.exec;
+            return BD3MG_OK;
+        }
+    if (b->graphs.size() >= 4) {
+        size_t lru = 0;
+        for (size_t i = 1; i < b->graphs.size(); ++i)
+            if (b->graphs[i].used < b->graphs[lru].used) lru = i;
+        graph_free(b->graphs[lru]);
+        b->graphs.erase(b->graphs.begin() + (long)lru);
+    }
+    bd3mg_batch_s::Graph g;
+    bd3mg_status st;
     if (batch_uses_fused(b))
-        return b->probs[0]->prec == BD3MG_FP64 ? batch_capture_fused_t<double>(b, active)
-                                               : batch_capture_fused_t<float>(b, active);
-    b->cap_fused = false;
-    return batch_capture(b, active);
+        st = b->probs[0]->prec == BD3MG_FP64 ? batch_capture_fused_t<double>(b, active, g)
+                                             : batch_capture_fused_t<float>(b, active, g);
+    else
+        st = batch_capture(b, active, g);
+    if (st != BD3MG_OK) {
+        graph_free(g);
+        return st;
+    }
+    g.key = key;
+    g.used = ++b->tick;
+    b->graphs.push_back(g);
+    *exec = g.exec;
+    return BD3MG_OK;
 }
 
 }  // namespace
@@ -2204,8 +2279,6 @@ bd3mg_status bd3mg_batch_create(int n, const bd3mg_problem *probs, bd3mg_batch *
     if (!b) return fail(BD3MG_ERR_NOMEM, "batch handle");
     b->probs.assign(probs, probs + n);
     b->join.assign(n, nullptr);
-    b->captured.assign(n, 0);
-    b->cap_cur.assign(n, -1);
     bool ok = hipStreamCreateWithFlags(&b->s0, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
               hipEventCreate(&b->ev0) == hipSuccess && hipEventCreate(&b->ev1) == hipSuccess;
@@ -2224,8 +2297,6 @@ bd3mg_status bd3mg_batch_destroy(bd3mg_batch b)
     if (!b) return BD3MG_OK;
     if (b->s0) (void)hipStreamSynchronize(b->s0);
     batch_drop_graph(b);
-    if (b->d_fa) (void)hipFree(b->d_fa);
-    if (b->d_owner) (void)hipFree(b->d_owner);
     for (hipEvent_t e : b->join)
         if (e) (void)hipEventDestroy(e);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -2265,10 +2336,7 @@ bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, in
     if (!b) return fail(BD3MG_ERR_ARG, "null batch");
     if (max_sweeps < 0 || check_every < 0) return fail(BD3MG_ERR_ARG, "negative sweep count");
     const int n = (int)b->probs.size();
-    for (bd3mg_problem p : b->probs) {
-        ST_TRY(ensure_ready(p));
-        p->hdp_valid = false;  // batch sweeps blur both directions and keep no H dp
-    }
+    for (bd3mg_problem p : b->probs) ST_TRY(ensure_ready(p));
     const bool stopping = grad_rtol > 0.0;
     int ce = check_every > 0 ? check_every : 16;
     ce += ce & 1;  // checks fall between graph launches of two sweeps
@@ -2284,15 +2352,16 @@ bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, in
         bool any = false;
         for (int i = 0; i < n; ++i) any = any || active[i];
         if (!any) break;
-        bool recapture = !b->exec || b->captured != active;
-        for (int i = 0; i < n && !recapture; ++i)
-            if (active[i] && b->cap_cur[i] != b->probs[i]->cur) recapture = true;
-        if (recapture) ST_TRY(batch_capture_any(b, active));
-        HIP_TRY(hipGraphLaunch(b->exec, b->s0));
+        hipGraphExec_t exec = nullptr;
+        ST_TRY(batch_graph(b, active, &exec));
+        HIP_TRY(hipGraphLaunch(exec, b->s0));
         bool need_sync = stopping && ((s + 2) % ce == 0);
         for (int i = 0; i < n; ++i) {
             if (!active[i]) continue;
             bd3mg_problem p = b->probs[i];
+            int m[2];
+            pair_modes(p, m);
+            p->hdp_valid = m[1] != 0;
             done[i] += 2;
             p->sweeps_done += 2;
             if (p->refresh_every > 0 && p->sweeps_done / p->refresh_every != (p->sweeps_done - 2) / p->refresh_every)
@@ -2327,7 +2396,9 @@ bd3mg_status bd3mg_batch_run(bd3mg_batch b, int max_sweeps, double grad_rtol, in
         for (int i = 0; i < n; ++i) {
             if (!active[i]) continue;
             bd3mg_problem p = b->probs[i];
-            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], false));
+            const int hm = hdp_mode(p, false, p->sweeps_done, p->hdp_valid);
+            for (int c = 0; c < p->ncolors; ++c) ST_TRY(phase(p, p->groups[c], false, nullptr, hm));
+            p->hdp_valid = hm != 0;
             p->cur ^= 1;
             done[i] += 1;
             p->sweeps_done += 1;

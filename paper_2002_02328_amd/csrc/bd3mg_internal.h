@@ -263,7 +263,7 @@ struct FusedArgs {
 enum : int { FP_GRAD = 0, FP_DIRS = 1, FP_SOLVE = 2, FP_UPDATE = 3 };
 template <typename T>
 hipError_t launch_fused(int pass, const Geom &g, const FusedArgs<T> *fa, const unsigned char *owner, unsigned nwg,
-                        hipStream_t st);
+                        hipStream_t st, bool one = false);
 
 // Start and stop events for the next kernel launch of this host thread (set
 // around a profiled single-kernel pass, null otherwise): the launchers then

@@ -1846,7 +1846,7 @@ k_grad_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restric
     grad_body<T, KZ, false, true>(vb, a.g, a.prm, a.s, a.s.q, a.s.x, nullptr, a.items, GM_BLOCK, a.pg, 0);
 }
 
-template <typename T, int KZ, int R, int TYK>
+template <typename T, int KZ, int R, int TYK, bool ONE>
 __global__ void __launch_bounds__(NT)
 k_dirs_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner)
 {
@@ -1854,7 +1854,7 @@ k_dirs_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restric
     VB vb;
     if (!fused_part(fa, owner, &p, &vb)) return;
     const FusedArgs<T> &a = fa[p];
-    dirs_body<T, KZ, R, TYK>(vb, a.g, a.prm, a.s, a.items, a.pd);
+    dirs_body<T, KZ, R, TYK, ONE>(vb, a.g, a.prm, a.s, a.items, a.pd);
 }
 
 template <typename T>
@@ -2022,7 +2022,7 @@ hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items,
 
 template <typename T>
 hipError_t launch_fused(int pass, const Geom &g, const FusedArgs<T> *fa, const unsigned char *owner, unsigned nwg,
-                        hipStream_t st)
+                        hipStream_t st, bool one)
 {
     if (nwg == 0) return hipSuccess;
     const dim3 grid(nwg);
@@ -2031,8 +2031,13 @@ hipError_t launch_fused(int pass, const Geom &g, const FusedArgs<T> *fa, const u
         BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_LAUNCH((k_grad_fused<T, KZ>), grid, dim3(NT), 0, st, fa, owner));
         break;
     case FP_DIRS:
-        BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
-                        BD3MG_LAUNCH((k_dirs_fused<T, KZ, R, TYK>), grid, dim3(NT), 0, st, fa, owner))));
+        if (one) {
+            BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
+                            BD3MG_LAUNCH((k_dirs_fused<T, KZ, R, TYK, true>), grid, dim3(NT), 0, st, fa, owner))));
+        } else {
+            BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_dirs,
+                            BD3MG_LAUNCH((k_dirs_fused<T, KZ, R, TYK, false>), grid, dim3(NT), 0, st, fa, owner))));
+        }
         break;
     case FP_SOLVE:
         BD3MG_LAUNCH((k_solve_fused<T>), grid, dim3(NT), 0, st, fa, owner);
@@ -2255,7 +2260,7 @@ hipError_t scratch_base(int device, void **ptr)
     template hipError_t launch_cg<T>(int, const Geom &, const DevState<T> &, const Item *, int,    \
                                      const CgBufs<T> &, int, double, hipStream_t);                \
     template hipError_t launch_fused<T>(int, const Geom &, const FusedArgs<T> *,                   \
-                                        const unsigned char *, unsigned, hipStream_t);            \
+                                        const unsigned char *, unsigned, hipStream_t, bool);      \
     template hipError_t launch_refresh<T>(const Geom &, const DevState<T> &, const T *, T *,       \
                                           const Item *, int, hipStream_t);                        \
     template hipError_t launch_H<T>(const Geom &, const DevState<T> &, const T *, const T *, T *,  \

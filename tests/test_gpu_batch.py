@@ -1,10 +1,12 @@
 """GPU parity of batched BD3MG: many problems of uneven sizes advanced together
 through one graph launch per two sweeps.
 
-The batch runs the same kernels with the same arguments as single-problem runs
-that blur both directions every sweep (BD3MG_OPT_HDP_EVERY = 0: a batch keeps
-no H dp), so a batched run must equal those single runs bitwise; against the
-FP64 oracle the usual FP64 / FP32 bounds apply (see test_gpu_solver).
+The batch runs the same kernels with the same arguments as single-problem
+runs, the direction pass of each problem blurring d1 only or both directions
+on the same sweeps as its single run (by its own sweep count), so a batched
+run must equal the single runs bitwise, with H dp kept (the default) and
+without (BD3MG_OPT_HDP_EVERY = 0); against the FP64 oracle the usual FP64 /
+FP32 bounds apply (see test_gpu_solver).
 """
 import numpy as np
 import pytest
@@ -15,7 +17,7 @@ from gpu_common import rel, rounded
 pytestmark = pytest.mark.gpu
 
 
-def setup(orc, w, prec):
+def setup(orc, w, prec, hdp_every=None):
     gxy = rounded(orc.gauss_table(w.sigma_xy, w.kxy), prec)
     gz = rounded(orc.gauss_table(w.sigma_z, w.kz), prec)
     y = rounded(orc.Problem(np.zeros(w.shape), gxy, gxy, gz).H(w.xbar) + w.noise, prec)
@@ -26,7 +28,8 @@ def setup(orc, w, prec):
     g.set_data(y)
     g.set_blocks(w.nslices)
     g.set_x0(None)
-    g.set_option(binding.OPT_HDP_EVERY, 0)  # single runs as a batch runs them
+    if hdp_every is not None:
+        g.set_option(binding.OPT_HDP_EVERY, hdp_every)
     o = orc.Problem(y, gxy, gxy, gz, lam=w.lam, delta=w.delta, eta=w.eta, kappa=w.kappa)
     return g, o, y
 
@@ -38,15 +41,16 @@ def small_members():
             inputs.tiny((5, 64, 64), 34, kxy=9, kz=1, nblocks=5)]
 
 
-@pytest.mark.parametrize("sweeps", [6, 7])
-def test_batch_equals_single_runs_bitwise(orc, sweeps):
+@pytest.mark.parametrize("hdp_every", [None, 0])
+@pytest.mark.parametrize("sweeps", [6, 7, 70])
+def test_batch_equals_single_runs_bitwise(orc, sweeps, hdp_every):
     ws = small_members()
     single = []
     for w in ws:
-        g, o, y = setup(orc, w, binding.FP32)
+        g, o, y = setup(orc, w, binding.FP32, hdp_every)
         g.run(sweeps, check_every=0)
         single.append(g.get_x())
-    probs = [setup(orc, w, binding.FP32)[0] for w in ws]
+    probs = [setup(orc, w, binding.FP32, hdp_every)[0] for w in ws]
     b = binding.Batch(probs)
     res = b.run(sweeps)
     for g, xs, r in zip(probs, single, res):
@@ -67,16 +71,16 @@ def fusable_members():
             inputs.tiny((16, 23, 91), 45, kxy=5, kz=5, nblocks=7)]
 
 
-@pytest.mark.parametrize("prec", [binding.FP32, binding.FP64])
-@pytest.mark.parametrize("sweeps", [6, 7])
-def test_fused_batch_equals_single_runs_bitwise(orc, prec, sweeps):
+@pytest.mark.parametrize("prec,hdp_every", [(binding.FP32, None), (binding.FP64, None), (binding.FP32, 0)])
+@pytest.mark.parametrize("sweeps", [6, 7, 70])
+def test_fused_batch_equals_single_runs_bitwise(orc, prec, sweeps, hdp_every):
     ws = fusable_members()
     single = []
     for w in ws:
-        g, o, y = setup(orc, w, prec)
+        g, o, y = setup(orc, w, prec, hdp_every)
         g.run(sweeps, check_every=0)
         single.append((g.get_x(), g.get_dprev()))
-    probs = [setup(orc, w, prec)[0] for w in ws]
+    probs = [setup(orc, w, prec, hdp_every)[0] for w in ws]
     b = binding.Batch(probs)
     assert b.set_mode(binding.BATCH_FUSED)
     res = b.run(sweeps)
@@ -84,7 +88,7 @@ def test_fused_batch_equals_single_runs_bitwise(orc, prec, sweeps):
         assert r["sweeps"] == sweeps
         assert np.array_equal(g.get_x(), xs) and np.array_equal(g.get_dprev(), ds)
     # and the branch mode gives the same again
-    probs2 = [setup(orc, w, prec)[0] for w in ws]
+    probs2 = [setup(orc, w, prec, hdp_every)[0] for w in ws]
     b2 = binding.Batch(probs2)
     assert not b2.set_mode(binding.BATCH_BRANCHES)
     b2.run(sweeps)

@@ -118,7 +118,6 @@ def test_round_batch_equals_single_runs(orc):
     single = []
     for i, (shape, ns, kxy, kz) in enumerate(cases):
         g, o, y = setup(shape, 20 + i, binding.FP32, kxy, kz, ns, binding.SCHED_ROUND, mu=0.3)
-        g.set_option(binding.OPT_HDP_EVERY, 0)  # as the batch runs it: no H dp kept
         g.run(7, check_every=0)
         single.append(g.get_x())
     probs = [setup(shape, 20 + i, binding.FP32, kxy, kz, ns, binding.SCHED_ROUND, mu=0.3)[0]
