@@ -611,8 +611,12 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     }
 }
 
+// Waves per SIMD the register budget aims at: the single-precision block
+// instance's branch-free z taps need 103 VGPRs (four waves); the LDS holds
+// the 3D-TV instances to three and double precision to two (one with 3D TV).
 template <typename T, int KZ, bool TV3, bool BLK>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(BLK ? 4 : 5)))
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (TV3 ? 1 : 2) : (TV3 ? 3 : (BLK ? 4 : 5)))))
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
        int nshare)
@@ -1836,7 +1840,7 @@ __device__ __forceinline__ bool fused_part(const FusedArgs<T> *__restrict__ fa, 
 }
 
 template <typename T, int KZ>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
 k_grad_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner)
 {
     int p;
