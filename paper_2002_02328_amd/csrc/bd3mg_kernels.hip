@@ -368,9 +368,14 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     __shared__ T PX[padded<PW, PH>()];
     __shared__ T PY[padded<PW, PH>()];
     __shared__ T WW[padded<PW, PH>()];
-    __shared__ T G[padded<GW, GH>()];
-    __shared__ T D[padded<GW, GH>()];
     __shared__ double red[(NT / 64) * NQG];
+    // g and dp on the tile plus one column and row, for the curvature sums,
+    // written over x and w VX x once the gradient is formed (four tiles of
+    // LDS instead of six: more workgroups fit a compute unit)
+    T *const G = X;
+    T *const D = PX;
+    static_assert(padded<GW, GH>() <= padded<XW, XH>() && padded<GW, GH>() <= padded<PW, PH>(),
+                  "g and dp must fit the tiles they replace");
     // TV3: x on slice k - 1 (same positions as X), and at the positions of w
     // the z part w_{k-1} VZ x_{k-1} - w_k VZ x_k of VZ^T(w VZ x)
     __shared__ T XM[TV3 ? padded<XW, XH>() : 1];
@@ -528,6 +533,7 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
             lo = (T)prm.xmin, hi = (T)prm.xmax;
     double qs[NQG] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     const __amdgpu_buffer_rsrc_t go = buf_of(s.g + (size_t)k * S, S);
+    T gr[rg.E];
 #pragma unroll
     for (int qq = 0; qq < rg.E; ++qq) {
         const int e = threadIdx.x + qq * NT;
@@ -581,10 +587,17 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
                 }
             }
         }
-        G[e] = gv;
-        D[e] = dv[qq];
+        gr[qq] = gv;
     }
     if (block) {
+        __syncthreads();  // x and w VX x are read no more
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            if (rg.N % NT != 0 && e >= rg.N) break;
+            G[e] = gr[qq];
+            D[e] = dv[qq];
+        }
         __syncthreads();
         // sum_S w (VX d_a VX d_b + VY d_a VY d_b), d1 = -g, d2 = dp
         const int tx = threadIdx.x & (TX - 1);
@@ -612,11 +625,12 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
 }
 
 // Waves per SIMD the register budget aims at: the single-precision block
-// instance's branch-free z taps need 103 VGPRs (four waves); the LDS holds
-// the 3D-TV instances to three and double precision to two (one with 3D TV).
+// instance's branch-free z taps need 104 VGPRs (four waves); the LDS holds
+// double precision to three (one with 3D TV) and single-precision 3D TV to
+// three.
 template <typename T, int KZ, bool TV3, bool BLK>
 __global__ void __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (TV3 ? 1 : 2) : (TV3 ? 3 : (BLK ? 4 : 5)))))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (TV3 ? 1 : 3) : (TV3 ? 3 : (BLK ? 4 : 5)))))
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
        int nshare)
@@ -1840,7 +1854,7 @@ __device__ __forceinline__ bool fused_part(const FusedArgs<T> *__restrict__ fa, 
 }
 
 template <typename T, int KZ>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 2 : 4)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4)))
 k_grad_fused(const FusedArgs<T> *__restrict__ fa, const unsigned char *__restrict__ owner)
 {
     int p;
