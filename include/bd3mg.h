@@ -387,7 +387,7 @@ typedef enum {
      * ones included; the state's sweep count (bd3mg_get_state) only those
      * kept.  Costs three volumes, an evaluation of f (the blur of x and an
      * evaluation pass) and a copy of the state every m sweeps.  Other
-     * schedules and bd3mg_run_noalloc ignore it. */
+     * schedules, batches and bd3mg_run_noalloc ignore it. */
     BD3MG_OPT_ROUND_GUARD = 7
 } bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
