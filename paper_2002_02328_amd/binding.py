@@ -27,6 +27,7 @@ OPT_REFRESH_EVERY, OPT_PROFILE = 0, 1
 OPT_TILE_ROWS_DIRS, OPT_TILE_ROWS_UPDATE, OPT_TILE_ROWS_AUX, OPT_DIRS_SLICES = 2, 3, 4, 5
 OPT_HDP_EVERY = 6
 OPT_ROUND_GUARD = 7
+OPT_STREAM_STORES = 8
 KERNEL_KINDS = ("grad", "dirs", "solve", "update", "eval")
 
 # Every function the header declares, with its C signature.

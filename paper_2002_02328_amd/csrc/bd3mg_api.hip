@@ -111,6 +111,7 @@ struct bd3mg_problem_s {
     void *d_hdp = nullptr;
     size_t hdp_alloc = 0, hdp_slots = 0;
     long long hdp_every = 64;  // sweeps 0, n, 2n, ... (counted from x^0) blur both directions (0: H dp never kept)
+    int stream_stores = -1;    // BD3MG_OPT_STREAM_STORES: -1 by volume size, 0 off, 1 on
     bool hdp_valid = false;    // the buffer cur selects holds H dp of every block
     int maxg = 1, maxd = 1;   // most gradient and direction items of a launch group
 
@@ -159,6 +160,17 @@ struct bd3mg_problem_s {
 
 namespace {
 
+// Non-temporal stores of the passes' volume outputs (BD3MG_OPT_STREAM_STORES):
+// by default when one volume of the problem holds at least 64 MiB, where a
+// colour's passes move several times the GPU's L2 and Infinity Cache and
+// kept lines are evicted before the next pass reads them (measured: 512 x
+// 512 x 128 in FP32 gains 3 %, 256 x 256 x 64 loses 9 %).
+bool stream_stores(bd3mg_problem p)
+{
+    if (p->stream_stores >= 0) return p->stream_stores != 0;
+    return (double)p->N * p->esz >= 64.0 * 1024 * 1024;
+}
+
 template <typename T>
 DevState<T> dev_state(bd3mg_problem p)
 {
@@ -177,6 +189,7 @@ DevState<T> dev_state(bd3mg_problem p)
     s.hd[1] = s.hd[0] ? s.hd[0] + p->hd_slots * p->nx * p->ny : nullptr;
     s.hdw = nullptr;
     s.stop = nullptr;
+    s.nt = stream_stores(p) ? 1 : 0;
     return s;
 }
 
@@ -1793,6 +1806,10 @@ bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value)
         *t = (int)value;
         return BD3MG_OK;
     }
+    case BD3MG_OPT_STREAM_STORES:
+        if (value < -1 || value > 1) return fail(BD3MG_ERR_ARG, "stream stores must be -1, 0 or 1");
+        p->stream_stores = (int)value;
+        return BD3MG_OK;
     case BD3MG_OPT_DIRS_SLICES:
         if (value < 0 || value > 2) return fail(BD3MG_ERR_ARG, "direction slices must be 0, 1 or 2");
         p->dirs_slices = (int)value;

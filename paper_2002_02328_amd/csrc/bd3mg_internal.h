@@ -118,6 +118,7 @@ struct DevState {
     const int *sblk;           // block of every slice
     T *hd[2];                  // H d1, H d2 of the launch group's direction items [slot][ny][nx]
     T *hdw;                    // when set: H d' of each update pair written here by slot (H dp of the next visit)
+    int nt;                    // 1: the sweep passes store their volume outputs with the non-temporal hint
 };
 
 enum GradMode : int {

@@ -116,14 +116,20 @@ __device__ __forceinline__ double ldbuf<double>(__amdgpu_buffer_rsrc_t r, uint32
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, boff, 0, 0));
 }
 
+// Stores of the passes' volume outputs; STREAM: with the non-temporal hint
+// (cache policy bit nt), which streams them through the caches instead of
+// keeping them there. It pays when the volumes a colour touches are far
+// larger than the caches and costs when the next pass would find them there.
+template <bool STREAM = false>
 __device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, uint32_t boff, float v)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, boff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, boff, 0, STREAM ? 2 : 0);
 }
+template <bool STREAM = false>
 __device__ __forceinline__ void stbuf(__amdgpu_buffer_rsrc_t r, uint32_t boff, double v)
 {
     typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, boff, 0, STREAM ? 2 : 0);
 }
 
 // x pass from I (rows of width WI, at least ROWS rows) to O (rows of width WO,
@@ -353,7 +359,8 @@ __device__ __forceinline__ size_t slot_of(const VB &v)
 // ---------------------------------------------------------------------------
 // BLK: the sweep's mode GM_BLOCK fixed at compile time (its instance carries
 // no code of the other modes and no copies of their sums); otherwise mode_in.
-template <typename T, int KZ, bool TV3, bool BLK>
+// STREAM: g stored with the non-temporal hint (s.nt).
+template <typename T, int KZ, bool TV3, bool BLK, bool STREAM = false>
 __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevState<T> s, const T *__restrict__ q,
                                           const T *__restrict__ x, T *__restrict__ out,
                                           const Item *__restrict__ items, int mode_in,
@@ -565,7 +572,6 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
             }
             if (interior) {
                 if (block) {
-                    stbuf(go, bo[qq], gv);
                     const double gd = (double)gv, dd = (double)dv[qq];
                     qs[0] += gd * gd;
                     qs[1] += gd * dd;
@@ -590,6 +596,13 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
         gr[qq] = gv;
     }
     if (block) {
+        // g of the tile's outputs, stored once the loop is done
+#pragma unroll
+        for (int qq = 0; qq < rg.E; ++qq) {
+            const int e = threadIdx.x + qq * NT;
+            const int lj = e / GW, li = e - lj * GW;
+            if (rg.inb[qq] && lj < TY && li < TX) stbuf<STREAM>(go, bo[qq], gr[qq]);
+        }
         __syncthreads();  // x and w VX x are read no more
 #pragma unroll
         for (int qq = 0; qq < rg.E; ++qq) {
@@ -628,14 +641,14 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
 // instance's branch-free z taps need 104 VGPRs (four waves); the LDS holds
 // double precision to three (one with 3D TV) and single-precision 3D TV to
 // three.
-template <typename T, int KZ, bool TV3, bool BLK>
+template <typename T, int KZ, bool TV3, bool BLK, bool STREAM>
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (TV3 ? 1 : 3) : (TV3 ? 3 : (BLK ? 4 : 5)))))
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
        int nshare)
 {
-    grad_body<T, KZ, TV3, BLK>(vb_native(), g, prm, s, q, x, out, items, mode, partials, nshare);
+    grad_body<T, KZ, TV3, BLK, STREAM>(vb_native(), g, prm, s, q, x, out, items, mode, partials, nshare);
 }
 
 // ---------------------------------------------------------------------------
@@ -995,7 +1008,7 @@ k_dirs(Geom g, Params prm, DevState<T> s, const Item *__restrict__ units, double
 // each pair's H d' on the tile is also stored in its slot there: the H dp of
 // the block's next visit, so that its direction pass blurs only d1.
 // ---------------------------------------------------------------------------
-template <typename T, int R, int TYK, bool MULTI>
+template <typename T, int R, int TYK, bool MULTI, bool STREAM = false>
 __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, const Item *__restrict__ items,
                                             const int2 *__restrict__ pairs, const double *__restrict__ u, int assign)
 {
@@ -1115,8 +1128,8 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
             if (i >= g.nx || j >= g.ny) continue;
             const uint32_t o = (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T);
             const T d = u2 * dv[e] - u1 * gv[e];
-            stbuf(xo, o, xv[e] + d);
-            stbuf(dpo, o, d);
+            stbuf<STREAM>(xo, o, xv[e] + d);
+            stbuf<STREAM>(dpo, o, d);
         }
     }
     __syncthreads();
@@ -1128,7 +1141,7 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
         for (int e = 0; e < NRK; ++e) {
             const int j = y0 + out_row<NRK>(e), i = x0 + tx;
             if (i >= g.nx || j >= g.ny) continue;
-            stbuf(ho, (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T), A[(out_row<NRK>(e) + R) * WS2 + tx + R]);
+            stbuf<STREAM>(ho, (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T), A[(out_row<NRK>(e) + R) * WS2 + tx + R]);
         }
     }
     xpass4<T, R, H2, true>(A, B, wx);
@@ -1140,16 +1153,17 @@ __device__ __forceinline__ void update_body(const VB vb, Geom g, DevState<T> s, 
     for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row<NRK>(e), i = x0 + tx;
         if (i >= g.nx || j >= g.ny) continue;
-        stbuf(qo, (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T), qv[e] + v[e]);
+        stbuf<STREAM>(qo, (uint32_t)(j * g.nx + i) * (uint32_t)sizeof(T), qv[e] + v[e]);
     }
 }
 
-template <typename T, int R, int TYK, bool MULTI>
+// STREAM: the instance whose volume stores carry the non-temporal hint (s.nt)
+template <typename T, int R, int TYK, bool MULTI, bool STREAM>
 __global__ void __launch_bounds__(NT)
 k_update(Geom g, DevState<T> s, const Item *__restrict__ items, const int2 *__restrict__ pairs,
          const double *__restrict__ u, int assign)
 {
-    update_body<T, R, TYK, MULTI>(vb_native(), g, s, items, pairs, u, assign);
+    update_body<T, R, TYK, MULTI, STREAM>(vb_native(), g, s, items, pairs, u, assign);
 }
 
 // ---------------------------------------------------------------------------
@@ -1983,21 +1997,23 @@ hipError_t launch_grad(const Geom &g, const Params &prm, const DevState<T> &s, c
 {
     if (nitems <= 0) return hipSuccess;
     if (nshare > 0 && g.rz != 0) return hipErrorInvalidValue;
-#define BD3MG_GRAD_LAUNCH(TV, BL)                                                                  \
-    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_LAUNCH((k_grad<T, KZ, TV, BL>), grid_of(g, nitems), dim3(NT), 0, st, \
-                                               g, prm, s, q, x, out, items, mode, partials, nshare))
+#define BD3MG_GRAD_LAUNCH(TV, BL, STR)                                                             \
+    BD3MG_KZ_SWITCH(2 * g.rz + 1, BD3MG_LAUNCH((k_grad<T, KZ, TV, BL, STR>), grid_of(g, nitems), dim3(NT), 0, \
+                                               st, g, prm, s, q, x, out, items, mode, partials, nshare))
     const bool blk = mode == GM_BLOCK;
     if (prm.tv3d) {
         if (blk) {
-            BD3MG_GRAD_LAUNCH(true, true);
+            BD3MG_GRAD_LAUNCH(true, true, false);
         } else {
-            BD3MG_GRAD_LAUNCH(true, false);
+            BD3MG_GRAD_LAUNCH(true, false, false);
         }
     } else {
-        if (blk) {
-            BD3MG_GRAD_LAUNCH(false, true);
+        if (blk && s.nt) {
+            BD3MG_GRAD_LAUNCH(false, true, true);
+        } else if (blk) {
+            BD3MG_GRAD_LAUNCH(false, true, false);
         } else {
-            BD3MG_GRAD_LAUNCH(false, false);
+            BD3MG_GRAD_LAUNCH(false, false, false);
         }
     }
 #undef BD3MG_GRAD_LAUNCH
@@ -2028,11 +2044,15 @@ hipError_t launch_update(const Geom &g, const DevState<T> &s, const Item *items,
     if (nitems <= 0) return hipSuccess;
     if (multi) {
         BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
-                       BD3MG_LAUNCH((k_update<T, R, TYK, true>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                       BD3MG_LAUNCH((k_update<T, R, TYK, true, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                                          st, g, s, items, pairs, u, assign)));
+    } else if (s.nt) {
+        BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
+                       BD3MG_LAUNCH((k_update<T, R, TYK, false, true>), grid_of(g, nitems, TYK), dim3(NT), 0,
                                           st, g, s, items, pairs, u, assign)));
     } else {
         BD3MG_R_SWITCH(g.R, BD3MG_TY_SWITCH(g.ty_update,
-                       BD3MG_LAUNCH((k_update<T, R, TYK, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
+                       BD3MG_LAUNCH((k_update<T, R, TYK, false, false>), grid_of(g, nitems, TYK), dim3(NT), 0,
                                           st, g, s, items, pairs, u, assign)));
     }
     return hipGetLastError();
