@@ -135,11 +135,14 @@ def kernel_variant(w, kernel, tile_rows):
         ty = tile_rows["dirs"]
         return {"grad": "k_dense<%s, %d, 1, true, %d>" % (t, r, ty), "dirs": "k_dense<%s, %d, 2, false, %d>" % (t, r, ty),
                 "solve": "k_solve", "update": "k_dense_update<%s>" % t}[kernel]
-    # the direction pass blurs d1 only (H dp kept) on all sweeps but one in 64
-    return {"grad": "k_grad<%s, %d, false, true>" % (t, kz),
+    # the direction pass blurs d1 only (H dp kept) on all sweeps but one in 64;
+    # the gradient and update instances that stream their stores run when one
+    # volume holds at least 64 MiB (the library's default)
+    st = "true" if np.prod(w.shape) * (8 if w.fp64 else 4) >= 64 * 2 ** 20 else "false"
+    return {"grad": "k_grad<%s, %d, false, true, %s>" % (t, kz, st),
             "dirs": "k_dirs<%s, %d, %d, %d, true>" % (t, kz, r, tile_rows["dirs"]),
             "solve": "k_solve",
-            "update": "k_update<%s, %d, %d, false>" % (t, r, tile_rows["update"])}[kernel]
+            "update": "k_update<%s, %d, %d, false, %s>" % (t, r, tile_rows["update"], st)}[kernel]
 
 
 def measured_traffic(workload, variant):
