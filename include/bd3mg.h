@@ -389,11 +389,12 @@ typedef enum {
      * evaluation pass) and a copy of the state every m sweeps.  Other
      * schedules, batches and bd3mg_run_noalloc ignore it. */
     BD3MG_OPT_ROUND_GUARD = 7,
-    /* Stores of the gradient and update passes' volume outputs (g; x, the
-     * steps, q and the kept H d' of a coloured or sequential sweep) with the
-     * non-temporal cache hint: 1 on, 0 off, -1 (the default) on when one
-     * volume of the problem holds at least 64 MiB.  A cache hint only:
-     * results are bitwise the same for every setting. */
+    /* Stores of the gradient and update passes' volume outputs (g, unless
+     * the total variation is taken along z as well; x, the steps, q and the
+     * kept H d' of a coloured or sequential sweep) with the non-temporal
+     * cache hint: 1 on, 0 off, -1 (the default) on when one volume of the
+     * problem holds at least 64 MiB.  A cache hint only: results are
+     * bitwise the same for every setting. */
     BD3MG_OPT_STREAM_STORES = 8
 } bd3mg_option;
 bd3mg_status bd3mg_set_option(bd3mg_problem p, int option, long long value);
