@@ -44,8 +44,12 @@ template <typename T>
 __device__ __forceinline__ T clampv(T v, T lo, T hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 // 1 / sqrt(v): the hardware reciprocal square root in single precision
-// (about 1 ulp), the correctly rounded quotient in double precision.
-__device__ __forceinline__ float inv_sqrt(float v) { return rsqrtf(v); }
+// (about 1 ulp), the correctly rounded quotient in double precision.  The
+// single-precision instruction flushes subnormal arguments, so v is held at
+// or above the smallest normal number (every argument here is at least
+// delta^2, a normal number for any delta above 1.1e-19); above it this is
+// the instruction rsqrtf takes there, with none of its rescaling.
+__device__ __forceinline__ float inv_sqrt(float v) { return __builtin_amdgcn_rsqf(fmaxf(v, 0x1p-126f)); }
 __device__ __forceinline__ double inv_sqrt(double v) { return 1.0 / sqrt(v); }
 
 // Tile row of a thread's e-th output when each thread owns NR consecutive
@@ -503,34 +507,37 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
             if (e < N) {
                 const int jj = e / PW, ii = e - jj * PW;
                 const int j = y0 - 1 + jj, i = x0 - 1 + ii;
-                T px = 0, py = 0, w = 0, pt = 0;
-                if (i >= 0 && i < g.nx && j >= 0 && j < g.ny) {
-                    const T *xc = X + jj * XW + ii;
-                    const T dxv = (i < g.nx - 1) ? xc[1] - xc[0] : T(0);
-                    const T dyv = (j < g.ny - 1) ? xc[XW] - xc[0] : T(0);
-                    if constexpr (TV3) {
-                        const T dzv = (k < g.nz - 1) ? xn[qq] - xc[0] : T(0);
-                        w = inv_sqrt(dxv * dxv + dyv * dyv + dzv * dzv + del2);
-                        // w VZ x on slice k - 1 at the same position
-                        T zm = 0;
-                        if (k >= 1) {
-                            const T *mc = XM + jj * XW + ii;
-                            const T dxm = (i < g.nx - 1) ? mc[1] - mc[0] : T(0);
-                            const T dym = (j < g.ny - 1) ? mc[XW] - mc[0] : T(0);
-                            const T dzm = xc[0] - mc[0];
-                            zm = inv_sqrt(dxm * dxm + dym * dym + dzm * dzm + del2) * dzm;
-                        }
-                        pt = zm - w * dzv;
-                    } else {
-                        w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
+                // computed everywhere without a branch: the reads stay inside
+                // the x tiles (jj + 1 < XH, ii + 1 < XW), whose elements
+                // outside the slice are zero, and the results there are
+                // replaced by zero
+                const bool in = i >= 0 && i < g.nx && j >= 0 && j < g.ny;
+                const T *xc = X + jj * XW + ii;
+                const T xv = xc[0];
+                const T dxv = (i < g.nx - 1) ? xc[1] - xv : T(0);
+                const T dyv = (j < g.ny - 1) ? xc[XW] - xv : T(0);
+                T w, pt = 0;
+                if constexpr (TV3) {
+                    const T dzv = (k < g.nz - 1) ? xn[qq] - xv : T(0);
+                    w = inv_sqrt(dxv * dxv + dyv * dyv + dzv * dzv + del2);
+                    // w VZ x on slice k - 1 at the same position
+                    T zm = 0;
+                    if (k >= 1) {
+                        const T *mc = XM + jj * XW + ii;
+                        const T mv = mc[0];
+                        const T dxm = (i < g.nx - 1) ? mc[1] - mv : T(0);
+                        const T dym = (j < g.ny - 1) ? mc[XW] - mv : T(0);
+                        const T dzm = xv - mv;
+                        zm = inv_sqrt(dxm * dxm + dym * dym + dzm * dzm + del2) * dzm;
                     }
-                    px = w * dxv;
-                    py = w * dyv;
+                    pt = zm - w * dzv;
+                } else {
+                    w = inv_sqrt(dxv * dxv + dyv * dyv + del2);
                 }
-                PX[e] = px;
-                PY[e] = py;
-                WW[e] = w;
-                if constexpr (TV3) PT[e] = pt;
+                PX[e] = in ? w * dxv : T(0);
+                PY[e] = in ? w * dyv : T(0);
+                WW[e] = in ? w : T(0);
+                if constexpr (TV3) PT[e] = in ? pt : T(0);
             }
         }
     }
