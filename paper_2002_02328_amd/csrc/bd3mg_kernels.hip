@@ -246,20 +246,25 @@ __device__ __forceinline__ void load_taps(T (&w)[2 * R + 1], const T *__restrict
     for (int a = 0; a < 2 * R + 1; ++a) w[a] = t[a];
 }
 
-// One DPP move of a double (both halves with the same lane pattern); lanes of
-// rows outside ROWS receive 0.
+// One DPP move of a double (both halves with the same lane pattern). Lanes of
+// rows outside ROWS are not written and hold whatever the destination held
+// (no zeroing move per half): callers use no value that passes through them.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_move(double v)
 {
     const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, ROWS, 0xf, false);
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // Sum over the 64 lanes of a wavefront in registers: butterflies inside each
-// row of 16 lanes (quad permutes, half-row and row mirrors), then the two row
-// broadcasts. Lane 63 ends with the total; the other lanes hold partial sums.
+// row of 16 lanes (quad permutes, half-row and row mirrors: every lane ends
+// with its row's sum), then the two row broadcasts. Only lane 63's result is
+// the total, and only it may be used: the broadcast steps add undefined values
+// in the rows they do not write (rows 0 and 2, then 0 and 1), and lane 63
+// reads only lane 47 (row 2 before its undefined add) and lane 31 (row 1,
+// written by the first broadcast).
 __device__ __forceinline__ double wave_sum_last(double s)
 {
     s += dpp_move<0xb1, 0xf>(s);   // quad_perm [1,0,3,2]
