@@ -557,9 +557,15 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     for (int qq = 0; qq < rg.E; ++qq) {
         const int e = threadIdx.x + qq * NT;
         const int lj = e / GW, li = e - lj * GW;
-        const bool interior = lj < TY && li < TX;
+        // the tile's own outputs inside the slice (the extra row and column
+        // are formed for the curvature sums only)
+        const bool own = rg.inb[qq] && lj < TY && li < TX;
         T gv = 0;
-        if (rg.inb[qq]) {
+        if (rg.N % NT == 0 || e < rg.N) {
+            // formed without a branch at every element of the region: the
+            // reads stay inside the tiles, whose elements outside the slice
+            // are zero; g there is replaced by zero, and the sums add exact
+            // zeros for all but the tile's own outputs
             const int j = y0 + lj, i = x0 + li;
             const T *xc = X + (lj + 1) * XW + (li + 1);
             const T xv = xc[0];
@@ -582,27 +588,26 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
             } else if (TV3 && mode == GM_EVAL && k < g.nz - 1) {
                 dz = x[o + S] - xv;
             }
-            if (interior) {
-                if (block) {
-                    const double gd = (double)gv, dd = (double)dv[qq];
-                    qs[0] += gd * gd;
-                    qs[1] += gd * dd;
-                    qs[2] += dd * dd;
-                } else if (mode == GM_GRAD) {
-                    out[o] = gv;
-                } else {  // GM_EVAL: terms of f in double
-                    const double xd = (double)xv;
-                    const double dxd = (i < g.nx - 1) ? (double)xc[1] - xd : 0.0;
-                    const double dyd = (j < g.ny - 1) ? (double)xc[XW] - xd : 0.0;
-                    const double dzd = (double)dz;
-                    const double bx = xd - (xd < prm.xmin ? prm.xmin : (xd > prm.xmax ? prm.xmax : xd));
-                    const double gd = (double)gv;
-                    qs[0] += gd * gd;
-                    const double tz = TV3 ? dzd * dzd : 0.0;
-                    qs[1] += sqrt(dxd * dxd + dyd * dyd + tz + prm.delta * prm.delta);
-                    qs[2] += bx * bx;
-                    qs[3] += dzd * dzd;
-                }
+            gv = rg.inb[qq] ? gv : T(0);
+            if (block) {
+                const double gd = own ? (double)gv : 0.0, dd = own ? (double)dv[qq] : 0.0;
+                qs[0] += gd * gd;
+                qs[1] += gd * dd;
+                qs[2] += dd * dd;
+            } else if (mode == GM_GRAD) {
+                if (own) out[o] = gv;
+            } else if (own) {  // GM_EVAL: terms of f in double
+                const double xd = (double)xv;
+                const double dxd = (i < g.nx - 1) ? (double)xc[1] - xd : 0.0;
+                const double dyd = (j < g.ny - 1) ? (double)xc[XW] - xd : 0.0;
+                const double dzd = (double)dz;
+                const double bx = xd - (xd < prm.xmin ? prm.xmin : (xd > prm.xmax ? prm.xmax : xd));
+                const double gd = (double)gv;
+                qs[0] += gd * gd;
+                const double tz = TV3 ? dzd * dzd : 0.0;
+                qs[1] += sqrt(dxd * dxd + dyd * dyd + tz + prm.delta * prm.delta);
+                qs[2] += bx * bx;
+                qs[3] += dzd * dzd;
             }
         }
         gr[qq] = gv;
@@ -630,8 +635,9 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
         for (int e = 0; e < RPT; ++e) {
             const int lj = out_row<RPT>(e), li = tx;
             const int j = y0 + lj, i = x0 + li;
-            if (i >= g.nx || j >= g.ny) continue;
-            const double w = (double)WW[(lj + 1) * PW + (li + 1)];
+            // formed at every row of the tile (the reads stay inside the
+            // tiles); outputs outside the slice weigh 0 and add exact zeros
+            const double w = (i < g.nx && j < g.ny) ? (double)WW[(lj + 1) * PW + (li + 1)] : 0.0;
             const int c0 = lj * GW + li;
             const double g0 = (double)G[c0], p0 = (double)D[c0];
             const double dx1 = (i < g.nx - 1) ? g0 - (double)G[c0 + 1] : 0.0;
