@@ -896,12 +896,14 @@ __device__ __forceinline__ void dirs_finish(const Geom &g, const Params &prm, co
 #pragma unroll
     for (int e = 0; e < NRK; ++e) {
         const int j = y0 + out_row<NRK>(e), ii = x0 + tx;
-        if (ii >= g.nx || j >= g.ny) continue;
-        const double a = (double)h1[e], b = (double)h2[e];
+        // every row of the tile without a branch: outputs outside the slice
+        // add exact zeros
+        const bool ok = ii < g.nx && j < g.ny;
+        const double a = ok ? (double)h1[e] : 0.0, b = ok ? (double)h2[e] : 0.0;
         qs[0] += a * a;
         qs[1] += a * b;
         qs[2] += b * b;
-        if (zterm) {
+        if (zterm && ok) {
             // VZ d at slice kk: d_{kk+1} - d_kk with d zero outside S
             const size_t o = vidx(g, kk, j, ii);
             double z1v = 0.0, z2v = 0.0;
