@@ -463,10 +463,12 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
 #pragma unroll
             for (int qq = 0; qq < rg.E; ++qq) ht[qq] += ldbuf<T>(qp, bo[qq]);
         }
-    } else if (KZ <= 7 && sizeof(T) == 4) {
+    } else if (sizeof(T) == 4 && (KZ <= 7 || BLK)) {
         // taps past the volume read the nearest slice with weight 0: no
         // branch per tap, so every tap's loads can be in flight together
-        // (up to 7 taps in single precision: more would spill registers)
+        // (single precision; the 9-tap block instance takes 86 VGPRs against
+        // 56 with a branch per tap and still runs 8 % faster on 512x512x128;
+        // the 9-tap instance of the other modes would spill)
 #pragma unroll
         for (int c = -RZ; c <= RZ; ++c) {
             const int m = min(max(k + c, 0), g.nz - 1);
@@ -655,13 +657,14 @@ __device__ __forceinline__ void grad_body(const VB vb, Geom g, Params prm, DevSt
     }
 }
 
-// Waves per SIMD the register budget aims at: the single-precision block
-// instance's branch-free z taps need 104 VGPRs (four waves); the LDS holds
-// double precision to three (one with 3D TV) and single-precision 3D TV to
-// three.
+// Waves per SIMD the register budget aims at: at least four in single
+// precision (the block instances' branch-free z taps take 56-86 VGPRs with
+// 1-9 taps, five to eight waves; the other modes' instances about 100, and
+// a five-wave budget spills them); the LDS holds double precision to three
+// (one with 3D TV) and single-precision 3D TV to three.
 template <typename T, int KZ, bool TV3, bool BLK, bool STREAM>
 __global__ void __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (TV3 ? 1 : 3) : (TV3 ? 3 : (BLK ? 4 : 5)))))
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? (TV3 ? 1 : 3) : (TV3 ? 3 : 4))))
 k_grad(Geom g, Params prm, DevState<T> s, const T *__restrict__ q, const T *__restrict__ x,
        T *__restrict__ out, const Item *__restrict__ items, int mode, double *__restrict__ partials,
        int nshare)
