@@ -452,6 +452,11 @@ void group_items(bd3mg_problem p, const std::vector<int> &blocks, std::vector<It
             const Item &d = di[grp.d_off + i];
             units.push_back(Item{d.k, d.block, d.z0, d.n, i, std::min(per, dend[t] - i), 0, 0});
         }
+    // the two-slice units first: when the grid takes more than one round of
+    // residency, the workgroups that start late are those of the one-slice
+    // units, about half the work (each unit's partial sums go to its own
+    // items' slots, so the order changes no result)
+    std::stable_partition(units.begin() + grp.du_off, units.end(), [](const Item &u) { return u.hn > 1; });
     grp.round = round;
     grp.du_cnt = (int)units.size() - grp.du_off;
     grp.g_cnt = (int)gi.size() - grp.g_off;
